@@ -1,0 +1,498 @@
+/*
+ * colsten oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, sequential, deliberately slow CPU implementation of the coloured
+ * stencil sweeps of Hazelwood & Weinzierl, "Coloured and task-based stencil
+ * codes" (arXiv:1810.04033).  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it.  The GPU library never links,
+ * includes or calls anything here, and this file includes nothing of the GPU
+ * library.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC
+ * (no contraction of a*b+c into an FMA, so every operation below is one
+ *  IEEE-754 round-to-nearest-even operation in the order written).
+ *
+ * Data (paper Sec. 2, "The studied stencil codes"): a d-dimensional Cartesian
+ * mesh of fixed size stored as a plain d-dimensional array holding one scalar
+ * per cell.  Here every array carries a one-point halo on each side that holds
+ * Dirichlet boundary values, x is the contiguous axis, and the element strides
+ * (1, sy, sz) may include row/plane padding.  Interior indices run over
+ * i in [1,nx], j in [1,ny], k in [1,nz]; in 2D nz == 1 and no z offsets exist.
+ *
+ * Stencils (paper Fig. 1 and Sec. 2): the 2d+1-point finite-difference family
+ * and the 3^d-point d-linear finite-element family.  The operator is
+ * A = S / h^2 with S the dimensionless stencil.  Weights S_o by offset o:
+ *   FD:       S_0 = 2d, face neighbours -1 (Fig. 1, middle, for d = 2).
+ *   Q1, d=2:  S_0 = 8/3, all eight neighbours -1/3 (Fig. 1, right).
+ *   Q1, d=3:  S_0 = 8/3, faces 0, edges -1/6, corners -1/12.  The paper does
+ *             not print the 27-point entries; these are the assembled
+ *             trilinear element stiffness (see og_q1_kref below and the
+ *             Gauss-quadrature pin in the tests).
+ *
+ * Colouring (paper Sec. 3, "Colouring"): red-black for the 2d+1-point
+ * stencils, 2^d colours otherwise.  With parity offset p:
+ *   FD: colour = ((i-1)+(j-1)+(k-1)+p) mod 2
+ *   Q1: colour = sum_m ((x_m-1+p) mod 2) * 2^m     (x_0 = i, x_1 = j, x_2 = k)
+ * p = 0 puts the first interior point into colour 0 (the greedy construction
+ * in the prose of Sec. 3); p = 1 reproduces the index formula of Algorithm 1,
+ * whose pass c = 0 starts at x = 2 on row y = 1.
+ *
+ * Gauss-Seidel colour pass (Sec. 2: one value per cell from its own and its
+ * neighbours' values, written in situ; Sec. 3: one pass per colour): for every
+ * interior point q of colour c, z-y-x order with x innermost,
+ *     u_q <- (h^2 b_q - sum_{o != 0} S_o u_{q+o}) / S_0
+ * where the neighbour sum runs over offsets in lexicographic (oz, oy, ox)
+ * order and skips zero weights.  A sweep is the colour passes 0..c-1 in order.
+ *
+ * Separate-output update (Sec. 2: a separate output array as in a mat-vec):
+ * weighted Jacobi  u'_q = u_q + w (h^2 b_q - sum_o S_o u_{q+o}) / S_0  and the
+ * residual  r_q = b_q - (sum_o S_o u_{q+o}) / h^2, both reading only the old u.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* Stencil weights and colours                                          */
+/* ------------------------------------------------------------------ */
+
+/* S_o for offset (ox, oy, oz); stencil 0 = FD (2d+1 points), 1 = Q1 (3^d). */
+double og_weight(int stencil, int dim, int ox, int oy, int oz)
+{
+    int nnz = (ox != 0) + (oy != 0) + (oz != 0);
+    if (dim == 2 && oz != 0) return 0.0;
+    if (stencil == 0) {
+        if (nnz == 0) return 2.0 * dim;
+        if (nnz == 1) return -1.0;
+        return 0.0;
+    }
+    if (dim == 2) {
+        if (nnz == 0) return 8.0 / 3.0;
+        return -1.0 / 3.0;
+    }
+    if (nnz == 0) return 8.0 / 3.0;
+    if (nnz == 1) return 0.0;
+    if (nnz == 2) return -1.0 / 6.0;
+    return -1.0 / 12.0;
+}
+
+/* The same weights rounded once to binary32 (for the FP32 sweeps). */
+static float og_weight_f32(int stencil, int dim, int ox, int oy, int oz)
+{
+    int nnz = (ox != 0) + (oy != 0) + (oz != 0);
+    if (dim == 2 && oz != 0) return 0.0f;
+    if (stencil == 0) {
+        if (nnz == 0) return 2.0f * (float)dim;
+        if (nnz == 1) return -1.0f;
+        return 0.0f;
+    }
+    if (dim == 2) {
+        if (nnz == 0) return 8.0f / 3.0f;
+        return -1.0f / 3.0f;
+    }
+    if (nnz == 0) return 8.0f / 3.0f;
+    if (nnz == 1) return 0.0f;
+    if (nnz == 2) return -1.0f / 6.0f;
+    return -1.0f / 12.0f;
+}
+
+int og_num_colours(int stencil, int dim)
+{
+    return stencil == 0 ? 2 : (1 << dim);
+}
+
+/* Colour of interior point (i, j, k), 1-based; k == 1 in 2D. */
+int og_colour(int stencil, int dim, int parity, int64_t i, int64_t j, int64_t k)
+{
+    if (stencil == 0) {
+        int64_t s = (i - 1) + (j - 1) + (dim == 3 ? (k - 1) : 0) + parity;
+        return (int)(s & 1);
+    }
+    int c = (int)((i - 1 + parity) & 1);
+    c |= (int)((j - 1 + parity) & 1) << 1;
+    if (dim == 3) c |= (int)((k - 1 + parity) & 1) << 2;
+    return c;
+}
+
+/* Static colour validity: no nonzero off-centre weight may couple two points
+ * of the same colour (the race-freedom colouring provides a priori, Sec. 3).
+ * Checks every interior point against every offset on an n^d box; returns 1
+ * when valid.  colour_rule 0 = the stencil's own rule, 1 = force red-black. */
+int og_colouring_valid(int stencil, int dim, int colour_rule, int64_t n)
+{
+    int zr = dim == 3 ? 1 : 0;
+    for (int64_t k = 1; k <= (dim == 3 ? n : 1); ++k)
+        for (int64_t j = 1; j <= n; ++j)
+            for (int64_t i = 1; i <= n; ++i)
+                for (int oz = -zr; oz <= zr; ++oz)
+                    for (int oy = -1; oy <= 1; ++oy)
+                        for (int ox = -1; ox <= 1; ++ox) {
+                            if (ox == 0 && oy == 0 && oz == 0) continue;
+                            if (og_weight(stencil, dim, ox, oy, oz) == 0.0) continue;
+                            int64_t i2 = i + ox, j2 = j + oy, k2 = k + oz;
+                            if (i2 < 1 || i2 > n || j2 < 1 || j2 > n) continue;
+                            if (dim == 3 && (k2 < 1 || k2 > n)) continue;
+                            int rule = colour_rule == 1 ? 0 : stencil;
+                            int c1 = og_colour(rule, dim, 0, i, j, k);
+                            int c2 = og_colour(rule, dim, 0, i2, j2, k2);
+                            if (c1 == c2) return 0;
+                        }
+    return 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* One point update, FP64 and FP32                                      */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int dim, stencil, parity;
+    int64_t nx, ny, nz, sy, sz;
+    double h;
+} og_grid;
+
+static og_grid og_make(int dim, int stencil, int parity, int64_t nx, int64_t ny,
+                       int64_t nz, int64_t sy, int64_t sz, double h)
+{
+    og_grid g;
+    g.dim = dim; g.stencil = stencil; g.parity = parity;
+    g.nx = nx; g.ny = ny; g.nz = dim == 3 ? nz : 1;
+    g.sy = sy; g.sz = dim == 3 ? sz : 0;
+    g.h = h;
+    return g;
+}
+
+static int64_t og_index(const og_grid* g, int64_t i, int64_t j, int64_t k)
+{
+    return (g->dim == 3 ? k * g->sz : 0) + j * g->sy + i;
+}
+
+/* sum_{o != 0} S_o u_{q+o}, lexicographic (oz, oy, ox), zero weights skipped */
+static double og_offsum(const og_grid* g, const double* u, int64_t q)
+{
+    int zr = g->dim == 3 ? 1 : 0;
+    double acc = 0.0;
+    for (int oz = -zr; oz <= zr; ++oz)
+        for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+                if (ox == 0 && oy == 0 && oz == 0) continue;
+                double w = og_weight(g->stencil, g->dim, ox, oy, oz);
+                if (w == 0.0) continue;
+                acc += w * u[q + oz * g->sz + oy * g->sy + ox];
+            }
+    return acc;
+}
+
+/* sum over all o (centre included, at its lexicographic place) */
+static double og_fullsum(const og_grid* g, const double* u, int64_t q)
+{
+    int zr = g->dim == 3 ? 1 : 0;
+    double acc = 0.0;
+    for (int oz = -zr; oz <= zr; ++oz)
+        for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+                double w = og_weight(g->stencil, g->dim, ox, oy, oz);
+                if (w == 0.0) continue;
+                acc += w * u[q + oz * g->sz + oy * g->sy + ox];
+            }
+    return acc;
+}
+
+static float og_offsum_f32(const og_grid* g, const float* u, int64_t q)
+{
+    int zr = g->dim == 3 ? 1 : 0;
+    float acc = 0.0f;
+    for (int oz = -zr; oz <= zr; ++oz)
+        for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+                if (ox == 0 && oy == 0 && oz == 0) continue;
+                float w = og_weight_f32(g->stencil, g->dim, ox, oy, oz);
+                if (w == 0.0f) continue;
+                acc += w * u[q + oz * g->sz + oy * g->sy + ox];
+            }
+    return acc;
+}
+
+static float og_fullsum_f32(const og_grid* g, const float* u, int64_t q)
+{
+    int zr = g->dim == 3 ? 1 : 0;
+    float acc = 0.0f;
+    for (int oz = -zr; oz <= zr; ++oz)
+        for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+                float w = og_weight_f32(g->stencil, g->dim, ox, oy, oz);
+                if (w == 0.0f) continue;
+                acc += w * u[q + oz * g->sz + oy * g->sy + ox];
+            }
+    return acc;
+}
+
+/* Gauss-Seidel point update, in situ. */
+static void og_update(const og_grid* g, double* u, const double* b, int64_t q)
+{
+    double h2 = g->h * g->h;
+    double w0 = og_weight(g->stencil, g->dim, 0, 0, 0);
+    double rhs = h2 * b[q];
+    double acc = og_offsum(g, u, q);
+    u[q] = (rhs - acc) / w0;
+}
+
+static void og_update_f32(const og_grid* g, float* u, const float* b, int64_t q)
+{
+    float h2 = (float)(g->h * g->h);
+    float w0 = og_weight_f32(g->stencil, g->dim, 0, 0, 0);
+    float rhs = h2 * b[q];
+    float acc = og_offsum_f32(g, u, q);
+    u[q] = (rhs - acc) / w0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Gauss-Seidel colour passes and sweeps                                */
+/* ------------------------------------------------------------------ */
+
+/* One colour pass: every interior point of colour c, z, y, x order. */
+void og_colour_pass_f64(int dim, int stencil, int parity, int64_t nx, int64_t ny,
+                        int64_t nz, int64_t sy, int64_t sz, double h,
+                        double* u, const double* b, int colour)
+{
+    og_grid g = og_make(dim, stencil, parity, nx, ny, nz, sy, sz, h);
+    for (int64_t k = 1; k <= g.nz; ++k)
+        for (int64_t j = 1; j <= g.ny; ++j)
+            for (int64_t i = 1; i <= g.nx; ++i)
+                if (og_colour(stencil, dim, parity, i, j, k) == colour)
+                    og_update(&g, u, b, og_index(&g, i, j, k));
+}
+
+void og_colour_pass_f32(int dim, int stencil, int parity, int64_t nx, int64_t ny,
+                        int64_t nz, int64_t sy, int64_t sz, double h,
+                        float* u, const float* b, int colour)
+{
+    og_grid g = og_make(dim, stencil, parity, nx, ny, nz, sy, sz, h);
+    for (int64_t k = 1; k <= g.nz; ++k)
+        for (int64_t j = 1; j <= g.ny; ++j)
+            for (int64_t i = 1; i <= g.nx; ++i)
+                if (og_colour(stencil, dim, parity, i, j, k) == colour)
+                    og_update_f32(&g, u, b, og_index(&g, i, j, k));
+}
+
+/* The same colour pass, visiting the listed flat indices in the given order.
+ * Used to check that the order inside one colour does not matter (Sec. 3:
+ * the updates within a pass are embarrassingly parallel). */
+void og_update_points_f64(int dim, int stencil, int parity, int64_t nx, int64_t ny,
+                          int64_t nz, int64_t sy, int64_t sz, double h,
+                          double* u, const double* b, const int64_t* idx, int64_t count)
+{
+    og_grid g = og_make(dim, stencil, parity, nx, ny, nz, sy, sz, h);
+    for (int64_t t = 0; t < count; ++t) og_update(&g, u, b, idx[t]);
+}
+
+/* nsweeps sweeps, each the colours 0..c-1 in order (Sec. 3, one loop over c). */
+void og_gs_sweeps_f64(int dim, int stencil, int parity, int64_t nx, int64_t ny,
+                      int64_t nz, int64_t sy, int64_t sz, double h,
+                      double* u, const double* b, int nsweeps)
+{
+    int nc = og_num_colours(stencil, dim);
+    for (int s = 0; s < nsweeps; ++s)
+        for (int c = 0; c < nc; ++c)
+            og_colour_pass_f64(dim, stencil, parity, nx, ny, nz, sy, sz, h, u, b, c);
+}
+
+void og_gs_sweeps_f32(int dim, int stencil, int parity, int64_t nx, int64_t ny,
+                      int64_t nz, int64_t sy, int64_t sz, double h,
+                      float* u, const float* b, int nsweeps)
+{
+    int nc = og_num_colours(stencil, dim);
+    for (int s = 0; s < nsweeps; ++s)
+        for (int c = 0; c < nc; ++c)
+            og_colour_pass_f32(dim, stencil, parity, nx, ny, nz, sy, sz, h, u, b, c);
+}
+
+/* ------------------------------------------------------------------ */
+/* Weighted Jacobi (separate output array)                              */
+/* ------------------------------------------------------------------ */
+
+/* tmp must have u's shape.  Its halo is overwritten with u's halo first; after
+ * the call u holds the result (the last sweep's output is copied back when
+ * the sweep count is odd). */
+void og_jacobi_sweeps_f64(int dim, int stencil, int parity, int64_t nx, int64_t ny,
+                          int64_t nz, int64_t sy, int64_t sz, double h,
+                          double* u, const double* b, double* tmp, double omega,
+                          int nsweeps, int64_t total_len)
+{
+    og_grid g = og_make(dim, stencil, parity, nx, ny, nz, sy, sz, h);
+    double h2 = h * h;
+    double w0 = og_weight(stencil, dim, 0, 0, 0);
+    memcpy(tmp, u, (size_t)total_len * sizeof(double));
+    double* src = u;
+    double* dst = tmp;
+    for (int s = 0; s < nsweeps; ++s) {
+        for (int64_t k = 1; k <= g.nz; ++k)
+            for (int64_t j = 1; j <= g.ny; ++j)
+                for (int64_t i = 1; i <= g.nx; ++i) {
+                    int64_t q = og_index(&g, i, j, k);
+                    double su = og_fullsum(&g, src, q);
+                    dst[q] = src[q] + omega * ((h2 * b[q] - su) / w0);
+                }
+        double* t = src; src = dst; dst = t;
+    }
+    if (src != u) memcpy(u, src, (size_t)total_len * sizeof(double));
+}
+
+void og_jacobi_sweeps_f32(int dim, int stencil, int parity, int64_t nx, int64_t ny,
+                          int64_t nz, int64_t sy, int64_t sz, double h,
+                          float* u, const float* b, float* tmp, double omega,
+                          int nsweeps, int64_t total_len)
+{
+    og_grid g = og_make(dim, stencil, parity, nx, ny, nz, sy, sz, h);
+    float h2 = (float)(h * h);
+    float w0 = og_weight_f32(stencil, dim, 0, 0, 0);
+    float om = (float)omega;
+    memcpy(tmp, u, (size_t)total_len * sizeof(float));
+    float* src = u;
+    float* dst = tmp;
+    for (int s = 0; s < nsweeps; ++s) {
+        for (int64_t k = 1; k <= g.nz; ++k)
+            for (int64_t j = 1; j <= g.ny; ++j)
+                for (int64_t i = 1; i <= g.nx; ++i) {
+                    int64_t q = og_index(&g, i, j, k);
+                    float su = og_fullsum_f32(&g, src, q);
+                    dst[q] = src[q] + om * ((h2 * b[q] - su) / w0);
+                }
+        float* t = src; src = dst; dst = t;
+    }
+    if (src != u) memcpy(u, src, (size_t)total_len * sizeof(float));
+}
+
+/* ------------------------------------------------------------------ */
+/* Residual and norms                                                   */
+/* ------------------------------------------------------------------ */
+
+/* Neumaier's compensated summation: adds x into (*s, *c). */
+static void og_neumaier(double* s, double* c, double x)
+{
+    double t = *s + x;
+    if (fabs(*s) >= fabs(x)) *c += (*s - t) + x;
+    else                     *c += (x - t) + *s;
+    *s = t;
+}
+
+/* r = b - S u / h^2 over the interior (r may be NULL).  norms[0] = ||r||_2,
+ * norms[1] = max |r|, norms[2] = ||b||_2, unweighted, interior points only. */
+void og_residual_f64(int dim, int stencil, int parity, int64_t nx, int64_t ny,
+                     int64_t nz, int64_t sy, int64_t sz, double h,
+                     const double* u, const double* b, double* r, double* norms)
+{
+    og_grid g = og_make(dim, stencil, parity, nx, ny, nz, sy, sz, h);
+    double h2 = h * h;
+    double s_r = 0.0, c_r = 0.0, s_b = 0.0, c_b = 0.0, mx = 0.0;
+    for (int64_t k = 1; k <= g.nz; ++k)
+        for (int64_t j = 1; j <= g.ny; ++j)
+            for (int64_t i = 1; i <= g.nx; ++i) {
+                int64_t q = og_index(&g, i, j, k);
+                double su = og_fullsum(&g, u, q);
+                double rq = b[q] - su / h2;
+                if (r) r[q] = rq;
+                og_neumaier(&s_r, &c_r, rq * rq);
+                og_neumaier(&s_b, &c_b, b[q] * b[q]);
+                if (fabs(rq) > mx) mx = fabs(rq);
+            }
+    norms[0] = sqrt(s_r + c_r);
+    norms[1] = mx;
+    norms[2] = sqrt(s_b + c_b);
+}
+
+/* Residual of an FP32 grid, evaluated in FP64 from the stored binary32 values. */
+void og_residual_f32in(int dim, int stencil, int parity, int64_t nx, int64_t ny,
+                       int64_t nz, int64_t sy, int64_t sz, double h,
+                       const float* u, const float* b, double* norms)
+{
+    og_grid g = og_make(dim, stencil, parity, nx, ny, nz, sy, sz, h);
+    double h2 = h * h;
+    double s_r = 0.0, c_r = 0.0, s_b = 0.0, c_b = 0.0, mx = 0.0;
+    int zr = dim == 3 ? 1 : 0;
+    for (int64_t k = 1; k <= g.nz; ++k)
+        for (int64_t j = 1; j <= g.ny; ++j)
+            for (int64_t i = 1; i <= g.nx; ++i) {
+                int64_t q = og_index(&g, i, j, k);
+                double su = 0.0;
+                for (int oz = -zr; oz <= zr; ++oz)
+                    for (int oy = -1; oy <= 1; ++oy)
+                        for (int ox = -1; ox <= 1; ++ox) {
+                            double w = og_weight(stencil, dim, ox, oy, oz);
+                            if (w == 0.0) continue;
+                            su += w * (double)u[q + oz * g.sz + oy * g.sy + ox];
+                        }
+                double bq = (double)b[q];
+                double rq = bq - su / h2;
+                og_neumaier(&s_r, &c_r, rq * rq);
+                og_neumaier(&s_b, &c_b, bq * bq);
+                if (fabs(rq) > mx) mx = fabs(rq);
+            }
+    norms[0] = sqrt(s_r + c_r);
+    norms[1] = mx;
+    norms[2] = sqrt(s_b + c_b);
+}
+
+/* ------------------------------------------------------------------ */
+/* Second formulation of the Q1 operator: element by element            */
+/* ------------------------------------------------------------------ */
+
+/* Reference-element stiffness of the d-linear element on the unit cell,
+ * entry for two vertices that differ in `ndiff` coordinates:
+ *   d = 2: 2/3, -1/6, -1/3          (ndiff = 0, 1, 2)
+ *   d = 3: 1/3, 0, -1/12, -1/12     (ndiff = 0, 1, 2, 3)                    */
+double og_q1_kref(int dim, int ndiff)
+{
+    if (dim == 2) {
+        if (ndiff == 0) return 2.0 / 3.0;
+        if (ndiff == 1) return -1.0 / 6.0;
+        return -1.0 / 3.0;
+    }
+    if (ndiff == 0) return 1.0 / 3.0;
+    if (ndiff == 1) return 0.0;
+    return -1.0 / 12.0;
+}
+
+/* out_q = (S u)_q for every interior vertex q, accumulated cell by cell:
+ * each cell (one per index box [i,i+1]x[j,j+1](x[k,k+1]) touching the
+ * interior) adds K_ref u_e into its 2^d vertices.  out must be zero on entry
+ * (halo entries of out receive partial sums and are not meaningful). */
+void og_q1_apply_cellwise(int dim, int64_t nx, int64_t ny, int64_t nz,
+                          int64_t sy, int64_t sz, const double* u, double* out)
+{
+    int nv = 1 << dim;
+    int64_t kz = dim == 3 ? nz : 0;
+    for (int64_t k = 0; k <= kz; ++k)
+        for (int64_t j = 0; j <= ny; ++j)
+            for (int64_t i = 0; i <= nx; ++i) {
+                for (int a = 0; a < nv; ++a) {
+                    int64_t qa = (i + (a & 1)) + (j + ((a >> 1) & 1)) * sy
+                               + (dim == 3 ? (k + ((a >> 2) & 1)) * sz : 0);
+                    double acc = 0.0;
+                    for (int bb = 0; bb < nv; ++bb) {
+                        int64_t qb = (i + (bb & 1)) + (j + ((bb >> 1) & 1)) * sy
+                                   + (dim == 3 ? (k + ((bb >> 2) & 1)) * sz : 0);
+                        int x = a ^ bb;
+                        int ndiff = (x & 1) + ((x >> 1) & 1) + ((x >> 2) & 1);
+                        double kab = og_q1_kref(dim, ndiff);
+                        if (kab == 0.0) continue;
+                        acc += kab * u[qb];
+                    }
+                    out[qa] += acc;
+                }
+            }
+}
+
+/* (S u)_q by the stencil form, for comparison with the cell-wise form. */
+void og_apply_stencil(int dim, int stencil, int64_t nx, int64_t ny, int64_t nz,
+                      int64_t sy, int64_t sz, const double* u, double* out)
+{
+    og_grid g = og_make(dim, stencil, 0, nx, ny, nz, sy, sz, 1.0);
+    for (int64_t k = 1; k <= g.nz; ++k)
+        for (int64_t j = 1; j <= g.ny; ++j)
+            for (int64_t i = 1; i <= g.nx; ++i) {
+                int64_t q = og_index(&g, i, j, k);
+                out[q] = og_fullsum(&g, u, q);
+            }
+}

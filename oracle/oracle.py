@@ -1,0 +1,248 @@
+"""colsten oracle -- TEST INFRASTRUCTURE ONLY.
+
+Python face of the sequential C oracle in ``colsten_oracle.c`` (built with gcc,
+``-O2 -ffp-contract=off``).  Only the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark import this module; the GPU library and its
+binding never do, and this module imports nothing from them.
+
+Every array argument is a halo'd numpy array in C order with x contiguous:
+shape ``(ny+2, px)`` in 2D and ``(nz+2, ny+2, px)`` in 3D, where the row pitch
+``px >= nx+2`` may include padding (a view ``a[..., :nx+2]`` of a wider array
+is accepted; the strides are read from the array).  The halo holds the
+Dirichlet boundary values.  Function-by-function citations of the paper
+(Hazelwood & Weinzierl, arXiv:1810.04033) are in the C source.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "colsten_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+FD, Q1 = 0, 1
+
+
+def build(force=True):
+    """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+           "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    alt = os.environ.get("COLSTEN_ORACLE_LIB")  # a deliberately mutated build (pin tests)
+    if alt:
+        lib = ctypes.CDLL(alt)
+    else:
+        build(force=False)
+        lib = ctypes.CDLL(_LIB)
+    i32, i64, f64, vp = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+    geo = [i32, i32, i32, i64, i64, i64, i64, i64, f64]
+    lib.og_weight.restype = f64
+    lib.og_weight.argtypes = [i32, i32, i32, i32, i32]
+    lib.og_num_colours.restype = i32
+    lib.og_num_colours.argtypes = [i32, i32]
+    lib.og_colour.restype = i32
+    lib.og_colour.argtypes = [i32, i32, i32, i64, i64, i64]
+    lib.og_colouring_valid.restype = i32
+    lib.og_colouring_valid.argtypes = [i32, i32, i32, i64]
+    for name in ("og_colour_pass_f64", "og_colour_pass_f32"):
+        getattr(lib, name).restype = None
+        getattr(lib, name).argtypes = geo + [vp, vp, i32]
+    lib.og_update_points_f64.restype = None
+    lib.og_update_points_f64.argtypes = geo + [vp, vp, vp, i64]
+    for name in ("og_gs_sweeps_f64", "og_gs_sweeps_f32"):
+        getattr(lib, name).restype = None
+        getattr(lib, name).argtypes = geo + [vp, vp, i32]
+    for name in ("og_jacobi_sweeps_f64", "og_jacobi_sweeps_f32"):
+        getattr(lib, name).restype = None
+        getattr(lib, name).argtypes = geo + [vp, vp, vp, f64, i32, i64]
+    lib.og_residual_f64.restype = None
+    lib.og_residual_f64.argtypes = geo + [vp, vp, vp, vp]
+    lib.og_residual_f32in.restype = None
+    lib.og_residual_f32in.argtypes = geo + [vp, vp, vp]
+    lib.og_q1_kref.restype = f64
+    lib.og_q1_kref.argtypes = [i32, i32]
+    lib.og_q1_apply_cellwise.restype = None
+    lib.og_q1_apply_cellwise.argtypes = [i32, i64, i64, i64, i64, i64, vp, vp]
+    lib.og_apply_stencil.restype = None
+    lib.og_apply_stencil.argtypes = [i32, i32, i64, i64, i64, i64, i64, vp, vp]
+    _lib = lib
+    return lib
+
+
+def _geometry(a, dim):
+    """(nx, ny, nz, sy, sz) of a halo'd array (element strides)."""
+    if a.ndim != dim:
+        raise ValueError("array rank %d does not match dim %d" % (a.ndim, dim))
+    it = a.itemsize
+    if a.strides[-1] != it:
+        raise ValueError("x must be the contiguous axis")
+    nx = a.shape[-1] - 2
+    ny = a.shape[-2] - 2
+    sy = a.strides[-2] // it
+    if dim == 3:
+        nz = a.shape[-3] - 2
+        sz = a.strides[-3] // it
+    else:
+        nz, sz = 1, 0
+    return nx, ny, nz, sy, sz
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _span(a):
+    """Number of elements between the first and one past the last element."""
+    it = a.itemsize
+    return (sum((s - 1) * st for s, st in zip(a.shape, a.strides)) // it) + 1
+
+
+def _args(u, dim, stencil, parity, h):
+    nx, ny, nz, sy, sz = _geometry(u, dim)
+    return [dim, stencil, parity, nx, ny, nz, sy, sz, float(h)]
+
+
+def _check_same(u, *others):
+    for o in others:
+        if o is None:
+            continue
+        if o.shape != u.shape or o.strides != u.strides or o.dtype != u.dtype:
+            raise ValueError("arrays must share shape, strides and dtype")
+
+
+def weight(stencil, dim, ox, oy, oz=0):
+    return _load().og_weight(stencil, dim, ox, oy, oz)
+
+
+def num_colours(stencil, dim):
+    return _load().og_num_colours(stencil, dim)
+
+
+def colour(stencil, dim, parity, i, j, k=1):
+    return _load().og_colour(stencil, dim, parity, i, j, k)
+
+
+def colouring_valid(stencil, dim, n, force_red_black=False):
+    return bool(_load().og_colouring_valid(stencil, dim, 1 if force_red_black else 0, n))
+
+
+def colour_pass(u, b, colour_id, *, dim, stencil, h, parity=0):
+    """One Gauss-Seidel colour pass, in situ on u (float64 or float32)."""
+    _check_same(u, b)
+    lib = _load()
+    fn = lib.og_colour_pass_f64 if u.dtype == np.float64 else lib.og_colour_pass_f32
+    fn(*_args(u, dim, stencil, parity, h), _ptr(u), _ptr(b), int(colour_id))
+
+
+def update_points(u, b, flat_idx, *, dim, stencil, h, parity=0):
+    """Point updates at the given flat element offsets, in the given order."""
+    _check_same(u, b)
+    idx = np.ascontiguousarray(flat_idx, dtype=np.int64)
+    _load().og_update_points_f64(*_args(u, dim, stencil, parity, h), _ptr(u), _ptr(b),
+                                 _ptr(idx), int(idx.size))
+
+
+def gs_sweeps(u, b, nsweeps, *, dim, stencil, h, parity=0):
+    """nsweeps Gauss-Seidel sweeps (all colours in canonical order), in situ."""
+    _check_same(u, b)
+    lib = _load()
+    fn = lib.og_gs_sweeps_f64 if u.dtype == np.float64 else lib.og_gs_sweeps_f32
+    fn(*_args(u, dim, stencil, parity, h), _ptr(u), _ptr(b), int(nsweeps))
+
+
+def _like(u):
+    """A zero array with u's shape, dtype and element strides (own buffer)."""
+    flat = np.zeros(_span(u), dtype=u.dtype)
+    return np.lib.stride_tricks.as_strided(flat, shape=u.shape, strides=u.strides), flat
+
+
+def jacobi_sweeps(u, b, nsweeps, omega, *, dim, stencil, h):
+    """nsweeps weighted Jacobi sweeps; the result is left in u."""
+    _check_same(u, b)
+    _, flat = _like(u)
+    lib = _load()
+    fn = lib.og_jacobi_sweeps_f64 if u.dtype == np.float64 else lib.og_jacobi_sweeps_f32
+    fn(*_args(u, dim, stencil, 0, h), _ptr(u), _ptr(b), _ptr(flat),
+       float(omega), int(nsweeps), int(flat.size))
+
+
+def residual(u, b, *, dim, stencil, h, want_r=False):
+    """r = b - S u / h^2 and (||r||_2, max|r|, ||b||_2) over the interior."""
+    _check_same(u, b)
+    norms = np.zeros(3, dtype=np.float64)
+    lib = _load()
+    if u.dtype == np.float32:
+        if want_r:
+            raise ValueError("r is only returned for float64 grids")
+        lib.og_residual_f32in(*_args(u, dim, stencil, 0, h), _ptr(u), _ptr(b), _ptr(norms))
+        return norms
+    r = _like(u)[0] if want_r else None
+    lib.og_residual_f64(*_args(u, dim, stencil, 0, h), _ptr(u), _ptr(b),
+                        _ptr(r) if r is not None else None, _ptr(norms))
+    return (norms, r) if want_r else norms
+
+
+def apply_stencil(u, *, dim, stencil):
+    """(S u) at interior points (dimensionless stencil, h = 1); halo entries 0."""
+    out = _like(u)[0]
+    nx, ny, nz, sy, sz = _geometry(u, dim)
+    _load().og_apply_stencil(dim, stencil, nx, ny, nz, sy, sz, _ptr(u), _ptr(out))
+    return out
+
+
+def q1_apply_cellwise(u, *, dim):
+    """(S u) at interior points by element-wise accumulation; halo entries invalid."""
+    out = _like(u)[0]
+    nx, ny, nz, sy, sz = _geometry(u, dim)
+    _load().og_q1_apply_cellwise(dim, nx, ny, nz, sy, sz, _ptr(u), _ptr(out))
+    return out
+
+
+def q1_kref(dim, ndiff):
+    return _load().og_q1_kref(dim, ndiff)
+
+
+def interior(a):
+    """The interior view of a halo'd array."""
+    if a.ndim == 2:
+        return a[1:-1, 1:a.shape[1] - 1]
+    return a[1:-1, 1:-1, 1:a.shape[2] - 1]
+
+
+def ir_solve(b, tol, *, dim, stencil, h, inner_sweeps, max_outer, check_every=1):
+    """FP32 Gauss-Seidel sweeps inside FP64 iterative refinement.
+
+    Each outer step: r = b - A x in FP64; s = 2**ceil(log2 max|r|);
+    r32 = fl32(r / s); inner_sweeps FP32 sweeps on A e = r32 from e = 0;
+    x <- x + s * e in FP64.  Stops when ||r||_2 / ||b||_2 <= tol.
+    Returns (x, history of relative residuals, outer steps taken).
+    """
+    x = np.zeros_like(b)
+    hist = []
+    for it in range(max_outer + 1):
+        norms, r = residual(x, b, dim=dim, stencil=stencil, h=h, want_r=True)
+        rel = norms[0] / norms[2] if norms[2] > 0 else norms[0]
+        hist.append(rel)
+        if rel <= tol or it == max_outer:
+            return x, hist, it
+        s = 2.0 ** np.ceil(np.log2(norms[1])) if norms[1] > 0 else 1.0
+        r32 = (r / s).astype(np.float32)
+        e = np.zeros_like(r32)
+        gs_sweeps(e, r32, inner_sweeps, dim=dim, stencil=stencil, h=h)
+        inner = interior(x)
+        inner += s * interior(e).astype(np.float64)
+    return x, hist, max_outer

@@ -1,0 +1,71 @@
+"""The pins must catch plausible mistakes in the oracle.
+
+Each case copies the oracle's C source, plants one mistake (a dropped term, a
+wrong sign, a transposed index, a wrong colour, a misplaced weight), compiles
+the copy on the CPU and runs the pin suite against it.  The suite has to fail.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "colsten_oracle.c")
+
+MUTANTS = {
+    "dropped_corner_weight": (
+        "    if (nnz == 2) return -1.0 / 6.0;\n    return -1.0 / 12.0;\n}",
+        "    if (nnz == 2) return -1.0 / 6.0;\n    return 0.0;\n}"),
+    "nonzero_q1_face": (
+        "    if (nnz == 0) return 8.0 / 3.0;\n    if (nnz == 1) return 0.0;",
+        "    if (nnz == 0) return 8.0 / 3.0;\n    if (nnz == 1) return -1.0 / 12.0;"),
+    "sign_of_neighbour_sum": (
+        "acc += w * u[q + oz * g->sz + oy * g->sy + ox];",
+        "acc -= w * u[q + oz * g->sz + oy * g->sy + ox];"),
+    "transposed_strides": (
+        "return (g->dim == 3 ? k * g->sz : 0) + j * g->sy + i;",
+        "return (g->dim == 3 ? k * g->sy : 0) + j * g->sz + i;"),
+    "swapped_update_operands": (
+        "    u[q] = (rhs - acc) / w0;\n}\n\nstatic void og_update_f32",
+        "    u[q] = (acc - rhs) / w0;\n}\n\nstatic void og_update_f32"),
+    "dropped_plus_x_neighbour": (
+        "            for (int ox = -1; ox <= 1; ++ox) {\n                if (ox == 0 && oy == 0 && oz == 0) continue;\n                double w",
+        "            for (int ox = -1; ox <= 0; ++ox) {\n                if (ox == 0 && oy == 0 && oz == 0) continue;\n                double w"),
+    "wrong_red_black_parity": (
+        "int64_t s = (i - 1) + (j - 1) +",
+        "int64_t s = (i - 1) + j +"),
+    "q1_colour_axis_mixup": (
+        "c |= (int)((j - 1 + parity) & 1) << 1;",
+        "c |= (int)((i - 1 + parity) & 1) << 1;"),
+    "jacobi_weight_dropped": (
+        "dst[q] = src[q] + omega * ((h2 * b[q] - su) / w0);",
+        "dst[q] = src[q] + ((h2 * b[q] - su) / w0);"),
+    "residual_scaled_wrongly": (
+        "double rq = b[q] - su / h2;\n                if (r) r[q] = rq;",
+        "double rq = b[q] - su * h2;\n                if (r) r[q] = rq;"),
+    "neumaier_compensation_sign": (
+        "if (fabs(*s) >= fabs(x)) *c += (*s - t) + x;",
+        "if (fabs(*s) >= fabs(x)) *c += (t - *s) + x;"),
+    "gs_skips_last_colour": (
+        "        for (int c = 0; c < nc; ++c)\n            og_colour_pass_f64(",
+        "        for (int c = 0; c < nc - 1; ++c)\n            og_colour_pass_f64("),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_reject_mutant(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) >= 1, "mutation site not found: %s" % name
+    mutated = src.replace(old, new, 1)
+    csrc = tmp_path / "mutant.c"
+    csrc.write_text(mutated)
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+                    "-o", str(lib), str(csrc), "-lm"], check=True)
+    env = dict(os.environ, COLSTEN_ORACLE_LIB=str(lib))
+    proc = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                           os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert proc.returncode != 0, "the pins accepted mutant %s:\n%s" % (name, proc.stdout[-2000:])
