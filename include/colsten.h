@@ -1,0 +1,131 @@
+/*
+ * colsten.h -- C ABI of the coloured stencil-sweep library for MI355X (gfx950).
+ *
+ * The operations follow Hazelwood & Weinzierl, "Coloured and task-based
+ * stencil codes" (arXiv:1810.04033):
+ *   - the mesh is a fixed-size d-dimensional Cartesian grid stored as a plain
+ *     d-dimensional array with one scalar per cell (Sec. 2);
+ *   - a Gauss-Seidel update computes one value per cell from its own and its
+ *     neighbours' values through a fixed stencil and writes it in situ (Sec. 2);
+ *   - the stencils are the 2d+1-point finite-difference and 3^d-point d-linear
+ *     finite-element families (Fig. 1, Sec. 2);
+ *   - colouring (red-black for 2d+1 points, 2^d colours otherwise) orders the
+ *     sweep into c passes whose updates are independent (Sec. 3);
+ *   - a separate output array turns the same sweep into a mat-vec (Sec. 2),
+ *     which is the weighted Jacobi sweep and the residual here.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Arrays live in device memory owned by the caller; the library never frees
+ * them.  Each array carries a one-point halo on every side holding Dirichlet
+ * boundary values; x is contiguous.  Element (i, j, k), 0 <= i <= n[0]+1 etc.,
+ * sits at offset i + j*stride[1] + k*stride[2] (k = 0 and no z halo in 2D).
+ * Interior points are 1 <= i <= n[0], 1 <= j <= n[1], 1 <= k <= n[2].
+ *
+ * The operator is A = S / h^2 with the dimensionless stencil S:
+ *   CS_FD, d = 2:  5-point,  S_0 = 4,   faces -1
+ *   CS_FD, d = 3:  7-point,  S_0 = 6,   faces -1
+ *   CS_Q1, d = 2:  9-point,  S_0 = 8/3, all neighbours -1/3
+ *   CS_Q1, d = 3:  27-point, S_0 = 8/3, faces 0, edges -1/6, corners -1/12
+ *                  (assembled trilinear element stiffness)
+ *
+ * Colours, with parity p in {0, 1} (p = 1 reproduces Algorithm 1's order):
+ *   CS_FD: colour = ((i-1) + (j-1) + (k-1) + p) mod 2       (2 colours)
+ *   CS_Q1: colour = sum_m ((x_m - 1 + p) mod 2) * 2^m        (2^d colours)
+ * A sweep applies the colours 0, 1, ..., c-1 in this order.
+ *
+ * Streams: every `stream` argument is a hipStream_t passed as void* (NULL is
+ * the default stream).  Work is enqueued asynchronously; nothing here
+ * synchronises the host except cs_grid_create/cs_batch_create, which may
+ * allocate.  Device faults surface at the caller's next synchronisation.
+ *
+ * Errors: every call returns a cs_status; CS_OK is 0.  On failure nothing has
+ * been enqueued (argument errors are detected before any launch) unless the
+ * status is CS_EHIP, and cs_last_error() describes the failure.
+ */
+#ifndef COLSTEN_H
+#define COLSTEN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CS_OK = 0,
+    CS_EINVAL = 1,        /* invalid argument (null, size, stride, range) */
+    CS_ENOMEM = 2,        /* device allocation failed */
+    CS_EHIP = 3,          /* a HIP runtime call or kernel launch failed */
+    CS_EUNSUPPORTED = 4   /* valid but not supported combination */
+} cs_status;
+
+typedef enum { CS_F64 = 0, CS_F32 = 1 } cs_dtype;
+typedef enum { CS_FD = 0, CS_Q1 = 1 } cs_stencil;
+
+/* Geometry and method of one grid.  All fields are read at create time. */
+typedef struct cs_grid_desc {
+    int32_t dim;        /* 2 or 3 */
+    int32_t stencil;    /* cs_stencil */
+    int32_t dtype;      /* cs_dtype: element type of u and b */
+    int32_t parity;     /* colour parity p, 0 or 1 */
+    int64_t n[3];       /* interior points along x, y, z; n[2] must be 1 in 2D */
+    int64_t stride[3];  /* element strides; stride[0] == 1,
+                           stride[1] >= n[0] + 2,
+                           stride[2] >= stride[1] * (n[1] + 2) in 3D (ignored in 2D) */
+    double h;           /* mesh width, > 0; A = S / h^2 */
+} cs_grid_desc;
+
+typedef struct cs_grid_s* cs_grid;
+
+/* Bind a grid to the caller's arrays u (unknowns, updated in place) and b
+ * (right-hand side).  Both must be device allocations on the current device
+ * covering the whole halo'd extent; the check uses the allocation's address
+ * range.  Allocates a small reduction scratch (freed by cs_grid_destroy).
+ * Errors: CS_EINVAL on a bad descriptor or pointer, CS_ENOMEM, CS_EHIP. */
+cs_status cs_grid_create(const cs_grid_desc* desc, void* u, const void* b, cs_grid* out);
+
+/* Release the handle and its scratch (not u or b).  NULL is a no-op.  The
+ * caller must ensure no work using the grid is still pending. */
+cs_status cs_grid_destroy(cs_grid g);
+
+/* Number of colours c: 2 for CS_FD, 2^d for CS_Q1 (Sec. 3). */
+cs_status cs_num_colours(cs_grid g, int32_t* out);
+
+/* One Gauss-Seidel colour pass (Sec. 3): every interior point q of the given
+ * colour is set to (h^2 b_q - sum_{o != 0} S_o u_{q+o}) / S_0, in place.
+ * Points of one colour do not couple, so the pass has no ordering freedom.
+ * Errors: CS_EINVAL if colour is outside [0, c). */
+cs_status cs_colour_pass(cs_grid g, int32_t colour, void* stream);
+
+/* nsweeps full Gauss-Seidel sweeps, each the colours 0..c-1 in order.
+ * u_tmp: NULL, or a caller-owned device array with exactly u's layout.  With
+ * u_tmp the library runs each sweep as one fused pass over memory that reads
+ * u (or u_tmp) and writes the other array (same result as the colour passes,
+ * up to rounding order); the halo of u_tmp is overwritten with u's halo, and
+ * the result ends in u.  Without u_tmp, each sweep is c in-place colour
+ * passes.  nsweeps == 0 is a no-op.  Errors: CS_EINVAL (nsweeps < 0). */
+cs_status cs_gs_sweeps(cs_grid g, int32_t nsweeps, void* u_tmp, void* stream);
+
+/* nsweeps weighted Jacobi sweeps (the separate-output-array form of Sec. 2):
+ *   u'_q = u_q + omega * (h^2 b_q - sum_o S_o u_{q+o}) / S_0
+ * reading only the previous iterate.  u_tmp (required) must have u's layout;
+ * its halo is overwritten with u's halo.  The result ends in u.
+ * Errors: CS_EINVAL (u_tmp NULL, nsweeps < 0, omega not finite). */
+cs_status cs_jacobi_sweeps(cs_grid g, double omega, int32_t nsweeps, void* u_tmp, void* stream);
+
+/* Residual r_q = b_q - (S u)_q / h^2 over the interior.  r: NULL or a device
+ * array with u's layout and dtype (halo untouched).  norms: device pointer to
+ * 3 doubles receiving ||r||_2, max |r| and ||b||_2 (unweighted sums over
+ * interior points).  The reduction order is fixed, so repeated calls on the
+ * same data give identical bits.  FP32 grids are evaluated in FP64. */
+cs_status cs_residual(cs_grid g, void* r, double* norms, void* stream);
+
+/* Description of the last failure on the calling thread ("" if none). */
+const char* cs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COLSTEN_H */

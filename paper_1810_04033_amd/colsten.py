@@ -1,0 +1,243 @@
+"""Python binding of libcolsten (ctypes; argument marshalling only).
+
+The functions carry the C names of include/colsten.h and raise ColstenError on
+a non-zero status.  Every step of the computation runs in the HIP kernels of
+libcolsten.so; there is no CPU fallback: if the library is missing, loading it
+raises.  torch is imported first so that the library binds to the HIP runtime
+torch already loaded (one runtime per process: torch's tensors and streams
+are valid in the library).
+
+``Grid`` wraps a handle around caller-owned torch tensors; ``empty_grid``
+allocates halo'd arrays whose interior rows start on a 128-byte boundary.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcolsten.so")
+
+CS_OK, CS_EINVAL, CS_ENOMEM, CS_EHIP, CS_EUNSUPPORTED = 0, 1, 2, 3, 4
+CS_F64, CS_F32 = 0, 1
+CS_FD, CS_Q1 = 0, 1
+
+_STATUS = {0: "CS_OK", 1: "CS_EINVAL", 2: "CS_ENOMEM", 3: "CS_EHIP", 4: "CS_EUNSUPPORTED"}
+
+
+class ColstenError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), msg))
+        self.status = status
+
+
+class cs_grid_desc(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("stencil", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("parity", ctypes.c_int32),
+        ("n", ctypes.c_int64 * 3),
+        ("stride", ctypes.c_int64 * 3),
+        ("h", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "cs_grid_create": (ctypes.c_int, [ctypes.POINTER(cs_grid_desc), ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_void_p)]),
+    "cs_grid_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "cs_num_colours": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "cs_colour_pass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "cs_gs_sweeps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "cs_jacobi_sweeps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32,
+                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "cs_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cs_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libcolsten.so is not built (%s); run `python -m "
+                          "paper_1810_04033_amd.build`" % LIB_PATH)
+    handle = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(handle, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = handle
+    return handle
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+def _check(status):
+    if status != CS_OK:
+        raise ColstenError(status, lib().cs_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def cs_last_error():
+    return lib().cs_last_error().decode()
+
+
+def cs_grid_create(desc, u_ptr, b_ptr):
+    out = ctypes.c_void_p()
+    _check(lib().cs_grid_create(ctypes.byref(desc), ctypes.c_void_p(u_ptr), ctypes.c_void_p(b_ptr),
+                                ctypes.byref(out)))
+    return out.value
+
+
+def cs_grid_destroy(handle):
+    _check(lib().cs_grid_destroy(ctypes.c_void_p(handle)))
+
+
+def cs_num_colours(handle):
+    out = ctypes.c_int32()
+    _check(lib().cs_num_colours(ctypes.c_void_p(handle), ctypes.byref(out)))
+    return out.value
+
+
+def cs_colour_pass(handle, colour, stream=None):
+    _check(lib().cs_colour_pass(ctypes.c_void_p(handle), int(colour), _stream(stream)))
+
+
+def cs_gs_sweeps(handle, nsweeps, u_tmp_ptr=0, stream=None):
+    _check(lib().cs_gs_sweeps(ctypes.c_void_p(handle), int(nsweeps), ctypes.c_void_p(u_tmp_ptr),
+                              _stream(stream)))
+
+
+def cs_jacobi_sweeps(handle, omega, nsweeps, u_tmp_ptr, stream=None):
+    _check(lib().cs_jacobi_sweeps(ctypes.c_void_p(handle), float(omega), int(nsweeps),
+                                  ctypes.c_void_p(u_tmp_ptr), _stream(stream)))
+
+
+def cs_residual(handle, r_ptr, norms_ptr, stream=None):
+    _check(lib().cs_residual(ctypes.c_void_p(handle), ctypes.c_void_p(r_ptr), ctypes.c_void_p(norms_ptr),
+                             _stream(stream)))
+
+
+# --------------------------------------------------------------------------
+# Tensor helpers
+# --------------------------------------------------------------------------
+
+_DT = {torch.float64: CS_F64, torch.float32: CS_F32}
+
+
+def empty_grid(n, dtype=torch.float64, device="cuda", align_bytes=128):
+    """A zeroed halo'd tensor for interior size n = (nx, ny[, nz]).
+
+    The returned view has shape (nz+2, ny+2, nx+2) (or (ny+2, nx+2)); its row
+    pitch is a multiple of align_bytes and element x = 1 of every row starts
+    on an align_bytes boundary (the base allocation is 256-byte aligned)."""
+    n = tuple(int(v) for v in n)
+    esz = torch.empty((), dtype=dtype).element_size()
+    a = max(1, align_bytes // esz)
+    nx = n[0]
+    px = ((nx + 2 + a - 1) // a) * a
+    shape = tuple(v + 2 for v in reversed(n[1:])) + (nx + 2,)
+    rows = 1
+    for v in shape[:-1]:
+        rows *= v
+    off = a - 1
+    flat = torch.zeros(off + rows * px, dtype=dtype, device=device)
+    strides = []
+    acc = px
+    for v in reversed(shape[:-1]):
+        strides.insert(0, acc)
+        acc *= v
+    view = flat.as_strided(shape, tuple(strides) + (1,), storage_offset=off)
+    return view
+
+
+def grid_like(t):
+    """A zeroed tensor with t's shape, strides and dtype (own storage)."""
+    span = 1 + sum((s - 1) * st for s, st in zip(t.shape, t.stride()))
+    off = t.storage_offset()
+    flat = torch.zeros(off + span, dtype=t.dtype, device=t.device)
+    return flat.as_strided(t.shape, t.stride(), storage_offset=off)
+
+
+def describe(u, *, dim, stencil, h, parity=0):
+    """cs_grid_desc of a halo'd tensor (shape and strides read from u)."""
+    if u.dim() != dim:
+        raise ValueError("tensor rank %d does not match dim %d" % (u.dim(), dim))
+    if u.stride(-1) != 1:
+        raise ValueError("x must be contiguous")
+    d = cs_grid_desc()
+    d.dim = dim
+    d.stencil = int(stencil)
+    d.dtype = _DT[u.dtype]
+    d.parity = int(parity)
+    d.n[0] = u.shape[-1] - 2
+    d.n[1] = u.shape[-2] - 2
+    d.n[2] = u.shape[-3] - 2 if dim == 3 else 1
+    d.stride[0] = 1
+    d.stride[1] = u.stride(-2)
+    d.stride[2] = u.stride(-3) if dim == 3 else 0
+    d.h = float(h)
+    return d
+
+
+class Grid:
+    """A colsten grid bound to caller-owned tensors u (updated) and b."""
+
+    def __init__(self, u, b, *, dim, stencil, h, parity=0):
+        if u.shape != b.shape or u.stride() != b.stride() or u.dtype != b.dtype:
+            raise ValueError("u and b must share shape, strides and dtype")
+        self.u, self.b = u, b
+        self.dim, self.stencil, self.h, self.parity = dim, stencil, h, parity
+        self.desc = describe(u, dim=dim, stencil=stencil, h=h, parity=parity)
+        self.handle = cs_grid_create(self.desc, u.data_ptr(), b.data_ptr())
+        self.norms = torch.zeros(3, dtype=torch.float64, device=u.device)
+
+    def close(self):
+        if self.handle:
+            cs_grid_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_colours(self):
+        return cs_num_colours(self.handle)
+
+    def colour_pass(self, colour, stream=None):
+        cs_colour_pass(self.handle, colour, stream)
+
+    def gs(self, nsweeps, tmp=None, stream=None):
+        cs_gs_sweeps(self.handle, nsweeps, 0 if tmp is None else tmp.data_ptr(), stream)
+
+    def jacobi(self, omega, nsweeps, tmp, stream=None):
+        cs_jacobi_sweeps(self.handle, omega, nsweeps, tmp.data_ptr(), stream)
+
+    def residual(self, r=None, norms=None, stream=None):
+        """Enqueue the residual; returns the device tensor of the 3 norms."""
+        out = self.norms if norms is None else norms
+        cs_residual(self.handle, 0 if r is None else r.data_ptr(), out.data_ptr(), stream)
+        return out

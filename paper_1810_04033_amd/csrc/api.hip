@@ -1,0 +1,273 @@
+// C ABI of the colsten library: argument validation, dispatch and the sweep
+// drivers.  No function here synchronises the host except the create calls.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <cmath>
+#include <new>
+
+#include "cs_internal.h"
+
+namespace cs {
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+void set_error(const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+cs_status hip_fail(hipError_t e, const char* what)
+{
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return CS_EHIP;
+}
+
+cs_status check_launch(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, what);
+    return CS_OK;
+}
+
+namespace {
+
+int64_t span_of(const cs_grid_desc& d)
+{
+    if (d.dim == 2) return (d.n[1] + 1) * d.stride[1] + d.n[0] + 2;
+    return (d.n[2] + 1) * d.stride[2] + (d.n[1] + 1) * d.stride[1] + d.n[0] + 2;
+}
+
+cs_status validate_desc(const cs_grid_desc* d)
+{
+    if (!d) { set_error("desc is NULL"); return CS_EINVAL; }
+    if (d->dim != 2 && d->dim != 3) { set_error("dim must be 2 or 3 (got %d)", d->dim); return CS_EINVAL; }
+    if (d->stencil != CS_FD && d->stencil != CS_Q1) { set_error("unknown stencil %d", d->stencil); return CS_EINVAL; }
+    if (d->dtype != CS_F64 && d->dtype != CS_F32) { set_error("unknown dtype %d", d->dtype); return CS_EINVAL; }
+    if (d->parity != 0 && d->parity != 1) { set_error("parity must be 0 or 1"); return CS_EINVAL; }
+    const int64_t lim = (int64_t)1 << 24;
+    for (int a = 0; a < d->dim; ++a)
+        if (d->n[a] < 1 || d->n[a] > lim) { set_error("n[%d] = %lld out of range [1, 2^24]", a, (long long)d->n[a]); return CS_EINVAL; }
+    if (d->dim == 2 && d->n[2] != 1) { set_error("n[2] must be 1 for a 2D grid"); return CS_EINVAL; }
+    if (d->stride[0] != 1) { set_error("stride[0] must be 1 (x contiguous)"); return CS_EINVAL; }
+    if (d->stride[1] < d->n[0] + 2) { set_error("stride[1] must be >= n[0] + 2"); return CS_EINVAL; }
+    if (d->dim == 3 && d->stride[2] < d->stride[1] * (d->n[1] + 2)) {
+        set_error("stride[2] must be >= stride[1] * (n[1] + 2)");
+        return CS_EINVAL;
+    }
+    if (!(d->h > 0.0) || !std::isfinite(d->h)) { set_error("h must be finite and > 0"); return CS_EINVAL; }
+    const double total = (double)span_of(*d);
+    if (total > 9.0e18 / 8) { set_error("grid extent overflows"); return CS_EINVAL; }
+    return CS_OK;
+}
+
+// The pointer must be device memory on the current device, aligned to the
+// element size, and the allocation must cover `bytes` from it.
+cs_status check_device_range(const void* p, size_t bytes, size_t align, const char* name)
+{
+    if (!p) { set_error("%s is NULL", name); return CS_EINVAL; }
+    if ((uintptr_t)p % align) { set_error("%s is not %zu-byte aligned", name, align); return CS_EINVAL; }
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipPointerAttribute_t attr;
+    e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("%s is not a HIP allocation", name);
+        return CS_EINVAL;
+    }
+    if (attr.type != hipMemoryTypeDevice) { set_error("%s is not device memory", name); return CS_EINVAL; }
+    if (attr.device != dev) { set_error("%s lives on device %d, current device is %d", name, attr.device, dev); return CS_EINVAL; }
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("%s: cannot query its allocation range", name);
+        return CS_EINVAL;
+    }
+    const uintptr_t lo = (uintptr_t)base, hi = lo + size, a = (uintptr_t)p;
+    if (a < lo || a + bytes > hi) {
+        set_error("%s: the halo'd grid (%zu bytes) runs past its allocation", name, bytes);
+        return CS_EINVAL;
+    }
+    return CS_OK;
+}
+
+cs_status check_grid(cs_grid g)
+{
+    if (!g) { set_error("grid is NULL"); return CS_EINVAL; }
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != g->device) { set_error("grid belongs to device %d, current device is %d", g->device, dev); return CS_EINVAL; }
+    return CS_OK;
+}
+
+double h2_of(const cs_grid_s* g)
+{
+    const double h2 = g->d.h * g->d.h;
+    return g->d.dtype == CS_F32 ? (double)(float)h2 : h2;
+}
+
+cs_status check_tmp(const cs_grid_s* g, const void* tmp)
+{
+    if (tmp == g->u || tmp == g->b) { set_error("u_tmp must be a separate array"); return CS_EINVAL; }
+    return check_device_range(tmp, (size_t)g->span * g->elem, g->elem, "u_tmp");
+}
+
+}  // namespace
+}  // namespace cs
+
+using namespace cs;
+
+extern "C" {
+
+const char* cs_last_error(void) { return g_err; }
+
+cs_status cs_grid_create(const cs_grid_desc* desc, void* u, const void* b, cs_grid* out)
+{
+    g_err[0] = 0;
+    if (!out) { set_error("out is NULL"); return CS_EINVAL; }
+    *out = nullptr;
+    cs_status st = validate_desc(desc);
+    if (st != CS_OK) return st;
+    const size_t elem = desc->dtype == CS_F64 ? 8 : 4;
+    const int64_t span = span_of(*desc);
+    if ((st = check_device_range(u, (size_t)span * elem, elem, "u")) != CS_OK) return st;
+    if ((st = check_device_range(b, (size_t)span * elem, elem, "b")) != CS_OK) return st;
+    if (u == b) { set_error("u and b must be separate arrays"); return CS_EINVAL; }
+    cs_grid_s* g = new (std::nothrow) cs_grid_s();
+    if (!g) { set_error("out of host memory"); return CS_ENOMEM; }
+    g->d = *desc;
+    if (g->d.dim == 2) { g->d.n[2] = 1; g->d.stride[2] = 0; }
+    g->geo.nx = g->d.n[0];
+    g->geo.ny = g->d.n[1];
+    g->geo.nz = g->d.dim == 3 ? g->d.n[2] : 1;
+    g->geo.sy = g->d.stride[1];
+    g->geo.sz = g->d.dim == 3 ? g->d.stride[2] : 0;
+    g->geo.parity = g->d.parity;
+    g->u = u;
+    g->b = b;
+    g->elem = elem;
+    g->span = span;
+    hipError_t e = hipGetDevice(&g->device);
+    if (e != hipSuccess) { delete g; return hip_fail(e, "hipGetDevice"); }
+    e = hipMalloc((void**)&g->partials, sizeof(Partial) * kMaxResidualBlocks);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete g;
+        set_error("hipMalloc of the reduction scratch failed: %s", hipGetErrorString(e));
+        return CS_ENOMEM;
+    }
+    *out = g;
+    return CS_OK;
+}
+
+cs_status cs_grid_destroy(cs_grid g)
+{
+    if (!g) return CS_OK;
+    hipError_t e = hipFree(g->partials);
+    delete g;
+    if (e != hipSuccess) return hip_fail(e, "hipFree");
+    return CS_OK;
+}
+
+cs_status cs_num_colours(cs_grid g, int32_t* out)
+{
+    if (!g || !out) { set_error("NULL argument"); return CS_EINVAL; }
+    *out = g->d.stencil == CS_FD ? 2 : (1 << g->d.dim);
+    return CS_OK;
+}
+
+cs_status cs_colour_pass(cs_grid g, int32_t colour, void* stream)
+{
+    cs_status st = check_grid(g);
+    if (st != CS_OK) return st;
+    const int nc = g->d.stencil == CS_FD ? 2 : (1 << g->d.dim);
+    if (colour < 0 || colour >= nc) { set_error("colour %d outside [0, %d)", colour, nc); return CS_EINVAL; }
+    return launch_colour_pass(g->d.dtype, g->d.dim, g->d.stencil, g->geo, g->u, g->b, h2_of(g),
+                              colour, (hipStream_t)stream);
+}
+
+cs_status cs_gs_sweeps(cs_grid g, int32_t nsweeps, void* u_tmp, void* stream)
+{
+    cs_status st = check_grid(g);
+    if (st != CS_OK) return st;
+    if (nsweeps < 0) { set_error("nsweeps must be >= 0"); return CS_EINVAL; }
+    if (nsweeps == 0) return CS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const double h2 = h2_of(g);
+    const int dt = g->d.dtype, dim = g->d.dim, sten = g->d.stencil;
+    if (u_tmp) {
+        if ((st = check_tmp(g, u_tmp)) != CS_OK) return st;
+    }
+    if (u_tmp && fused_supported(dt, dim, sten, g->geo)) {
+        if ((st = launch_halo_copy(dt, dim, g->geo, g->u, u_tmp, s)) != CS_OK) return st;
+        const void* src = g->u;
+        void* dst = u_tmp;
+        for (int32_t it = 0; it < nsweeps; ++it) {
+            st = launch_fused_sweep(dt, dim, sten, g->geo, src, dst, g->b, h2, s);
+            if (st != CS_OK) return st;
+            void* nsrc = dst;
+            dst = (void*)src;
+            src = nsrc;
+        }
+        if (src != g->u) return launch_interior_copy(dt, dim, g->geo, src, g->u, s);
+        return CS_OK;
+    }
+    const int nc = sten == CS_FD ? 2 : (1 << dim);
+    for (int32_t it = 0; it < nsweeps; ++it)
+        for (int c = 0; c < nc; ++c)
+            if ((st = launch_colour_pass(dt, dim, sten, g->geo, g->u, g->b, h2, c, s)) != CS_OK)
+                return st;
+    return CS_OK;
+}
+
+cs_status cs_jacobi_sweeps(cs_grid g, double omega, int32_t nsweeps, void* u_tmp, void* stream)
+{
+    cs_status st = check_grid(g);
+    if (st != CS_OK) return st;
+    if (nsweeps < 0) { set_error("nsweeps must be >= 0"); return CS_EINVAL; }
+    if (!std::isfinite(omega)) { set_error("omega must be finite"); return CS_EINVAL; }
+    if (!u_tmp) { set_error("Jacobi needs u_tmp"); return CS_EINVAL; }
+    if ((st = check_tmp(g, u_tmp)) != CS_OK) return st;
+    if (nsweeps == 0) return CS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int dt = g->d.dtype, dim = g->d.dim, sten = g->d.stencil;
+    if ((st = launch_halo_copy(dt, dim, g->geo, g->u, u_tmp, s)) != CS_OK) return st;
+    const void* src = g->u;
+    void* dst = u_tmp;
+    for (int32_t it = 0; it < nsweeps; ++it) {
+        st = launch_jacobi(dt, dim, sten, g->geo, src, dst, g->b, h2_of(g), omega, s);
+        if (st != CS_OK) return st;
+        void* nsrc = dst;
+        dst = (void*)src;
+        src = nsrc;
+    }
+    if (src != g->u) return launch_interior_copy(dt, dim, g->geo, src, g->u, s);
+    return CS_OK;
+}
+
+cs_status cs_residual(cs_grid g, void* r, double* norms, void* stream)
+{
+    cs_status st = check_grid(g);
+    if (st != CS_OK) return st;
+    if ((st = check_device_range(norms, 3 * sizeof(double), sizeof(double), "norms")) != CS_OK)
+        return st;
+    if (r) {
+        if (r == g->u || r == g->b) { set_error("r must be a separate array"); return CS_EINVAL; }
+        if ((st = check_device_range(r, (size_t)g->span * g->elem, g->elem, "r")) != CS_OK) return st;
+    }
+    return launch_residual(g->d.dtype, g->d.dim, g->d.stencil, g->geo, g->u, g->b, r,
+                           g->d.h * g->d.h, g->partials, norms, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+// Device-side stencil helpers shared by the colsten kernels.
+//
+// The dimensionless stencils of the 2d+1-point finite-difference family and
+// the 3^d-point d-linear finite-element family (Fig. 1 and Sec. 2 of
+// Hazelwood & Weinzierl, arXiv:1810.04033; the 27-point entries are the
+// assembled trilinear element stiffness: faces 0, edges -1/6, corners -1/12).
+//
+// The library is compiled with -ffp-contract=off: `acc += w * v` is one
+// rounded multiply and one rounded add.  Neighbour sums visit the offsets in
+// lexicographic (oz, oy, ox) order and skip zero weights, so a kernel using
+// these helpers rounds exactly like a plain sequential evaluation of
+//     u_q <- (h^2 b_q - sum_{o != 0} S_o u_{q+o}) / S_0 .
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cs {
+
+enum { FD = 0, Q1 = 1 };
+
+// S_o for offset (ox, oy, oz).  Weights are formed in T's own arithmetic
+// (T(-1) / T(6) is the correctly rounded quotient in T).
+template <typename T, int DIM, int ST>
+__host__ __device__ constexpr T weight(int ox, int oy, int oz)
+{
+    const int nnz = (ox != 0) + (oy != 0) + (oz != 0);
+    if (DIM == 2 && oz != 0) return T(0);
+    if (ST == FD) return nnz == 0 ? T(2 * DIM) : (nnz == 1 ? T(-1) : T(0));
+    if (DIM == 2) return nnz == 0 ? T(8) / T(3) : T(-1) / T(3);
+    return nnz == 0 ? T(8) / T(3)
+         : nnz == 1 ? T(0)
+         : nnz == 2 ? T(-1) / T(6)
+                    : T(-1) / T(12);
+}
+
+template <int ST, int DIM>
+__host__ __device__ constexpr int num_colours()
+{
+    return ST == FD ? 2 : (1 << DIM);
+}
+
+// sum_{o} S_o * ld(ox, oy, oz) over the nonzero weights, lexicographic
+// (oz, oy, ox) order; the centre is included iff CENTRE.
+template <typename T, int DIM, int ST, bool CENTRE, typename Load>
+__device__ __forceinline__ T ordered_sum(const Load& ld)
+{
+    T acc = T(0);
+#pragma unroll
+    for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz) {
+#pragma unroll
+        for (int oy = -1; oy <= 1; ++oy) {
+#pragma unroll
+            for (int ox = -1; ox <= 1; ++ox) {
+                if (!CENTRE && ox == 0 && oy == 0 && oz == 0) continue;
+                const T w = weight<T, DIM, ST>(ox, oy, oz);
+                if (w == T(0)) continue;
+                acc += w * ld(ox, oy, oz);
+            }
+        }
+    }
+    return acc;
+}
+
+// Gauss-Seidel value of one point from its neighbours (centre excluded).
+template <typename T, int DIM, int ST, typename Load>
+__device__ __forceinline__ T gs_value(T h2, T bq, const Load& ld)
+{
+    const T rhs = h2 * bq;
+    const T acc = ordered_sum<T, DIM, ST, false>(ld);
+    return (rhs - acc) / weight<T, DIM, ST>(0, 0, 0);
+}
+
+// Weighted Jacobi value: u_q + omega * (h^2 b_q - sum_o S_o u_{q+o}) / S_0.
+template <typename T, int DIM, int ST, typename Load>
+__device__ __forceinline__ T jacobi_value(T h2, T omega, T bq, T uq, const Load& ld)
+{
+    const T su = ordered_sum<T, DIM, ST, true>(ld);
+    return uq + omega * ((h2 * bq - su) / weight<T, DIM, ST>(0, 0, 0));
+}
+
+}  // namespace cs

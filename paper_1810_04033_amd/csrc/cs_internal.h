@@ -1,0 +1,64 @@
+// Internal declarations of the colsten host library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/colsten.h"
+
+namespace cs {
+
+// Geometry passed by value to every kernel.
+struct Geo {
+    int64_t nx, ny, nz;  // interior points (nz == 1 in 2D)
+    int64_t sy, sz;      // element strides (sz == 0 in 2D)
+    int parity;
+};
+
+// Residual partial sums written by each block of the first reduction stage.
+struct Partial {
+    double sum_r2;
+    double max_r;
+    double sum_b2;
+};
+
+// Largest number of first-stage residual blocks (fixed, so the reduction
+// order does not depend on anything but the grid shape).
+constexpr int kMaxResidualBlocks = 2048;
+
+void set_error(const char* fmt, ...);
+cs_status hip_fail(hipError_t e, const char* what);
+// Maps the last launch error to CS_EHIP (and records it); CS_OK otherwise.
+cs_status check_launch(const char* what);
+
+// ---- launchers (kernels in k_basic.hip / k_fused.hip) --------------------
+// dtype 0 = double, 1 = float.  All return CS_OK or CS_EHIP.
+cs_status launch_colour_pass(int dtype, int dim, int stencil, const Geo& g, void* u,
+                             const void* b, double h2, int colour, hipStream_t s);
+cs_status launch_jacobi(int dtype, int dim, int stencil, const Geo& g, const void* src,
+                        void* dst, const void* b, double h2, double omega, hipStream_t s);
+cs_status launch_halo_copy(int dtype, int dim, const Geo& g, const void* src, void* dst,
+                           hipStream_t s);
+cs_status launch_interior_copy(int dtype, int dim, const Geo& g, const void* src, void* dst,
+                               hipStream_t s);
+cs_status launch_residual(int dtype, int dim, int stencil, const Geo& g, const void* u,
+                          const void* b, void* r, double h2, Partial* partials,
+                          double* norms, hipStream_t s);
+// One fused Gauss-Seidel sweep src -> dst (3D grids); returns
+// CS_EUNSUPPORTED for shapes the fused kernels do not cover.
+cs_status launch_fused_sweep(int dtype, int dim, int stencil, const Geo& g, const void* src,
+                             void* dst, const void* b, double h2, hipStream_t s);
+bool fused_supported(int dtype, int dim, int stencil, const Geo& g);
+
+}  // namespace cs
+
+struct cs_grid_s {
+    cs_grid_desc d;
+    cs::Geo geo;
+    void* u;
+    const void* b;
+    int device;
+    size_t elem;          // bytes per element
+    int64_t span;         // elements from the first to one past the last halo'd element
+    cs::Partial* partials;  // kMaxResidualBlocks entries of device scratch
+};

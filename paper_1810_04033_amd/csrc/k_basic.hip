@@ -1,0 +1,340 @@
+// Basic kernels: one launch per colour pass, weighted Jacobi, halo and
+// interior copies, and the residual with a deterministic two-stage reduction.
+//
+// The colour pass is the GPU form of the paper's flat BSP colouring (Sec. 3:
+// one loop over the c colours, each pass a parallel loop over the grid, a
+// global synchronisation between passes): here one kernel launch per colour,
+// the stream order being the synchronisation.  Only the points of the colour
+// are enumerated, x fastest within a wavefront.
+#include "cs_device.h"
+#include "cs_internal.h"
+
+namespace cs {
+
+namespace {
+
+constexpr int kBX = 64;  // threads along x (one wavefront)
+constexpr int kBY = 4;   // rows per block
+
+// Number of i in [i0, n] with step 2.
+__host__ __device__ inline int64_t count_step2(int64_t i0, int64_t n)
+{
+    return i0 <= n ? (n - i0) / 2 + 1 : 0;
+}
+
+template <typename T, int DIM, int ST>
+__global__ void __launch_bounds__(kBX* kBY)
+k_colour_pass(T* __restrict__ u, const T* __restrict__ b, Geo g, T h2, int colour,
+              int64_t rows_y, int64_t rows_z, int64_t xblocks)
+{
+    const int64_t bid = blockIdx.x;
+    const int64_t xb = bid % xblocks;
+    const int64_t row = (bid / xblocks) * kBY + threadIdx.y;
+    if (row >= rows_y * rows_z) return;
+    const int64_t ty = row % rows_y;
+    const int64_t tz = row / rows_y;
+    int64_t i0, j, k;
+    if (ST == FD) {
+        j = 1 + ty;
+        k = 1 + tz;
+        const int64_t kk = DIM == 3 ? k - 1 : 0;
+        i0 = 1 + ((colour + (j - 1) + kk + g.parity) & 1);
+    } else {
+        const int px = colour & 1, py = (colour >> 1) & 1, pz = (colour >> 2) & 1;
+        i0 = 1 + ((px + g.parity) & 1);
+        j = 1 + ((py + g.parity) & 1) + 2 * ty;
+        k = DIM == 3 ? 1 + ((pz + g.parity) & 1) + 2 * tz : 1;
+    }
+    const int64_t i = i0 + 2 * (xb * kBX + threadIdx.x);
+    if (i > g.nx) return;
+    const int64_t q = (DIM == 3 ? k * g.sz : 0) + j * g.sy + i;
+    const int64_t sy = g.sy, sz = g.sz;
+    auto ld = [&](int ox, int oy, int oz) { return u[q + oz * sz + oy * sy + ox]; };
+    u[q] = gs_value<T, DIM, ST>(h2, b[q], ld);
+}
+
+template <typename T, int DIM, int ST>
+__global__ void __launch_bounds__(kBX* kBY)
+k_jacobi(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict__ b, Geo g, T h2,
+         T omega, int64_t xblocks)
+{
+    const int64_t bid = blockIdx.x;
+    const int64_t xb = bid % xblocks;
+    const int64_t row = (bid / xblocks) * kBY + threadIdx.y;
+    if (row >= g.ny * g.nz) return;
+    const int64_t j = 1 + row % g.ny;
+    const int64_t k = 1 + row / g.ny;
+    const int64_t i = 1 + xb * kBX + threadIdx.x;
+    if (i > g.nx) return;
+    const int64_t q = (DIM == 3 ? k * g.sz : 0) + j * g.sy + i;
+    const int64_t sy = g.sy, sz = g.sz;
+    auto ld = [&](int ox, int oy, int oz) { return src[q + oz * sz + oy * sy + ox]; };
+    dst[q] = jacobi_value<T, DIM, ST>(h2, omega, b[q], src[q], ld);
+}
+
+// Halo points enumerated as: (3D) planes k = 0 and k = nz+1 in full, then for
+// each interior plane the rows j = 0, j = ny+1 and the columns i = 0, i = nx+1.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256)
+k_halo_copy(const T* __restrict__ src, T* __restrict__ dst, Geo g, int64_t total)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int64_t wx = g.nx + 2;
+    const int64_t plane = wx * (g.ny + 2);
+    int64_t i, j, k;
+    int64_t r = t;
+    if (DIM == 3 && r < 2 * plane) {
+        k = r < plane ? 0 : g.nz + 1;
+        r %= plane;
+        j = r / wx;
+        i = r % wx;
+    } else {
+        if (DIM == 3) r -= 2 * plane;
+        const int64_t per = 2 * wx + 2 * g.ny;
+        k = DIM == 3 ? 1 + r / per : 0;
+        r %= per;
+        if (r < 2 * wx) {
+            j = r < wx ? 0 : g.ny + 1;
+            i = r % wx;
+        } else {
+            r -= 2 * wx;
+            j = 1 + r / 2;
+            i = (r & 1) ? g.nx + 1 : 0;
+        }
+    }
+    const int64_t q = (DIM == 3 ? k * g.sz : 0) + j * g.sy + i;
+    dst[q] = src[q];
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBX* kBY)
+k_interior_copy(const T* __restrict__ src, T* __restrict__ dst, Geo g, int64_t xblocks)
+{
+    const int64_t bid = blockIdx.x;
+    const int64_t xb = bid % xblocks;
+    const int64_t row = (bid / xblocks) * kBY + threadIdx.y;
+    if (row >= g.ny * g.nz) return;
+    const int64_t j = 1 + row % g.ny;
+    const int64_t k = 1 + row / g.ny;
+    const int64_t i = 1 + xb * kBX + threadIdx.x;
+    if (i > g.nx) return;
+    const int64_t q = (DIM == 3 ? k * g.sz : 0) + j * g.sy + i;
+    dst[q] = src[q];
+}
+
+// Fixed-shape tree reduction of three values over a 256-thread block.
+__device__ inline void block_reduce3(double& a, double& m, double& c, double* sh)
+{
+    const int t = threadIdx.y * blockDim.x + threadIdx.x;
+    sh[t] = a;
+    sh[256 + t] = m;
+    sh[512 + t] = c;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            sh[t] = sh[t] + sh[t + w];
+            sh[256 + t] = fmax(sh[256 + t], sh[256 + t + w]);
+            sh[512 + t] = sh[512 + t] + sh[512 + t + w];
+        }
+        __syncthreads();
+    }
+    a = sh[0];
+    m = sh[256];
+    c = sh[512];
+}
+
+// Stage 1: each block walks a fixed set of (x-block, row-group) tiles.
+template <typename S, int DIM, int ST>
+__global__ void __launch_bounds__(kBX* kBY)
+k_residual(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ r, Geo g,
+           double h2, int64_t xblocks, int64_t tiles, Partial* __restrict__ partials)
+{
+    __shared__ double sh[3 * 256];
+    double s_r2 = 0.0, mx = 0.0, s_b2 = 0.0;
+    const int64_t sy = g.sy, sz = g.sz;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int64_t xb = tile % xblocks;
+        const int64_t row = (tile / xblocks) * kBY + threadIdx.y;
+        const int64_t i = 1 + xb * kBX + threadIdx.x;
+        if (row >= g.ny * g.nz || i > g.nx) continue;
+        const int64_t j = 1 + row % g.ny;
+        const int64_t k = 1 + row / g.ny;
+        const int64_t q = (DIM == 3 ? k * g.sz : 0) + j * g.sy + i;
+        auto ld = [&](int ox, int oy, int oz) { return (double)u[q + oz * sz + oy * sy + ox]; };
+        const double su = ordered_sum<double, DIM, ST, true>(ld);
+        const double bq = (double)b[q];
+        const double rq = bq - su / h2;
+        if (r) r[q] = (S)rq;
+        s_r2 += rq * rq;
+        s_b2 += bq * bq;
+        mx = fmax(mx, fabs(rq));
+    }
+    block_reduce3(s_r2, mx, s_b2, sh);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        partials[blockIdx.x].sum_r2 = s_r2;
+        partials[blockIdx.x].max_r = mx;
+        partials[blockIdx.x].sum_b2 = s_b2;
+    }
+}
+
+// Stage 2: one block folds the partials in a fixed order.
+__global__ void __launch_bounds__(256)
+k_residual_finish(const Partial* __restrict__ partials, int count, double* __restrict__ norms)
+{
+    __shared__ double sh[3 * 256];
+    double a = 0.0, m = 0.0, c = 0.0;
+    for (int p = threadIdx.x; p < count; p += 256) {
+        a += partials[p].sum_r2;
+        m = fmax(m, partials[p].max_r);
+        c += partials[p].sum_b2;
+    }
+    block_reduce3(a, m, c, sh);
+    if (threadIdx.x == 0) {
+        norms[0] = sqrt(a);
+        norms[1] = m;
+        norms[2] = sqrt(c);
+    }
+}
+
+template <typename T, int DIM, int ST>
+cs_status colour_pass_t(const Geo& g, void* u, const void* b, double h2, int colour,
+                        hipStream_t s)
+{
+    int64_t rows_y, rows_z, xcount;
+    if (ST == FD) {
+        rows_y = g.ny;
+        rows_z = DIM == 3 ? g.nz : 1;
+        xcount = (g.nx + 1) / 2;
+    } else {
+        const int px = colour & 1, py = (colour >> 1) & 1, pz = (colour >> 2) & 1;
+        xcount = count_step2(1 + ((px + g.parity) & 1), g.nx);
+        rows_y = count_step2(1 + ((py + g.parity) & 1), g.ny);
+        rows_z = DIM == 3 ? count_step2(1 + ((pz + g.parity) & 1), g.nz) : 1;
+    }
+    if (xcount == 0 || rows_y == 0 || rows_z == 0) return CS_OK;
+    const int64_t xblocks = (xcount + kBX - 1) / kBX;
+    const int64_t rblocks = (rows_y * rows_z + kBY - 1) / kBY;
+    const int64_t blocks = xblocks * rblocks;
+    if (blocks > 0x7fffffff) {
+        set_error("colour pass: grid too large (%lld blocks)", (long long)blocks);
+        return CS_EUNSUPPORTED;
+    }
+    hipLaunchKernelGGL((k_colour_pass<T, DIM, ST>), dim3((unsigned)blocks), dim3(kBX, kBY), 0, s,
+                       (T*)u, (const T*)b, g, (T)h2, colour, rows_y, rows_z, xblocks);
+    return check_launch("colour pass");
+}
+
+template <typename T, int DIM, int ST>
+cs_status jacobi_t(const Geo& g, const void* src, void* dst, const void* b, double h2,
+                   double omega, hipStream_t s)
+{
+    const int64_t xblocks = (g.nx + kBX - 1) / kBX;
+    const int64_t blocks = xblocks * ((g.ny * g.nz + kBY - 1) / kBY);
+    if (blocks > 0x7fffffff) {
+        set_error("jacobi: grid too large");
+        return CS_EUNSUPPORTED;
+    }
+    hipLaunchKernelGGL((k_jacobi<T, DIM, ST>), dim3((unsigned)blocks), dim3(kBX, kBY), 0, s,
+                       (const T*)src, (T*)dst, (const T*)b, g, (T)h2, (T)omega, xblocks);
+    return check_launch("jacobi");
+}
+
+template <typename S, int DIM, int ST>
+cs_status residual_t(const Geo& g, const void* u, const void* b, void* r, double h2,
+                     Partial* partials, double* norms, hipStream_t s)
+{
+    const int64_t xblocks = (g.nx + kBX - 1) / kBX;
+    const int64_t tiles = xblocks * ((g.ny * g.nz + kBY - 1) / kBY);
+    const int blocks = (int)(tiles < kMaxResidualBlocks ? tiles : kMaxResidualBlocks);
+    hipLaunchKernelGGL((k_residual<S, DIM, ST>), dim3(blocks), dim3(kBX, kBY), 0, s,
+                       (const S*)u, (const S*)b, (S*)r, g, h2, xblocks, tiles, partials);
+    cs_status st = check_launch("residual");
+    if (st != CS_OK) return st;
+    hipLaunchKernelGGL(k_residual_finish, dim3(1), dim3(256), 0, s, partials, blocks, norms);
+    return check_launch("residual finish");
+}
+
+}  // namespace
+
+#define CS_DISPATCH(FN, dtype, dim, stencil, ...)                                         \
+    do {                                                                                  \
+        if (dtype == 0) {                                                                 \
+            if (dim == 2) return stencil == FD ? FN<double, 2, FD>(__VA_ARGS__)           \
+                                               : FN<double, 2, Q1>(__VA_ARGS__);          \
+            return stencil == FD ? FN<double, 3, FD>(__VA_ARGS__)                         \
+                                 : FN<double, 3, Q1>(__VA_ARGS__);                        \
+        }                                                                                 \
+        if (dim == 2) return stencil == FD ? FN<float, 2, FD>(__VA_ARGS__)                \
+                                           : FN<float, 2, Q1>(__VA_ARGS__);               \
+        return stencil == FD ? FN<float, 3, FD>(__VA_ARGS__) : FN<float, 3, Q1>(__VA_ARGS__); \
+    } while (0)
+
+cs_status launch_colour_pass(int dtype, int dim, int stencil, const Geo& g, void* u,
+                             const void* b, double h2, int colour, hipStream_t s)
+{
+    CS_DISPATCH(colour_pass_t, dtype, dim, stencil, g, u, b, h2, colour, s);
+}
+
+cs_status launch_jacobi(int dtype, int dim, int stencil, const Geo& g, const void* src,
+                        void* dst, const void* b, double h2, double omega, hipStream_t s)
+{
+    CS_DISPATCH(jacobi_t, dtype, dim, stencil, g, src, dst, b, h2, omega, s);
+}
+
+cs_status launch_residual(int dtype, int dim, int stencil, const Geo& g, const void* u,
+                          const void* b, void* r, double h2, Partial* partials,
+                          double* norms, hipStream_t s)
+{
+    CS_DISPATCH(residual_t, dtype, dim, stencil, g, u, b, r, h2, partials, norms, s);
+}
+
+cs_status launch_halo_copy(int dtype, int dim, const Geo& g, const void* src, void* dst,
+                           hipStream_t s)
+{
+    const int64_t wx = g.nx + 2;
+    const int64_t per = 2 * wx + 2 * g.ny;
+    const int64_t total = dim == 3 ? 2 * wx * (g.ny + 2) + g.nz * per : per;
+    const int64_t blocks = (total + 255) / 256;
+    if (dtype == 0) {
+        if (dim == 2)
+            hipLaunchKernelGGL((k_halo_copy<double, 2>), dim3((unsigned)blocks), dim3(256), 0, s,
+                               (const double*)src, (double*)dst, g, total);
+        else
+            hipLaunchKernelGGL((k_halo_copy<double, 3>), dim3((unsigned)blocks), dim3(256), 0, s,
+                               (const double*)src, (double*)dst, g, total);
+    } else {
+        if (dim == 2)
+            hipLaunchKernelGGL((k_halo_copy<float, 2>), dim3((unsigned)blocks), dim3(256), 0, s,
+                               (const float*)src, (float*)dst, g, total);
+        else
+            hipLaunchKernelGGL((k_halo_copy<float, 3>), dim3((unsigned)blocks), dim3(256), 0, s,
+                               (const float*)src, (float*)dst, g, total);
+    }
+    return check_launch("halo copy");
+}
+
+cs_status launch_interior_copy(int dtype, int dim, const Geo& g, const void* src, void* dst,
+                               hipStream_t s)
+{
+    const int64_t xblocks = (g.nx + kBX - 1) / kBX;
+    const int64_t blocks = xblocks * ((g.ny * g.nz + kBY - 1) / kBY);
+    if (dtype == 0) {
+        if (dim == 2)
+            hipLaunchKernelGGL((k_interior_copy<double, 2>), dim3((unsigned)blocks), dim3(kBX, kBY),
+                               0, s, (const double*)src, (double*)dst, g, xblocks);
+        else
+            hipLaunchKernelGGL((k_interior_copy<double, 3>), dim3((unsigned)blocks), dim3(kBX, kBY),
+                               0, s, (const double*)src, (double*)dst, g, xblocks);
+    } else {
+        if (dim == 2)
+            hipLaunchKernelGGL((k_interior_copy<float, 2>), dim3((unsigned)blocks), dim3(kBX, kBY),
+                               0, s, (const float*)src, (float*)dst, g, xblocks);
+        else
+            hipLaunchKernelGGL((k_interior_copy<float, 3>), dim3((unsigned)blocks), dim3(kBX, kBY),
+                               0, s, (const float*)src, (float*)dst, g, xblocks);
+    }
+    return check_launch("interior copy");
+}
+
+}  // namespace cs
