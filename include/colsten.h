@@ -121,6 +121,10 @@ cs_status cs_jacobi_sweeps(cs_grid g, double omega, int32_t nsweeps, void* u_tmp
  * same data give identical bits.  FP32 grids are evaluated in FP64. */
 cs_status cs_residual(cs_grid g, void* r, double* norms, void* stream);
 
+/* *out = 1 if cs_gs_sweeps with a work array runs this grid's sweeps as fused
+ * single passes, 0 if it falls back to one launch per colour. */
+cs_status cs_gs_fused(cs_grid g, int32_t* out);
+
 /* Description of the last failure on the calling thread ("" if none). */
 const char* cs_last_error(void);
 

@@ -51,6 +51,7 @@ _SIGS = {
                                       ctypes.POINTER(ctypes.c_void_p)]),
     "cs_grid_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "cs_num_colours": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "cs_gs_fused": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "cs_colour_pass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "cs_gs_sweeps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "cs_jacobi_sweeps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32,
@@ -117,6 +118,12 @@ def cs_num_colours(handle):
     out = ctypes.c_int32()
     _check(lib().cs_num_colours(ctypes.c_void_p(handle), ctypes.byref(out)))
     return out.value
+
+
+def cs_gs_fused(handle):
+    out = ctypes.c_int32()
+    _check(lib().cs_gs_fused(ctypes.c_void_p(handle), ctypes.byref(out)))
+    return bool(out.value)
 
 
 def cs_colour_pass(handle, colour, stream=None):
@@ -226,6 +233,10 @@ class Grid:
     @property
     def num_colours(self):
         return cs_num_colours(self.handle)
+
+    @property
+    def fused(self):
+        return cs_gs_fused(self.handle)
 
     def colour_pass(self, colour, stream=None):
         cs_colour_pass(self.handle, colour, stream)

@@ -187,6 +187,13 @@ cs_status cs_num_colours(cs_grid g, int32_t* out)
     return CS_OK;
 }
 
+cs_status cs_gs_fused(cs_grid g, int32_t* out)
+{
+    if (!g || !out) { set_error("NULL argument"); return CS_EINVAL; }
+    *out = fused_supported(g->d.dtype, g->d.dim, g->d.stencil, g->geo) ? 1 : 0;
+    return CS_OK;
+}
+
 cs_status cs_colour_pass(cs_grid g, int32_t colour, void* stream)
 {
     cs_status st = check_grid(g);

@@ -79,8 +79,6 @@ def test_zero_sweeps_and_destroy_leave_buffers_alone():
     C.cs_grid_destroy(0)
     torch.cuda.synchronize()
     assert torch.equal(u, ref)
-    assert C.cs_num_colours  # library still usable
-    assert u.sum().item() == ref.sum().item()
 
 
 def test_num_colours():
