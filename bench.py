@@ -197,9 +197,12 @@ def main():
     # mean launch duration below charges that to the kernel (conservative)
     mean_launch_s = row_ms[dom] * 1e-3 / launches
     achieved = bytes_per_launch / mean_launch_s / 1e9
-    src = ["paper_1810_04033_amd/csrc/k_fused.hip", "paper_1810_04033_amd/csrc/cs_device.h"] if (
-        dom.startswith("gs") and fused_rows[st_name]) else ["paper_1810_04033_amd/csrc/k_basic.hip",
-                                              "paper_1810_04033_amd/csrc/cs_device.h"]
+    if kernel.startswith("fused"):
+        src = ["paper_1810_04033_amd/csrc/k_fused.hip", "paper_1810_04033_amd/csrc/cs_device.h"]
+    elif kernel.startswith("jacobi"):
+        src = ["paper_1810_04033_amd/csrc/k_stream.hip", "paper_1810_04033_amd/csrc/cs_device.h"]
+    else:
+        src = ["paper_1810_04033_amd/csrc/k_basic.hip", "paper_1810_04033_amd/csrc/cs_device.h"]
     sha = _source_sha(src)
     traffic = _traffic(kernel, sha)
     roofline = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),

@@ -49,6 +49,15 @@ cs_status launch_residual(int dtype, int dim, int stencil, const Geo& g, const v
 cs_status launch_fused_sweep(int dtype, int dim, int stencil, const Geo& g, const void* src,
                              void* dst, const void* b, double h2, hipStream_t s);
 bool fused_supported(int dtype, int dim, int stencil, const Geo& g);
+// Second (fixed-order) stage of the residual reduction over `count` partials.
+cs_status launch_residual_finish(const Partial* partials, int count, double* norms, hipStream_t s);
+// z-streaming Jacobi and residual for 3D grids (k_stream.hip).
+bool stream_supported(const Geo& g);
+cs_status launch_jacobi3_stream(int dtype, int stencil, const Geo& g, const void* src, void* dst,
+                                const void* b, double h2, double omega, hipStream_t s);
+cs_status launch_residual3_stream(int dtype, int stencil, const Geo& g, const void* u,
+                                  const void* b, void* r, double h2, Partial* partials,
+                                  double* norms, hipStream_t s);
 
 }  // namespace cs
 

@@ -251,8 +251,7 @@ cs_status residual_t(const Geo& g, const void* u, const void* b, void* r, double
                        (const S*)u, (const S*)b, (S*)r, g, h2, xblocks, tiles, partials);
     cs_status st = check_launch("residual");
     if (st != CS_OK) return st;
-    hipLaunchKernelGGL(k_residual_finish, dim3(1), dim3(256), 0, s, partials, blocks, norms);
-    return check_launch("residual finish");
+    return launch_residual_finish(partials, blocks, norms, s);
 }
 
 }  // namespace
@@ -270,6 +269,12 @@ cs_status residual_t(const Geo& g, const void* u, const void* b, void* r, double
         return stencil == FD ? FN<float, 3, FD>(__VA_ARGS__) : FN<float, 3, Q1>(__VA_ARGS__); \
     } while (0)
 
+cs_status launch_residual_finish(const Partial* partials, int count, double* norms, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_residual_finish, dim3(1), dim3(256), 0, s, partials, count, norms);
+    return check_launch("residual finish");
+}
+
 cs_status launch_colour_pass(int dtype, int dim, int stencil, const Geo& g, void* u,
                              const void* b, double h2, int colour, hipStream_t s)
 {
@@ -279,6 +284,8 @@ cs_status launch_colour_pass(int dtype, int dim, int stencil, const Geo& g, void
 cs_status launch_jacobi(int dtype, int dim, int stencil, const Geo& g, const void* src,
                         void* dst, const void* b, double h2, double omega, hipStream_t s)
 {
+    if (dim == 3 && stream_supported(g))
+        return launch_jacobi3_stream(dtype, stencil, g, src, dst, b, h2, omega, s);
     CS_DISPATCH(jacobi_t, dtype, dim, stencil, g, src, dst, b, h2, omega, s);
 }
 
@@ -286,6 +293,8 @@ cs_status launch_residual(int dtype, int dim, int stencil, const Geo& g, const v
                           const void* b, void* r, double h2, Partial* partials,
                           double* norms, hipStream_t s)
 {
+    if (dim == 3 && stream_supported(g))
+        return launch_residual3_stream(dtype, stencil, g, u, b, r, h2, partials, norms, s);
     CS_DISPATCH(residual_t, dtype, dim, stencil, g, u, b, r, h2, partials, norms, s);
 }
 

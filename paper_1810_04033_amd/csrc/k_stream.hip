@@ -1,0 +1,269 @@
+// Streaming stencil application for the separate-output-array sweeps (Sec. 2:
+// a separate output array gives a mat-vec): weighted Jacobi and the residual,
+// 3D grids.
+//
+// Each workgroup owns an xy tile T of TX x TY points and a chunk of z planes;
+// it streams through z keeping the planes k-1, k, k+1 of the region T+1 in a
+// ring of five LDS slots (the next plane is prefetched into registers one
+// step ahead and stored two slots ahead, so one barrier per plane suffices).
+// Every output point reads its neighbours from LDS in the lexicographic
+// offset order of the plain definition, so the values match the point-wise
+// kernels bit for bit.  The residual accumulates sum r^2, max |r| and sum b^2
+// per thread in a fixed order and folds them per block into the partials
+// consumed by the fixed-order second stage.
+#include "cs_device.h"
+#include "cs_internal.h"
+
+#include <type_traits>
+
+namespace cs {
+
+namespace {
+
+constexpr int kXcds = 8;
+
+__device__ inline int64_t xcd_block(int64_t nblocks)
+{
+    const int64_t b = blockIdx.x;
+    const int64_t per = nblocks / kXcds;
+    const int64_t rem = nblocks % kXcds;
+    const int64_t xcd = b % kXcds;
+    const int64_t slot = b / kXcds;
+    const int64_t start = xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per;
+    return start + slot;
+}
+
+struct StreamWork {
+    int tiles_x, tiles_y;
+    int chunks;
+    int64_t nblocks;
+};
+
+enum { MODE_JACOBI = 0, MODE_RESIDUAL = 1 };
+
+__device__ inline void block_fold3(double& a, double& m, double& c, double* sh, int nt)
+{
+    const int t = threadIdx.x;
+    sh[t] = a;
+    sh[nt + t] = m;
+    sh[2 * nt + t] = c;
+    __syncthreads();
+    for (int w = nt / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            sh[t] = sh[t] + sh[t + w];
+            sh[nt + t] = fmax(sh[nt + t], sh[nt + t + w]);
+            sh[2 * nt + t] = sh[2 * nt + t] + sh[2 * nt + t + w];
+        }
+        __syncthreads();
+    }
+    a = sh[0];
+    m = sh[nt];
+    c = sh[2 * nt];
+}
+
+// S: storage type; the arithmetic type is S for Jacobi and double for the
+// residual.
+template <typename S, int ST, int MODE, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT)
+k_stream3(const S* __restrict__ src, S* __restrict__ dst, const S* __restrict__ b, Geo g,
+          double h2d, double omegad, StreamWork wk, Partial* __restrict__ partials)
+{
+    using A = typename std::conditional<MODE == MODE_RESIDUAL, double, S>::type;
+    constexpr int W = TX + 2, HH = TY + 2, NCOL = W * HH;
+    constexpr int M = (NCOL + NT - 1) / NT;   // load columns per thread
+    constexpr int P = (TX * TY + NT - 1) / NT;  // output points per thread
+    constexpr int R = 5;
+    __shared__ S L[R][NCOL];
+
+    const int64_t work = xcd_block(wk.nblocks);
+    const int64_t tiles = (int64_t)wk.tiles_x * wk.tiles_y;
+    const int64_t chunk = work / tiles;
+    const int64_t tile = work % tiles;
+    const int64_t x0 = 1 + (tile % wk.tiles_x) * TX;
+    const int64_t y0 = 1 + (tile / wk.tiles_x) * TY;
+    const int64_t z0 = 1 + (chunk * g.nz) / wk.chunks;
+    const int64_t z1 = 1 + ((chunk + 1) * g.nz) / wk.chunks;  // output planes [z0, z1)
+    const int tid = threadIdx.x;
+
+    int coff[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int c = tid + NT * m;
+        const int ly = c / W, lx = c % W;
+        const int64_t x = x0 - 1 + lx, y = y0 - 1 + ly;
+        const bool ok = c < NCOL && x >= 0 && x <= g.nx + 1 && y >= 0 && y <= g.ny + 1;
+        coff[m] = ok ? (int)(y * g.sy + x) : -1;
+    }
+    int pc[P], poff[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const int s = tid + NT * i;
+        const int ty = s / TX, tx = s % TX;
+        const int64_t x = x0 + tx, y = y0 + ty;
+        const bool ok = s < TX * TY && x <= g.nx && y <= g.ny;
+        pc[i] = ok ? (ty + 1) * W + (tx + 1) : -1;
+        poff[i] = ok ? (int)(y * g.sy + x) : 0;
+    }
+
+    auto load_plane = [&](int64_t k, S* v) {
+        const bool kin = k >= 0 && k <= g.nz + 1;
+        const S* sp = src + (kin ? k : 0) * g.sz;
+#pragma unroll
+        for (int m = 0; m < M; ++m) v[m] = (kin && coff[m] >= 0) ? sp[coff[m]] : S(0);
+    };
+    auto store_plane = [&](const S* v, S* lp) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int c = tid + NT * m;
+            if (c < NCOL) lp[c] = v[m];
+        }
+    };
+    auto load_b = [&](int64_t k, S* v) {
+        const bool kin = k >= 1 && k <= g.nz;
+        const S* bp = b + (kin ? k : 0) * g.sz;
+#pragma unroll
+        for (int i = 0; i < P; ++i) v[i] = (kin && pc[i] >= 0) ? bp[poff[i]] : S(0);
+    };
+    auto slot = [&](int64_t k) { return (int)((k - z0 + 2 * R) % R); };
+
+    S pre[M], bcur[P], bnxt[P];
+    {
+        S t[M];
+        load_plane(z0 - 1, t);
+        store_plane(t, L[slot(z0 - 1)]);
+        load_plane(z0, t);
+        store_plane(t, L[slot(z0)]);
+    }
+    load_plane(z0 + 1, pre);
+    load_b(z0, bcur);
+
+    const A h2 = (A)h2d, omega = (A)omegad;
+    double s_r2 = 0.0, mx = 0.0, s_b2 = 0.0;
+    for (int64_t k = z0; k < z1; ++k) {
+        store_plane(pre, L[slot(k + 1)]);
+        if (k + 2 <= z1) load_plane(k + 2, pre);
+        if (k + 1 < z1) load_b(k + 1, bnxt);
+        __syncthreads();
+        const S* lm = L[slot(k - 1)];
+        const S* l0 = L[slot(k)];
+        const S* lp = L[slot(k + 1)];
+        S* dp = dst + k * g.sz;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            const int c = pc[i];
+            if (c < 0) continue;
+            auto ld = [&](int ox, int oy, int oz) -> A {
+                const S* pl = oz < 0 ? lm : (oz > 0 ? lp : l0);
+                return (A)pl[c + oy * W + ox];
+            };
+            if (MODE == MODE_JACOBI) {
+                dp[poff[i]] = jacobi_value<A, 3, ST>(h2, omega, (A)bcur[i], (A)l0[c], ld);
+            } else {
+                const double su = ordered_sum<double, 3, ST, true>(ld);
+                const double bq = (double)bcur[i];
+                const double rq = bq - su / h2d;
+                if (dst) dp[poff[i]] = (S)rq;
+                s_r2 += rq * rq;
+                s_b2 += bq * bq;
+                mx = fmax(mx, fabs(rq));
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < P; ++i) bcur[i] = bnxt[i];
+    }
+    if (MODE == MODE_RESIDUAL) {
+        __shared__ double sh[3 * NT];
+        __syncthreads();
+        block_fold3(s_r2, mx, s_b2, sh, NT);
+        if (tid == 0) {
+            partials[blockIdx.x].sum_r2 = s_r2;
+            partials[blockIdx.x].max_r = mx;
+            partials[blockIdx.x].sum_b2 = s_b2;
+        }
+    }
+}
+
+template <typename S, int ST, int MODE, int TX, int TY, int NT>
+StreamWork plan(const Geo& g, int max_blocks)
+{
+    auto kern = k_stream3<S, ST, MODE, TX, TY, NT>;
+    StreamWork wk;
+    wk.tiles_x = (int)((g.nx + TX - 1) / TX);
+    wk.tiles_y = (int)((g.ny + TY - 1) / TY);
+    const int64_t tiles = (int64_t)wk.tiles_x * wk.tiles_y;
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, 0) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        per_cu = 2;
+        cus = 256;
+    }
+    const int64_t resident = (int64_t)(per_cu > 0 ? per_cu : 1) * cus;
+    int64_t chunks = resident / tiles;
+    if (chunks < 1) chunks = 1;
+    if (chunks > g.nz / 4) chunks = g.nz / 4 > 0 ? g.nz / 4 : 1;
+    while (chunks > 1 && tiles * chunks > max_blocks) --chunks;
+    wk.chunks = (int)chunks;
+    wk.nblocks = tiles * chunks;
+    return wk;
+}
+
+template <typename S, int ST>
+cs_status jacobi3_t(const Geo& g, const void* src, void* dst, const void* b, double h2,
+                    double omega, hipStream_t s)
+{
+    constexpr int TX = 64, TY = 8, NT = 256;
+    const StreamWork wk = plan<S, ST, MODE_JACOBI, TX, TY, NT>(g, 1 << 30);
+    hipLaunchKernelGGL((k_stream3<S, ST, MODE_JACOBI, TX, TY, NT>), dim3((unsigned)wk.nblocks),
+                       dim3(NT), 0, s, (const S*)src, (S*)dst, (const S*)b, g, h2, omega, wk,
+                       (Partial*)nullptr);
+    return check_launch("streaming jacobi");
+}
+
+template <typename S, int ST>
+cs_status residual3_t(const Geo& g, const void* u, const void* b, void* r, double h2,
+                      Partial* partials, double* norms, hipStream_t s)
+{
+    constexpr int TX = 64, TY = 8, NT = 256;
+    const StreamWork wk = plan<S, ST, MODE_RESIDUAL, TX, TY, NT>(g, kMaxResidualBlocks);
+    if (wk.nblocks > kMaxResidualBlocks) {
+        set_error("residual: grid needs more than %d blocks", kMaxResidualBlocks);
+        return CS_EUNSUPPORTED;
+    }
+    hipLaunchKernelGGL((k_stream3<S, ST, MODE_RESIDUAL, TX, TY, NT>), dim3((unsigned)wk.nblocks),
+                       dim3(NT), 0, s, (const S*)u, (S*)r, (const S*)b, g, h2, 0.0, wk, partials);
+    cs_status st = check_launch("streaming residual");
+    if (st != CS_OK) return st;
+    return launch_residual_finish(partials, (int)wk.nblocks, norms, s);
+}
+
+}  // namespace
+
+bool stream_supported(const Geo& g)
+{
+    return (g.ny + 2) * g.sy < ((int64_t)1 << 31);
+}
+
+cs_status launch_jacobi3_stream(int dtype, int stencil, const Geo& g, const void* src, void* dst,
+                                const void* b, double h2, double omega, hipStream_t s)
+{
+    if (dtype == 0)
+        return stencil == FD ? jacobi3_t<double, FD>(g, src, dst, b, h2, omega, s)
+                             : jacobi3_t<double, Q1>(g, src, dst, b, h2, omega, s);
+    return stencil == FD ? jacobi3_t<float, FD>(g, src, dst, b, h2, omega, s)
+                         : jacobi3_t<float, Q1>(g, src, dst, b, h2, omega, s);
+}
+
+cs_status launch_residual3_stream(int dtype, int stencil, const Geo& g, const void* u,
+                                  const void* b, void* r, double h2, Partial* partials,
+                                  double* norms, hipStream_t s)
+{
+    if (dtype == 0)
+        return stencil == FD ? residual3_t<double, FD>(g, u, b, r, h2, partials, norms, s)
+                             : residual3_t<double, Q1>(g, u, b, r, h2, partials, norms, s);
+    return stencil == FD ? residual3_t<float, FD>(g, u, b, r, h2, partials, norms, s)
+                         : residual3_t<float, Q1>(g, u, b, r, h2, partials, norms, s);
+}
+
+}  // namespace cs
