@@ -121,6 +121,23 @@ cs_status cs_jacobi_sweeps(cs_grid g, double omega, int32_t nsweeps, void* u_tmp
  * same data give identical bits.  FP32 grids are evaluated in FP64. */
 cs_status cs_residual(cs_grid g, void* r, double* norms, void* stream);
 
+/* ---- FP32 sweeps inside FP64 iterative refinement ----------------------
+ * g64: an FP64 grid whose u holds the iterate x and whose b is the right-hand
+ * side.  g32: an FP32 grid of the same dim, stencil, parity, n and h (its own
+ * strides) whose u holds the correction e and whose b array receives the
+ * scaled residual.  One refinement step is
+ *   cs_ir_residual(g64, g32, s)   r = b - A x (FP64); g32.b = fl32(r / s);
+ *                                 g32.u = 0 on the interior; norms of r
+ *   cs_gs_sweeps(g32, m, ...)     m FP32 Gauss-Seidel sweeps on A e = r / s
+ *   cs_ir_update(g64, g32, s)     x <- x + s * e (FP64)
+ * scale s must be a positive power of two (then r / s and s * e are exact)
+ * and is chosen by the caller, e.g. from the previous step's max |r|.  The
+ * residual and the update stay in FP64 on the device.  norms: device pointer
+ * to 3 doubles as in cs_residual.  Errors: CS_EINVAL on mismatched grids, a
+ * scale that is not a power of two, or a bad norms pointer. */
+cs_status cs_ir_residual(cs_grid g64, cs_grid g32, double scale, double* norms, void* stream);
+cs_status cs_ir_update(cs_grid g64, cs_grid g32, double scale, void* stream);
+
 /* *out = 1 if cs_gs_sweeps with a work array runs this grid's sweeps as fused
  * single passes, 0 if it falls back to one launch per colour. */
 cs_status cs_gs_fused(cs_grid g, int32_t* out);

@@ -223,26 +223,42 @@ def interior(a):
     return a[1:-1, 1:-1, 1:a.shape[2] - 1]
 
 
-def ir_solve(b, tol, *, dim, stencil, h, inner_sweeps, max_outer, check_every=1):
+def _pow2_at_least(v):
+    """Smallest power of two >= v (1.0 for v <= 0)."""
+    if not v > 0.0:
+        return 1.0
+    p = 1.0
+    while p < v:
+        p *= 2.0
+    while p / 2.0 >= v:
+        p /= 2.0
+    return p
+
+
+def ir_solve(b, tol, *, dim, stencil, h, inner_sweeps, max_outer, x0=None):
     """FP32 Gauss-Seidel sweeps inside FP64 iterative refinement.
 
-    Each outer step: r = b - A x in FP64; s = 2**ceil(log2 max|r|);
-    r32 = fl32(r / s); inner_sweeps FP32 sweeps on A e = r32 from e = 0;
-    x <- x + s * e in FP64.  Stops when ||r||_2 / ||b||_2 <= tol.
-    Returns (x, history of relative residuals, outer steps taken).
+    Step i: r_i = b - A x_i in FP64; stop when ||r_i||_2 / ||b||_2 <= tol;
+    r32 = fl32(r_i / s_i); inner_sweeps FP32 sweeps on A e = r32 from e = 0;
+    x_{i+1} = x_i + s_i e in FP64.  The scale s_i is the smallest power of two
+    >= max |r_{i-1}|, with r_{-1} = r_0 (so the residual and its FP32 copy can
+    be formed in one pass).  Returns (x, history of relative residuals, outer
+    steps taken).
     """
-    x = np.zeros_like(b)
+    x = np.zeros_like(b) if x0 is None else x0.copy()
     hist = []
+    norms = residual(x, b, dim=dim, stencil=stencil, h=h)
+    s = _pow2_at_least(norms[1])
     for it in range(max_outer + 1):
         norms, r = residual(x, b, dim=dim, stencil=stencil, h=h, want_r=True)
         rel = norms[0] / norms[2] if norms[2] > 0 else norms[0]
         hist.append(rel)
         if rel <= tol or it == max_outer:
             return x, hist, it
-        s = 2.0 ** np.ceil(np.log2(norms[1])) if norms[1] > 0 else 1.0
         r32 = (r / s).astype(np.float32)
         e = np.zeros_like(r32)
         gs_sweeps(e, r32, inner_sweeps, dim=dim, stencil=stencil, h=h)
         inner = interior(x)
         inner += s * interior(e).astype(np.float64)
+        s = _pow2_at_least(norms[1])
     return x, hist, max_outer

@@ -57,6 +57,9 @@ _SIGS = {
     "cs_jacobi_sweeps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32,
                                         ctypes.c_void_p, ctypes.c_void_p]),
     "cs_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cs_ir_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                                      ctypes.c_void_p]),
+    "cs_ir_update": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]),
     "cs_last_error": (ctypes.c_char_p, []),
 }
 
@@ -143,6 +146,15 @@ def cs_jacobi_sweeps(handle, omega, nsweeps, u_tmp_ptr, stream=None):
 def cs_residual(handle, r_ptr, norms_ptr, stream=None):
     _check(lib().cs_residual(ctypes.c_void_p(handle), ctypes.c_void_p(r_ptr), ctypes.c_void_p(norms_ptr),
                              _stream(stream)))
+
+
+def cs_ir_residual(h64, h32, scale, norms_ptr, stream=None):
+    _check(lib().cs_ir_residual(ctypes.c_void_p(h64), ctypes.c_void_p(h32), float(scale),
+                                ctypes.c_void_p(norms_ptr), _stream(stream)))
+
+
+def cs_ir_update(h64, h32, scale, stream=None):
+    _check(lib().cs_ir_update(ctypes.c_void_p(h64), ctypes.c_void_p(h32), float(scale), _stream(stream)))
 
 
 # --------------------------------------------------------------------------

@@ -277,4 +277,46 @@ cs_status cs_residual(cs_grid g, void* r, double* norms, void* stream)
                            g->d.h * g->d.h, g->partials, norms, (hipStream_t)stream);
 }
 
+static cs_status check_ir_pair(cs_grid g64, cs_grid g32, double scale)
+{
+    cs_status st = check_grid(g64);
+    if (st != CS_OK) return st;
+    if ((st = check_grid(g32)) != CS_OK) return st;
+    if (g64->d.dtype != CS_F64 || g32->d.dtype != CS_F32) {
+        set_error("refinement needs an FP64 grid and an FP32 grid");
+        return CS_EINVAL;
+    }
+    if (g64->d.dim != g32->d.dim || g64->d.stencil != g32->d.stencil ||
+        g64->d.parity != g32->d.parity || g64->d.h != g32->d.h || g64->d.n[0] != g32->d.n[0] ||
+        g64->d.n[1] != g32->d.n[1] || g64->d.n[2] != g32->d.n[2]) {
+        set_error("refinement grids differ in dim, stencil, parity, n or h");
+        return CS_EINVAL;
+    }
+    int ex = 0;
+    if (!(scale > 0.0) || !std::isfinite(scale) || std::frexp(scale, &ex) != 0.5) {
+        set_error("scale must be a positive power of two");
+        return CS_EINVAL;
+    }
+    return CS_OK;
+}
+
+cs_status cs_ir_residual(cs_grid g64, cs_grid g32, double scale, double* norms, void* stream)
+{
+    cs_status st = check_ir_pair(g64, g32, scale);
+    if (st != CS_OK) return st;
+    if ((st = check_device_range(norms, 3 * sizeof(double), sizeof(double), "norms")) != CS_OK)
+        return st;
+    return launch_ir_residual(g64->d.dim, g64->d.stencil, g64->geo, g64->u, g64->b,
+                              g64->d.h * g64->d.h, 1.0 / scale, g32->geo, (void*)g32->b, g32->u,
+                              g64->partials, norms, (hipStream_t)stream);
+}
+
+cs_status cs_ir_update(cs_grid g64, cs_grid g32, double scale, void* stream)
+{
+    cs_status st = check_ir_pair(g64, g32, scale);
+    if (st != CS_OK) return st;
+    return launch_ir_update(g64->d.dim, g64->geo, g64->u, g32->geo, g32->u, scale,
+                            (hipStream_t)stream);
+}
+
 }  // extern "C"

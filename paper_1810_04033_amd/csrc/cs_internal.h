@@ -51,6 +51,16 @@ cs_status launch_fused_sweep(int dtype, int dim, int stencil, const Geo& g, cons
 bool fused_supported(int dtype, int dim, int stencil, const Geo& g);
 // Second (fixed-order) stage of the residual reduction over `count` partials.
 cs_status launch_residual_finish(const Partial* partials, int count, double* norms, hipStream_t s);
+// Mixed-precision refinement: FP64 residual with the scaled FP32 copy and
+// e32 = 0 (g2 is the FP32 layout), and x += e32 * scale.
+cs_status launch_ir_residual(int dim, int stencil, const Geo& g, const void* x, const void* b,
+                             double h2, double inv_scale, const Geo& g2, void* r32, void* e32,
+                             Partial* partials, double* norms, hipStream_t s);
+cs_status launch_ir_residual3(int stencil, const Geo& g, const void* x, const void* b, double h2,
+                              double inv_scale, const Geo& g2, void* r32, void* e32,
+                              Partial* partials, double* norms, hipStream_t s);
+cs_status launch_ir_update(int dim, const Geo& g, void* x, const Geo& g2, const void* e32,
+                           double scale, hipStream_t s);
 // z-streaming Jacobi and residual for 3D grids (k_stream.hip).
 bool stream_supported(const Geo& g);
 cs_status launch_jacobi3_stream(int dtype, int stencil, const Geo& g, const void* src, void* dst,

@@ -178,6 +178,64 @@ k_residual(const S* __restrict__ u, const S* __restrict__ b, S* __restrict__ r, 
     }
 }
 
+// Residual of an FP64 grid with the scaled FP32 copy r32 = fl32(r * inv_scale)
+// and e32 = 0 written at the same points of the FP32 layout g2 (2D grids and
+// grids the streaming kernel does not cover).
+template <int DIM, int ST>
+__global__ void __launch_bounds__(kBX* kBY)
+k_ir_residual(const double* __restrict__ u, const double* __restrict__ b, Geo g, double h2,
+              double inv_scale, Geo g2, float* __restrict__ r32, float* __restrict__ e32,
+              int64_t xblocks, int64_t tiles, Partial* __restrict__ partials)
+{
+    __shared__ double sh[3 * 256];
+    double s_r2 = 0.0, mx = 0.0, s_b2 = 0.0;
+    const int64_t sy = g.sy, sz = g.sz;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int64_t xb = tile % xblocks;
+        const int64_t row = (tile / xblocks) * kBY + threadIdx.y;
+        const int64_t i = 1 + xb * kBX + threadIdx.x;
+        if (row >= g.ny * g.nz || i > g.nx) continue;
+        const int64_t j = 1 + row % g.ny;
+        const int64_t k = 1 + row / g.ny;
+        const int64_t q = (DIM == 3 ? k * g.sz : 0) + j * g.sy + i;
+        const int64_t q2 = (DIM == 3 ? k * g2.sz : 0) + j * g2.sy + i;
+        auto ld = [&](int ox, int oy, int oz) { return u[q + oz * sz + oy * sy + ox]; };
+        const double su = ordered_sum<double, DIM, ST, true>(ld);
+        const double bq = b[q];
+        const double rq = bq - su / h2;
+        r32[q2] = (float)(rq * inv_scale);
+        e32[q2] = 0.0f;
+        s_r2 += rq * rq;
+        s_b2 += bq * bq;
+        mx = fmax(mx, fabs(rq));
+    }
+    block_reduce3(s_r2, mx, s_b2, sh);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        partials[blockIdx.x].sum_r2 = s_r2;
+        partials[blockIdx.x].max_r = mx;
+        partials[blockIdx.x].sum_b2 = s_b2;
+    }
+}
+
+// x <- x + e32 * scale (FP64) over the interior; scale is a power of two.
+template <int DIM>
+__global__ void __launch_bounds__(kBX* kBY)
+k_ir_update(double* __restrict__ x, Geo g, const float* __restrict__ e32, Geo g2, double scale,
+            int64_t xblocks)
+{
+    const int64_t bid = blockIdx.x;
+    const int64_t xb = bid % xblocks;
+    const int64_t row = (bid / xblocks) * kBY + threadIdx.y;
+    if (row >= g.ny * g.nz) return;
+    const int64_t j = 1 + row % g.ny;
+    const int64_t k = 1 + row / g.ny;
+    const int64_t i = 1 + xb * kBX + threadIdx.x;
+    if (i > g.nx) return;
+    const int64_t q = (DIM == 3 ? k * g.sz : 0) + j * g.sy + i;
+    const int64_t q2 = (DIM == 3 ? k * g2.sz : 0) + j * g2.sy + i;
+    x[q] = x[q] + (double)e32[q2] * scale;
+}
+
 // Stage 2: one block folds the partials in a fixed order.
 __global__ void __launch_bounds__(256)
 k_residual_finish(const Partial* __restrict__ partials, int count, double* __restrict__ norms)
@@ -268,6 +326,49 @@ cs_status residual_t(const Geo& g, const void* u, const void* b, void* r, double
                                            : FN<float, 2, Q1>(__VA_ARGS__);               \
         return stencil == FD ? FN<float, 3, FD>(__VA_ARGS__) : FN<float, 3, Q1>(__VA_ARGS__); \
     } while (0)
+
+template <int DIM, int ST>
+cs_status ir_residual_t(const Geo& g, const void* x, const void* b, double h2, double inv_scale,
+                        const Geo& g2, void* r32, void* e32, Partial* partials, double* norms,
+                        hipStream_t s)
+{
+    const int64_t xblocks = (g.nx + kBX - 1) / kBX;
+    const int64_t tiles = xblocks * ((g.ny * g.nz + kBY - 1) / kBY);
+    const int blocks = (int)(tiles < kMaxResidualBlocks ? tiles : kMaxResidualBlocks);
+    hipLaunchKernelGGL((k_ir_residual<DIM, ST>), dim3(blocks), dim3(kBX, kBY), 0, s,
+                       (const double*)x, (const double*)b, g, h2, inv_scale, g2, (float*)r32,
+                       (float*)e32, xblocks, tiles, partials);
+    cs_status st = check_launch("ir residual");
+    if (st != CS_OK) return st;
+    return launch_residual_finish(partials, blocks, norms, s);
+}
+
+cs_status launch_ir_residual(int dim, int stencil, const Geo& g, const void* x, const void* b,
+                             double h2, double inv_scale, const Geo& g2, void* r32, void* e32,
+                             Partial* partials, double* norms, hipStream_t s)
+{
+    if (dim == 3 && stream_supported(g) && stream_supported(g2))
+        return launch_ir_residual3(stencil, g, x, b, h2, inv_scale, g2, r32, e32, partials, norms, s);
+    if (dim == 2)
+        return stencil == FD ? ir_residual_t<2, FD>(g, x, b, h2, inv_scale, g2, r32, e32, partials, norms, s)
+                             : ir_residual_t<2, Q1>(g, x, b, h2, inv_scale, g2, r32, e32, partials, norms, s);
+    return stencil == FD ? ir_residual_t<3, FD>(g, x, b, h2, inv_scale, g2, r32, e32, partials, norms, s)
+                         : ir_residual_t<3, Q1>(g, x, b, h2, inv_scale, g2, r32, e32, partials, norms, s);
+}
+
+cs_status launch_ir_update(int dim, const Geo& g, void* x, const Geo& g2, const void* e32,
+                           double scale, hipStream_t s)
+{
+    const int64_t xblocks = (g.nx + kBX - 1) / kBX;
+    const int64_t blocks = xblocks * ((g.ny * g.nz + kBY - 1) / kBY);
+    if (dim == 2)
+        hipLaunchKernelGGL((k_ir_update<2>), dim3((unsigned)blocks), dim3(kBX, kBY), 0, s,
+                           (double*)x, g, (const float*)e32, g2, scale, xblocks);
+    else
+        hipLaunchKernelGGL((k_ir_update<3>), dim3((unsigned)blocks), dim3(kBX, kBY), 0, s,
+                           (double*)x, g, (const float*)e32, g2, scale, xblocks);
+    return check_launch("ir update");
+}
 
 cs_status launch_residual_finish(const Partial* partials, int count, double* norms, hipStream_t s)
 {

@@ -39,7 +39,7 @@ struct StreamWork {
     int64_t nblocks;
 };
 
-enum { MODE_JACOBI = 0, MODE_RESIDUAL = 1 };
+enum { MODE_JACOBI = 0, MODE_RESIDUAL = 1, MODE_IR = 2 };
 
 __device__ inline void block_fold3(double& a, double& m, double& c, double* sh, int nt)
 {
@@ -63,12 +63,15 @@ __device__ inline void block_fold3(double& a, double& m, double& c, double* sh, 
 
 // S: storage type; the arithmetic type is S for Jacobi and double for the
 // residual.
+// MODE_IR (S = double): the residual r = b - A x plus, at the same points of a
+// second (FP32) layout g2, r32 = fl32(r * inv_scale) and e32 = 0.
 template <typename S, int ST, int MODE, int TX, int TY, int NT>
 __global__ void __launch_bounds__(NT)
 k_stream3(const S* __restrict__ src, S* __restrict__ dst, const S* __restrict__ b, Geo g,
-          double h2d, double omegad, StreamWork wk, Partial* __restrict__ partials)
+          double h2d, double omegad, StreamWork wk, Partial* __restrict__ partials,
+          Geo g2, float* __restrict__ r32, float* __restrict__ e32)
 {
-    using A = typename std::conditional<MODE == MODE_RESIDUAL, double, S>::type;
+    using A = typename std::conditional<MODE == MODE_JACOBI, S, double>::type;
     constexpr int W = TX + 2, HH = TY + 2, NCOL = W * HH;
     constexpr int M = (NCOL + NT - 1) / NT;   // load columns per thread
     constexpr int P = (TX * TY + NT - 1) / NT;  // output points per thread
@@ -94,7 +97,7 @@ k_stream3(const S* __restrict__ src, S* __restrict__ dst, const S* __restrict__ 
         const bool ok = c < NCOL && x >= 0 && x <= g.nx + 1 && y >= 0 && y <= g.ny + 1;
         coff[m] = ok ? (int)(y * g.sy + x) : -1;
     }
-    int pc[P], poff[P];
+    int pc[P], poff[P], poff2[MODE == MODE_IR ? P : 1];
 #pragma unroll
     for (int i = 0; i < P; ++i) {
         const int s = tid + NT * i;
@@ -103,6 +106,7 @@ k_stream3(const S* __restrict__ src, S* __restrict__ dst, const S* __restrict__ 
         const bool ok = s < TX * TY && x <= g.nx && y <= g.ny;
         pc[i] = ok ? (ty + 1) * W + (tx + 1) : -1;
         poff[i] = ok ? (int)(y * g.sy + x) : 0;
+        if (MODE == MODE_IR) poff2[i] = ok ? (int)(y * g2.sy + x) : 0;
     }
 
     auto load_plane = [&](int64_t k, S* v) {
@@ -162,7 +166,11 @@ k_stream3(const S* __restrict__ src, S* __restrict__ dst, const S* __restrict__ 
                 const double su = ordered_sum<double, 3, ST, true>(ld);
                 const double bq = (double)bcur[i];
                 const double rq = bq - su / h2d;
-                if (dst) dp[poff[i]] = (S)rq;
+                if (MODE == MODE_RESIDUAL && dst) dp[poff[i]] = (S)rq;
+                if (MODE == MODE_IR) {
+                    r32[k * g2.sz + poff2[i]] = (float)(rq * omegad);
+                    e32[k * g2.sz + poff2[i]] = 0.0f;
+                }
                 s_r2 += rq * rq;
                 s_b2 += bq * bq;
                 mx = fmax(mx, fabs(rq));
@@ -171,7 +179,7 @@ k_stream3(const S* __restrict__ src, S* __restrict__ dst, const S* __restrict__ 
 #pragma unroll
         for (int i = 0; i < P; ++i) bcur[i] = bnxt[i];
     }
-    if (MODE == MODE_RESIDUAL) {
+    if (MODE != MODE_JACOBI) {
         __shared__ double sh[3 * NT];
         __syncthreads();
         block_fold3(s_r2, mx, s_b2, sh, NT);
@@ -217,7 +225,7 @@ cs_status jacobi3_t(const Geo& g, const void* src, void* dst, const void* b, dou
     const StreamWork wk = plan<S, ST, MODE_JACOBI, TX, TY, NT>(g, 1 << 30);
     hipLaunchKernelGGL((k_stream3<S, ST, MODE_JACOBI, TX, TY, NT>), dim3((unsigned)wk.nblocks),
                        dim3(NT), 0, s, (const S*)src, (S*)dst, (const S*)b, g, h2, omega, wk,
-                       (Partial*)nullptr);
+                       (Partial*)nullptr, g, (float*)nullptr, (float*)nullptr);
     return check_launch("streaming jacobi");
 }
 
@@ -232,13 +240,42 @@ cs_status residual3_t(const Geo& g, const void* u, const void* b, void* r, doubl
         return CS_EUNSUPPORTED;
     }
     hipLaunchKernelGGL((k_stream3<S, ST, MODE_RESIDUAL, TX, TY, NT>), dim3((unsigned)wk.nblocks),
-                       dim3(NT), 0, s, (const S*)u, (S*)r, (const S*)b, g, h2, 0.0, wk, partials);
+                       dim3(NT), 0, s, (const S*)u, (S*)r, (const S*)b, g, h2, 0.0, wk, partials,
+                       g, (float*)nullptr, (float*)nullptr);
     cs_status st = check_launch("streaming residual");
     if (st != CS_OK) return st;
     return launch_residual_finish(partials, (int)wk.nblocks, norms, s);
 }
 
+template <int ST>
+cs_status ir_residual3_t(const Geo& g, const void* x, const void* b, double h2, double inv_scale,
+                         const Geo& g2, void* r32, void* e32, Partial* partials, double* norms,
+                         hipStream_t s)
+{
+    constexpr int TX = 64, TY = 8, NT = 256;
+    const StreamWork wk = plan<double, ST, MODE_IR, TX, TY, NT>(g, kMaxResidualBlocks);
+    if (wk.nblocks > kMaxResidualBlocks) {
+        set_error("ir residual: grid needs more than %d blocks", kMaxResidualBlocks);
+        return CS_EUNSUPPORTED;
+    }
+    hipLaunchKernelGGL((k_stream3<double, ST, MODE_IR, TX, TY, NT>), dim3((unsigned)wk.nblocks),
+                       dim3(NT), 0, s, (const double*)x, (double*)nullptr, (const double*)b, g, h2,
+                       inv_scale, wk, partials, g2, (float*)r32, (float*)e32);
+    cs_status st = check_launch("ir residual");
+    if (st != CS_OK) return st;
+    return launch_residual_finish(partials, (int)wk.nblocks, norms, s);
+}
+
 }  // namespace
+
+cs_status launch_ir_residual3(int stencil, const Geo& g, const void* x, const void* b, double h2,
+                              double inv_scale, const Geo& g2, void* r32, void* e32,
+                              Partial* partials, double* norms, hipStream_t s)
+{
+    return stencil == FD
+               ? ir_residual3_t<FD>(g, x, b, h2, inv_scale, g2, r32, e32, partials, norms, s)
+               : ir_residual3_t<Q1>(g, x, b, h2, inv_scale, g2, r32, e32, partials, norms, s);
+}
 
 bool stream_supported(const Geo& g)
 {
