@@ -138,6 +138,39 @@ cs_status cs_residual(cs_grid g, void* r, double* norms, void* stream);
 cs_status cs_ir_residual(cs_grid g64, cs_grid g32, double scale, double* norms, void* stream);
 cs_status cs_ir_update(cs_grid g64, cs_grid g32, double scale, void* stream);
 
+/* ---- Batched patches ----------------------------------------------------
+ * Many independent 3D patches (the regular patches of block-structured
+ * meshes, Sec. 1-2), each with its own descriptor (n, strides, h, parity),
+ * its own u and b, and a work array tmp with u's layout; stencil and dtype
+ * may differ between patches.  Patches are grouped by (stencil, dtype, tile
+ * variant) and every sweep is one launch per group covering all its patches.
+ * All pointers are validated like cs_grid_create's; the descriptor tables are
+ * uploaded (synchronously) at create.  The arrays stay owned by the caller
+ * and must outlive the batch. */
+typedef struct cs_batch_s* cs_batch;
+
+cs_status cs_batch_create(const cs_grid_desc* descs, void* const* u, const void* const* b,
+                          void* const* tmp, int32_t count, cs_batch* out);
+cs_status cs_batch_destroy(cs_batch bt);
+
+/* nsweeps Gauss-Seidel sweeps of every patch (colours in canonical order),
+ * each patch reading its u / tmp alternately; the result ends in u (one copy
+ * back for odd counts).  The halo of every tmp is overwritten with u's. */
+cs_status cs_batch_gs_sweeps(cs_batch bt, int32_t nsweeps, void* stream);
+
+/* Per-patch residual norms: norms (device, count x 3 doubles) receives, for
+ * patch i at 3*i, ||r||_2, max |r| and ||b||_2 of r = b - A u (FP64
+ * arithmetic).  Each patch's reduction order depends only on its own shape,
+ * so its norms do not depend on the rest of the batch. */
+cs_status cs_batch_residual(cs_batch bt, double* norms, void* stream);
+
+/* Tile policy for batches created afterwards (process-wide): a patch with
+ * n[0] <= small_max uses the small tile, n[0] <= mid_max the middle one,
+ * else the large one (7-point: 16x16, 32x16, 64x16; 27-point: 16x8, 32x16,
+ * 64x16).  Used by the autotuner.  Errors: CS_EINVAL for a bad stencil or
+ * small_max > mid_max. */
+cs_status cs_batch_tile_policy(int32_t stencil, int32_t small_max, int32_t mid_max);
+
 /* *out = 1 if cs_gs_sweeps with a work array runs this grid's sweeps as fused
  * single passes, 0 if it falls back to one launch per colour. */
 cs_status cs_gs_fused(cs_grid g, int32_t* out);

@@ -60,6 +60,13 @@ _SIGS = {
     "cs_ir_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
                                       ctypes.c_void_p]),
     "cs_ir_update": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]),
+    "cs_batch_create": (ctypes.c_int, [ctypes.POINTER(cs_grid_desc), ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+    "cs_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "cs_batch_gs_sweeps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "cs_batch_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cs_batch_tile_policy": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "cs_last_error": (ctypes.c_char_p, []),
 }
 
@@ -155,6 +162,31 @@ def cs_ir_residual(h64, h32, scale, norms_ptr, stream=None):
 
 def cs_ir_update(h64, h32, scale, stream=None):
     _check(lib().cs_ir_update(ctypes.c_void_p(h64), ctypes.c_void_p(h32), float(scale), _stream(stream)))
+
+
+def cs_batch_create(descs, u_ptrs, b_ptrs, tmp_ptrs):
+    n = len(descs)
+    arr = (cs_grid_desc * n)(*descs)
+    vp = ctypes.c_void_p * n
+    out = ctypes.c_void_p()
+    _check(lib().cs_batch_create(arr, vp(*u_ptrs), vp(*b_ptrs), vp(*tmp_ptrs), n, ctypes.byref(out)))
+    return out.value
+
+
+def cs_batch_destroy(handle):
+    _check(lib().cs_batch_destroy(ctypes.c_void_p(handle)))
+
+
+def cs_batch_gs_sweeps(handle, nsweeps, stream=None):
+    _check(lib().cs_batch_gs_sweeps(ctypes.c_void_p(handle), int(nsweeps), _stream(stream)))
+
+
+def cs_batch_residual(handle, norms_ptr, stream=None):
+    _check(lib().cs_batch_residual(ctypes.c_void_p(handle), ctypes.c_void_p(norms_ptr), _stream(stream)))
+
+
+def cs_batch_tile_policy(stencil, small_max, mid_max):
+    _check(lib().cs_batch_tile_policy(int(stencil), int(small_max), int(mid_max)))
 
 
 # --------------------------------------------------------------------------
@@ -264,3 +296,38 @@ class Grid:
         out = self.norms if norms is None else norms
         cs_residual(self.handle, 0 if r is None else r.data_ptr(), out.data_ptr(), stream)
         return out
+
+
+class Batch:
+    """A batch of 3D patches.  patches: list of (u, b, tmp, stencil, h, parity)
+    with caller-owned tensors (tmp with u's layout)."""
+
+    def __init__(self, patches):
+        self.patches = list(patches)
+        descs = [describe(u, dim=3, stencil=st, h=h, parity=par) for (u, b, t, st, h, par) in self.patches]
+        for (u, b, t, st, h, par) in self.patches:
+            if u.shape != b.shape or u.stride() != b.stride() or t.shape != u.shape or t.stride() != u.stride():
+                raise ValueError("u, b and tmp of a patch must share shape and strides")
+        self.handle = cs_batch_create(descs, [p[0].data_ptr() for p in self.patches],
+                                      [p[1].data_ptr() for p in self.patches],
+                                      [p[2].data_ptr() for p in self.patches])
+        self.norms = torch.zeros(len(self.patches), 3, dtype=torch.float64,
+                                 device=self.patches[0][0].device)
+
+    def close(self):
+        if self.handle:
+            cs_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def gs(self, nsweeps, stream=None):
+        cs_batch_gs_sweeps(self.handle, nsweeps, stream)
+
+    def residual(self, stream=None):
+        cs_batch_residual(self.handle, self.norms.data_ptr(), stream)
+        return self.norms

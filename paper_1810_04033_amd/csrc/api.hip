@@ -124,6 +124,17 @@ cs_status check_tmp(const cs_grid_s* g, const void* tmp)
 }
 
 }  // namespace
+
+cs_status check_device_range_pub(const void* p, size_t bytes, size_t align, const char* name)
+{
+    return check_device_range(p, bytes, align, name);
+}
+
+cs_status validate_desc_pub(const cs_grid_desc* d)
+{
+    return validate_desc(d);
+}
+
 }  // namespace cs
 
 using namespace cs;

@@ -1,0 +1,33 @@
+// Internal declarations of the batched-patch kernels (not part of the ABI).
+#pragma once
+
+#include "cs_internal.h"
+
+namespace cs {
+
+// One patch of a batch group, as stored in the group's device table.
+struct BatchPatch {
+    Geo g;
+    void* u;          // iterate (the result ends here)
+    void* tmp;        // work array with u's layout
+    const void* b;    // right-hand side
+    double h2;        // h^2 as the sweeps use it (rounded to FP32 for FP32 patches)
+    double hh;        // h*h in FP64 (residual)
+    int tiles_x, tiles_y, chunks;
+    int index;        // position of the patch in the caller's arrays
+    int64_t item_begin;  // first work item of this patch in the sweep launch
+    int64_t res_begin;   // first row-block item in the residual / copy launches
+    int res_items;
+};
+
+int64_t batch_residual_items(const Geo& g);
+void batch_variant_tile(int stencil, int variant, int* tx, int* ty);
+cs_status launch_batch_sweep(int dtype, int stencil, int variant, const BatchPatch* tab, int count,
+                             int64_t items, int phase, hipStream_t s);
+cs_status launch_batch_halo(int dtype, const BatchPatch* tab, int count, hipStream_t s);
+cs_status launch_batch_copyback(int dtype, const BatchPatch* tab, int count, int64_t res_items,
+                                hipStream_t s);
+cs_status launch_batch_residual(int dtype, int stencil, const BatchPatch* tab, int count,
+                                int64_t res_items, Partial* partials, double* norms, hipStream_t s);
+
+}  // namespace cs

@@ -1,0 +1,399 @@
+// Tile bodies of the fused Gauss-Seidel sweeps: every colour of one sweep in a single pass over
+// memory, reading the previous iterate from `src` and writing the new one to
+// `dst` (both arrays carry the same Dirichlet halo).
+//
+// Red-black, 7-point (colouring of Sec. 3 with c = 2).  Red points depend only
+// on black values of the previous iterate and black points only on the new red
+// values, so a sweep can stream through z: at plane step k the red points of
+// plane k are updated from the old black values of planes k-1..k+1, then the
+// black points of plane k-1 from the new red values of planes k-2..k.  Plane
+// k-1 is then final and is written out.  This is the colour order of the
+// sweep, so the result equals the c in-place colour passes.
+//
+// Each workgroup owns an xy tile T of TX x TY interior points and a chunk of
+// ZC planes.  Neighbouring tiles run independently: a tile recomputes the new
+// red values on the one-point ring T+1 itself (from old values on T+2), which
+// is why the two arrays are needed -- old values are never overwritten during
+// the sweep.  Each thread owns columns of the region T+2 and keeps a window of
+// four planes of its columns in registers (z neighbours), the in-plane
+// neighbours are exchanged through two LDS planes.  Neighbour sums keep the
+// lexicographic offset order of the plain sequential definition, so the
+// values are bit-identical to the colour passes.
+//
+// Workgroups are mapped XCD by XCD: consecutive tile indices (the xy tiles of
+// one z chunk) land on the same XCD so that the tiles' overlapping halo rows
+// are served from that XCD's L2.
+#pragma once
+
+#include "cs_device.h"
+#include "cs_internal.h"
+
+namespace cs {
+
+constexpr int kXcds = 8;
+
+// Logical work index of this workgroup such that the hardware's round-robin
+// placement of workgroups over the XCDs gives each XCD a contiguous range.
+__device__ inline int64_t xcd_ordered_block(int64_t nblocks)
+{
+    const int64_t b = blockIdx.x;
+    const int64_t per = nblocks / kXcds;
+    const int64_t rem = nblocks % kXcds;
+    const int64_t xcd = b % kXcds;
+    const int64_t slot = b / kXcds;
+    // XCDs [0, rem) hold per+1 blocks, the others per blocks
+    const int64_t start = xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per;
+    return start + slot;
+}
+
+// Work split of one grid: tile index (x fastest) and z chunk, planes split
+// evenly over the chunks.
+struct FusedWork {
+    int tiles_x, tiles_y;
+    int chunks;
+    int64_t nblocks;
+};
+
+// The interior box a workgroup finalises: x from x0, y from y0 (tile T) and
+// planes [z0, z1).
+struct TileBox {
+    int64_t x0, y0, z0, z1;
+};
+
+template <int TX, int TY>
+__device__ inline TileBox tile_box(const Geo& g, int tiles_x, int tiles_y, int chunks, int64_t work)
+{
+    const int64_t tiles = (int64_t)tiles_x * tiles_y;
+    const int64_t chunk = work / tiles;
+    const int64_t tile = work % tiles;
+    TileBox t;
+    t.x0 = 1 + (tile % tiles_x) * TX;
+    t.y0 = 1 + (tile / tiles_x) * TY;
+    t.z0 = 1 + (chunk * g.nz) / chunks;
+    t.z1 = 1 + ((chunk + 1) * g.nz) / chunks;
+    return t;
+}
+
+template <typename T, int TX, int TY, int NT, int D>
+struct FdCfg {
+    static constexpr int W = TX + 4;           // region T+2, x extent
+    static constexpr int HH = TY + 4;          // region T+2, y extent
+    static constexpr int NCOL = W * HH;
+    static constexpr int M = (NCOL + NT - 1) / NT;  // columns per thread
+    // register planes k-2 .. k+1 in use plus D planes in flight
+    static constexpr int RING = 4 + D;
+};
+
+// One red-black sweep of the 7-point stencil over the box tb, src -> dst.
+template <typename T, int TX, int TY, int NT, int D>
+__device__ __forceinline__ void fd3_tile(const T* __restrict__ src, T* __restrict__ dst,
+                                         const T* __restrict__ b, const Geo& g, T h2,
+                                         const TileBox& tb)
+{
+    using C = FdCfg<T, TX, TY, NT, D>;
+    constexpr int W = C::W, M = C::M, NCOL = C::NCOL, R = C::RING;
+    // two LDS buffer sets (planes k and k-1), alternating with the step parity,
+    // so one barrier per plane step suffices
+    __shared__ T lds[2][2][NCOL];
+    const int64_t x0 = tb.x0, y0 = tb.y0, z0 = tb.z0, z1 = tb.z1;
+    const int tid = threadIdx.x;
+
+    int off[M];   // y*sy + x of the column (32-bit: checked on the host)
+    int flags[M]; // bit0 valid, bit1 interior in T+1, bit2 interior in T, bit3 colour parity
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int c = tid + NT * m;
+        const int ly = c / W, lx = c % W;
+        const int64_t x = x0 - 2 + lx, y = y0 - 2 + ly;
+        const bool valid = c < NCOL && x >= 0 && x <= g.nx + 1 && y >= 0 && y <= g.ny + 1;
+        const bool interior = valid && x >= 1 && x <= g.nx && y >= 1 && y <= g.ny;
+        const bool t1 = interior && lx >= 1 && lx <= TX + 2 && ly >= 1 && ly <= TY + 2;
+        const bool t0 = interior && lx >= 2 && lx <= TX + 1 && ly >= 2 && ly <= TY + 1;
+        const int par = (int)(((x - 1) + (y - 1) + g.parity) & 1);
+        flags[m] = (valid ? 1 : 0) | (t1 ? 2 : 0) | (t0 ? 4 : 0) | (par << 3);
+        off[m] = valid ? (int)(y * g.sy + x) : 0;
+    }
+
+    // register rings: the slot of plane p is (p - z0 + 3) mod R for u and b
+    T U[R][M];
+    T B[R][M];
+    auto load_u = [&](int64_t k, T* v) {
+        const bool kin = k >= 0 && k <= g.nz + 1;
+        const T* sp = src + (kin ? k : 0) * g.sz;
+#pragma unroll
+        for (int m = 0; m < M; ++m) v[m] = (kin && (flags[m] & 1)) ? sp[off[m]] : T(0);
+    };
+    auto load_b = [&](int64_t k, T* v) {
+        const bool kin = k >= 1 && k <= g.nz;
+        const T* bp = b + (kin ? k : 0) * g.sz;
+#pragma unroll
+        for (int m = 0; m < M; ++m) v[m] = (kin && (flags[m] & 2)) ? bp[off[m]] : T(0);
+    };
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        U[0][m] = T(0);
+        B[1][m] = T(0);
+    }
+#pragma unroll
+    for (int d = 0; d < D + 2; ++d) load_u(z0 - 2 + d, U[1 + d]);  // planes z0-2 .. z0-1+D
+#pragma unroll
+    for (int d = 0; d < D; ++d) load_b(z0 - 1 + d, B[2 + d]);      // b of z0-1 .. z0-2+D
+
+    for (int64_t kb = z0 - 1; kb <= z1; kb += R) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t k = kb + r;
+            if (k > z1) break;
+            T* u_km2 = U[r % R];
+            T* u_km1 = U[(r + 1) % R];
+            T* u_k = U[(r + 2) % R];
+            T* u_kp1 = U[(r + 3) % R];
+            T* b_km1 = B[(r + 1) % R];
+            T* b_k = B[(r + 2) % R];
+            // prefetch plane k+1+D and b of plane k+D (used D steps later)
+            if (k + 1 + D <= z1 + 1) load_u(k + 1 + D, U[(r + 3 + D) % R]);
+            if (k + D <= z1) load_b(k + D, B[(r + 2 + D) % R]);
+            T* lk = lds[k & 1][0];
+            T* lkm1 = lds[k & 1][1];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int c = tid + NT * m;
+                if (c < NCOL) {
+                    lk[c] = u_k[m];
+                    lkm1[c] = u_km1[m];
+                }
+            }
+            __syncthreads();
+            const bool do_red = k >= 1 && k <= g.nz;
+            const bool do_black = k - 1 >= z0 && k - 1 < z1;
+            const int kc = (int)((k - 1) & 1);
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int c = tid + NT * m;
+                const bool sel = (((flags[m] >> 3) + kc) & 1) == 0;
+                if (do_red && (flags[m] & 2) && sel) {
+                    const T zm = u_km1[m], zp = u_kp1[m];
+                    auto ld = [&](int ox, int oy, int oz) -> T {
+                        return oz < 0 ? zm : oz > 0 ? zp : lk[c + oy * W + ox];
+                    };
+                    u_k[m] = gs_value<T, 3, FD>(h2, b_k[m], ld);
+                }
+            }
+            T* dp = dst + (k - 1) * g.sz;
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int c = tid + NT * m;
+                const bool sel = (((flags[m] >> 3) + kc) & 1) == 0;
+                // (x, y, k-1) is black exactly when (x, y, k) is red
+                if (do_black && (flags[m] & 4) && sel) {
+                    const T zm = u_km2[m], zp = u_k[m];
+                    auto ld = [&](int ox, int oy, int oz) -> T {
+                        return oz < 0 ? zm : oz > 0 ? zp : lkm1[c + oy * W + ox];
+                    };
+                    u_km1[m] = gs_value<T, 3, FD>(h2, b_km1[m], ld);
+                }
+                if (do_black && (flags[m] & 4)) dp[off[m]] = u_km1[m];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 8-colour sweep of the 27-point trilinear stencil.
+//
+// Colour = px + 2 py + 4 pz (parities of x, y, z).  The face weights of this
+// stencil are zero, so two colours that differ only in px never read each
+// other: colours {0,1} (py = 0, pz = 0), {2,3}, {4,5}, {6,7} are four row
+// phases A, B, C, D, each one a set of whole x-rows, and running a pair at
+// once equals running its two colours one after the other.  A and B live on
+// "even" planes (pz = 0), C and D on "odd" planes (pz = 1).  A reads only
+// values of the previous iterate; B reads the new A rows of its plane; C and D
+// read the final values of both neighbouring even planes, and D also the new C
+// rows.  The sweep therefore streams through z in double steps: even plane e
+// (A then B), then odd plane e-1 (C then D), after which planes e-1 and e are
+// final.  A tile needs a recomputed halo of 4 (A on T+3, B on T+2, C on T+1,
+// D on T).  Four planes (e-2 .. e+1) of the region T+4 live in LDS; the next
+// two planes are prefetched into registers.  Neighbour sums keep the
+// lexicographic offset order, so values equal the eight colour passes bit
+// for bit.
+// ---------------------------------------------------------------------------
+template <int TX, int TY, int NT, int HALO>
+struct Q1Phase {
+    static constexpr int W = TX + 8;
+    static constexpr int COLS = TX + 2 * HALO;
+    static constexpr int ROWS = (TY + 2 * HALO + 1) / 2;  // rows of one type, at most
+    static constexpr int P = (ROWS * COLS + NT - 1) / NT;  // points per thread, at most
+};
+
+// The points of one phase owned by a thread: rows of type rho inside T+halo.
+template <int TX, int TY, int NT, int HALO, int P>
+__device__ __forceinline__ void q1_make_pts(const Geo& g, int64_t x0, int64_t y0, int rho,
+                                            int* pc, int* poff, bool* pout)
+{
+    constexpr int W = TX + 8;
+    constexpr int COLS = TX + 2 * HALO;
+    const int ly_lo = 4 - HALO;
+    const int rt_lo = (int)((y0 - 4 + ly_lo - 1 + g.parity) & 1);
+    const int first = ly_lo + ((rho - rt_lo) & 1);
+    const int nrows = (TY + 2 * HALO - (first - ly_lo) + 1) / 2;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const int sidx = (int)threadIdx.x + NT * i;
+        const int row = sidx / COLS, col = sidx % COLS;
+        const int ly = first + 2 * row, lx = 4 - HALO + col;
+        const int64_t x = x0 - 4 + lx, y = y0 - 4 + ly;
+        const bool ok = row < nrows && x >= 1 && x <= g.nx && y >= 1 && y <= g.ny;
+        pc[i] = ok ? ly * W + lx : -1;
+        poff[i] = ok ? (int)(y * g.sy + x) : 0;
+        pout[i] = ok && lx >= 4 && lx < 4 + TX && ly >= 4 && ly < 4 + TY;
+    }
+}
+
+template <typename T, int P>
+__device__ __forceinline__ void q1_load_b(const T* __restrict__ b, const Geo& g, int64_t k,
+                                          const int* pc, const int* poff, T* v)
+{
+    const bool kin = k >= 1 && k <= g.nz;
+    const T* bp = b + (kin ? k : 0) * g.sz;
+#pragma unroll
+    for (int i = 0; i < P; ++i) v[i] = (kin && pc[i] >= 0) ? bp[poff[i]] : T(0);
+}
+
+// One phase: update the listed points in place in plane slot lk (z neighbours
+// in lm and lp), writing the ones inside T to dst when `write`.
+template <typename T, int W, int P>
+__device__ __forceinline__ void q1_phase(bool active, const int* pc, const int* poff,
+                                         const bool* pout, const T* bv, const T* lm, T* lk,
+                                         const T* lp, T h2, T* dp, bool write)
+{
+    if (!active) return;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const int c = pc[i];
+        if (c < 0) continue;
+        auto ld = [&](int ox, int oy, int oz) -> T {
+            const T* pl = oz < 0 ? lm : (oz > 0 ? lp : lk);
+            return pl[c + oy * W + ox];
+        };
+        const T v = gs_value<T, 3, Q1>(h2, bv[i], ld);
+        lk[c] = v;
+        if (write && pout[i]) dp[poff[i]] = v;
+    }
+}
+
+
+// One 8-colour sweep of the 27-point stencil over the box tb, src -> dst.
+template <typename T, int TX, int TY, int NT>
+__device__ __forceinline__ void q1_3_tile(const T* __restrict__ src, T* __restrict__ dst,
+                                          const T* __restrict__ b, const Geo& g, T h2,
+                                          const TileBox& tb)
+{
+    constexpr int W = TX + 8, HH = TY + 8, NCOL = W * HH;
+    constexpr int M = (NCOL + NT - 1) / NT;
+    using PA = Q1Phase<TX, TY, NT, 3>;
+    using PB = Q1Phase<TX, TY, NT, 2>;
+    using PC = Q1Phase<TX, TY, NT, 1>;
+    using PD = Q1Phase<TX, TY, NT, 0>;
+    __shared__ T L[4][NCOL];
+    const int64_t x0 = tb.x0, y0 = tb.y0, z0 = tb.z0, z1 = tb.z1;
+    const int tid = threadIdx.x;
+    const int par = g.parity;
+
+    // columns of the region T+4 (plane loads into LDS)
+    int coff[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int c = tid + NT * m;
+        const int ly = c / W, lx = c % W;
+        const int64_t x = x0 - 4 + lx, y = y0 - 4 + ly;
+        const bool ok = c < NCOL && x >= 0 && x <= g.nx + 1 && y >= 0 && y <= g.ny + 1;
+        coff[m] = ok ? (int)(y * g.sy + x) : -1;
+    }
+    int ca[PA::P], oa[PA::P], cb[PB::P], ob[PB::P], cc[PC::P], oc[PC::P], cd[PD::P], od[PD::P];
+    bool wa[PA::P], wb[PB::P], wc[PC::P], wd[PD::P];
+    q1_make_pts<TX, TY, NT, 3, PA::P>(g, x0, y0, 0, ca, oa, wa);
+    q1_make_pts<TX, TY, NT, 2, PB::P>(g, x0, y0, 1, cb, ob, wb);
+    q1_make_pts<TX, TY, NT, 1, PC::P>(g, x0, y0, 0, cc, oc, wc);
+    q1_make_pts<TX, TY, NT, 0, PD::P>(g, x0, y0, 1, cd, od, wd);
+
+    auto is_even = [&](int64_t k) { return ((k - 1 + par) & 1) == 0; };
+    const int64_t e_first = is_even(z0 - 1) ? z0 - 1 : z0;
+    const int64_t e_last = is_even(z1) ? z1 : z1 - 1;
+
+    auto load_plane = [&](int64_t k, T* v) {
+        const bool kin = k >= 0 && k <= g.nz + 1;
+        const T* sp = src + (kin ? k : 0) * g.sz;
+#pragma unroll
+        for (int m = 0; m < M; ++m) v[m] = (kin && coff[m] >= 0) ? sp[coff[m]] : T(0);
+    };
+    auto store_plane = [&](const T* v, T* lp) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int c = tid + NT * m;
+            if (c < NCOL) lp[c] = v[m];
+        }
+    };
+
+    // prefetched planes e, e+1 and the b values of the next double step; each
+    // double step is long (five barriers), so the prefetch has completed by the
+    // time the values move into place
+    T n0[M], n1[M];
+    T ba[PA::P], bb[PB::P], bc[PC::P], bd[PD::P];
+    {
+        T t[M];
+        load_plane(e_first - 1, t);
+        store_plane(t, L[(e_first - 1) & 3]);
+    }
+    load_plane(e_first, n0);
+    load_plane(e_first + 1, n1);
+    q1_load_b<T, PA::P>(b, g, e_first, ca, oa, ba);
+    q1_load_b<T, PB::P>(b, g, e_first, cb, ob, bb);
+    q1_load_b<T, PC::P>(b, g, e_first - 1, cc, oc, bc);
+    q1_load_b<T, PD::P>(b, g, e_first - 1, cd, od, bd);
+
+    for (int64_t e = e_first; e <= e_last; e += 2) {
+        T* lm2 = L[(e - 2) & 3];
+        T* lm1 = L[(e - 1) & 3];
+        T* l0 = L[e & 3];
+        T* lp1 = L[(e + 1) & 3];
+        store_plane(n0, l0);
+        store_plane(n1, lp1);
+        T ba_n[PA::P], bb_n[PB::P], bc_n[PC::P], bd_n[PD::P];
+        const bool more = e + 2 <= e_last;
+        if (more) {
+            load_plane(e + 2, n0);
+            load_plane(e + 3, n1);
+            q1_load_b<T, PA::P>(b, g, e + 2, ca, oa, ba_n);
+            q1_load_b<T, PB::P>(b, g, e + 2, cb, ob, bb_n);
+            q1_load_b<T, PC::P>(b, g, e + 1, cc, oc, bc_n);
+            q1_load_b<T, PD::P>(b, g, e + 1, cd, od, bd_n);
+        }
+        __syncthreads();
+        const bool ab = e >= 1 && e <= g.nz;
+        const bool wr_e = e >= z0 && e < z1;
+        T* dpe = dst + (ab ? e : 0) * g.sz;
+        q1_phase<T, W, PA::P>(ab, ca, oa, wa, ba, lm1, l0, lp1, h2, dpe, wr_e);
+        __syncthreads();
+        q1_phase<T, W, PB::P>(ab, cb, ob, wb, bb, lm1, l0, lp1, h2, dpe, wr_e);
+        __syncthreads();
+        const int64_t o = e - 1;
+        const bool cdo = o >= z0 && o < z1 && o >= 1 && o <= g.nz;
+        T* dpo = dst + (cdo ? o : 0) * g.sz;
+        q1_phase<T, W, PC::P>(cdo, cc, oc, wc, bc, lm2, lm1, l0, h2, dpo, true);
+        __syncthreads();
+        q1_phase<T, W, PD::P>(cdo, cd, od, wd, bd, lm2, lm1, l0, h2, dpo, true);
+        __syncthreads();
+        if (more) {
+#pragma unroll
+            for (int i = 0; i < PA::P; ++i) ba[i] = ba_n[i];
+#pragma unroll
+            for (int i = 0; i < PB::P; ++i) bb[i] = bb_n[i];
+#pragma unroll
+            for (int i = 0; i < PC::P; ++i) bc[i] = bc_n[i];
+#pragma unroll
+            for (int i = 0; i < PD::P; ++i) bd[i] = bd_n[i];
+        }
+    }
+}
+
+}  // namespace cs

@@ -1,0 +1,294 @@
+// Batched patches: many independent Dirichlet patches of block-structured
+// meshes (Sec. 1 and Sec. 2: regular patches of adaptive meshes) swept by one
+// launch per sweep for all patches of a group.
+//
+// A group holds patches of one stencil, element type and tile variant.  Its
+// device table lists every patch's geometry, arrays and the first index of
+// its work items; a workgroup finds its patch by binary search over those
+// prefixes (the table read is uniform across the workgroup) and then runs the
+// same tile body as the single-grid fused kernels.  Patches are sorted by size,
+// largest first, so the hardware dispatcher hands out the longest work first.
+// The sweeps ping-pong between each patch's u and its work array tmp.
+//
+// Per-patch residual norms come from a fixed decomposition of each patch into
+// row blocks (it depends on the patch's own shape only) and a per-patch
+// finisher that folds its partials in order, so a patch's norms do not depend
+// on which other patches share the batch.
+#include "cs_tiles.h"
+
+#include "cs_batch.h"
+
+namespace cs {
+
+namespace {
+
+__device__ inline int find_patch(const BatchPatch* __restrict__ tab, int count, int64_t w,
+                                 bool residual)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int64_t beg = residual ? tab[mid].res_begin : tab[mid].item_begin;
+        if (beg <= w)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T, int TX, int TY, int NT, int D>
+__global__ void __launch_bounds__(NT)
+k_batch_fd3(const BatchPatch* __restrict__ tab, int count, int phase)
+{
+    const int64_t w = blockIdx.x;
+    const int p = find_patch(tab, count, w, false);
+    const BatchPatch P = tab[p];
+    const TileBox tb = tile_box<TX, TY>(P.g, P.tiles_x, P.tiles_y, P.chunks, w - P.item_begin);
+    const T* src = (const T*)(phase ? P.tmp : P.u);
+    T* dst = (T*)(phase ? P.u : P.tmp);
+    fd3_tile<T, TX, TY, NT, D>(src, dst, (const T*)P.b, P.g, (T)P.h2, tb);
+}
+
+template <typename T, int TX, int TY, int NT, int WPE>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_batch_q1_3(const BatchPatch* __restrict__ tab, int count, int phase)
+{
+    const int64_t w = blockIdx.x;
+    const int p = find_patch(tab, count, w, false);
+    const BatchPatch P = tab[p];
+    const TileBox tb = tile_box<TX, TY>(P.g, P.tiles_x, P.tiles_y, P.chunks, w - P.item_begin);
+    const T* src = (const T*)(phase ? P.tmp : P.u);
+    T* dst = (T*)(phase ? P.u : P.tmp);
+    q1_3_tile<T, TX, TY, NT>(src, dst, (const T*)P.b, P.g, (T)P.h2, tb);
+}
+
+// Halo copy u -> tmp, one workgroup per patch.
+template <typename T>
+__global__ void __launch_bounds__(256) k_batch_halo(const BatchPatch* __restrict__ tab)
+{
+    const BatchPatch P = tab[blockIdx.x];
+    const Geo& g = P.g;
+    const T* src = (const T*)P.u;
+    T* dst = (T*)P.tmp;
+    const int64_t wx = g.nx + 2, plane = wx * (g.ny + 2);
+    const int64_t per = 2 * wx + 2 * g.ny;
+    const int64_t total = 2 * plane + g.nz * per;
+    for (int64_t t = threadIdx.x; t < total; t += 256) {
+        int64_t i, j, k, r = t;
+        if (r < 2 * plane) {
+            k = r < plane ? 0 : g.nz + 1;
+            r %= plane;
+            j = r / wx;
+            i = r % wx;
+        } else {
+            r -= 2 * plane;
+            k = 1 + r / per;
+            r %= per;
+            if (r < 2 * wx) {
+                j = r < wx ? 0 : g.ny + 1;
+                i = r % wx;
+            } else {
+                r -= 2 * wx;
+                j = 1 + r / 2;
+                i = (r & 1) ? g.nx + 1 : 0;
+            }
+        }
+        const int64_t q = k * g.sz + j * g.sy + i;
+        dst[q] = src[q];
+    }
+}
+
+constexpr int kRowsPerItem = 16;
+
+// Row-block items (residual and copy-back): item covers kRowsPerItem rows
+// (j, k) of the patch interior; 256 threads = 64 along x x 4 rows.
+template <typename T>
+__global__ void __launch_bounds__(256) k_batch_copyback(const BatchPatch* __restrict__ tab, int count)
+{
+    const int64_t w = blockIdx.x;
+    const int p = find_patch(tab, count, w, true);
+    const BatchPatch P = tab[p];
+    const Geo& g = P.g;
+    const int64_t item = w - P.res_begin;
+    const int64_t rows = g.ny * g.nz;
+    const T* src = (const T*)P.tmp;
+    T* dst = (T*)P.u;
+    for (int rr = threadIdx.y; rr < kRowsPerItem; rr += 4) {
+        const int64_t row = item * kRowsPerItem + rr;
+        if (row >= rows) break;
+        const int64_t j = 1 + row % g.ny, k = 1 + row / g.ny;
+        for (int64_t i = 1 + threadIdx.x; i <= g.nx; i += 64) {
+            const int64_t q = k * g.sz + j * g.sy + i;
+            dst[q] = src[q];
+        }
+    }
+}
+
+template <typename S, int ST>
+__global__ void __launch_bounds__(256)
+k_batch_residual(const BatchPatch* __restrict__ tab, int count, Partial* __restrict__ partials)
+{
+    __shared__ double sh[3 * 256];
+    const int64_t w = blockIdx.x;
+    const int p = find_patch(tab, count, w, true);
+    const BatchPatch P = tab[p];
+    const Geo& g = P.g;
+    const int64_t item = w - P.res_begin;
+    const int64_t rows = g.ny * g.nz;
+    const S* u = (const S*)P.u;
+    const S* b = (const S*)P.b;
+    const int64_t sy = g.sy, sz = g.sz;
+    double s_r2 = 0.0, mx = 0.0, s_b2 = 0.0;
+    for (int rr = threadIdx.y; rr < kRowsPerItem; rr += 4) {
+        const int64_t row = item * kRowsPerItem + rr;
+        if (row >= rows) break;
+        const int64_t j = 1 + row % g.ny, k = 1 + row / g.ny;
+        for (int64_t i = 1 + threadIdx.x; i <= g.nx; i += 64) {
+            const int64_t q = k * g.sz + j * g.sy + i;
+            auto ld = [&](int ox, int oy, int oz) { return (double)u[q + oz * sz + oy * sy + ox]; };
+            const double su = ordered_sum<double, 3, ST, true>(ld);
+            const double bq = (double)b[q];
+            const double rq = bq - su / P.hh;
+            s_r2 += rq * rq;
+            s_b2 += bq * bq;
+            mx = fmax(mx, fabs(rq));
+        }
+    }
+    const int t = threadIdx.y * 64 + threadIdx.x;
+    sh[t] = s_r2;
+    sh[256 + t] = mx;
+    sh[512 + t] = s_b2;
+    __syncthreads();
+    for (int wdt = 128; wdt > 0; wdt >>= 1) {
+        if (t < wdt) {
+            sh[t] = sh[t] + sh[t + wdt];
+            sh[256 + t] = fmax(sh[256 + t], sh[256 + t + wdt]);
+            sh[512 + t] = sh[512 + t] + sh[512 + t + wdt];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        partials[w].sum_r2 = sh[0];
+        partials[w].max_r = sh[256];
+        partials[w].sum_b2 = sh[512];
+    }
+}
+
+// One workgroup per patch folds the patch's partials in order.
+__global__ void __launch_bounds__(64)
+k_batch_finish(const BatchPatch* __restrict__ tab, const Partial* __restrict__ partials,
+               double* __restrict__ norms)
+{
+    const BatchPatch P = tab[blockIdx.x];
+    if (threadIdx.x != 0) return;
+    double a = 0.0, m = 0.0, c = 0.0;
+    for (int i = 0; i < P.res_items; ++i) {
+        const Partial q = partials[P.res_begin + i];
+        a += q.sum_r2;
+        m = fmax(m, q.max_r);
+        c += q.sum_b2;
+    }
+    norms[3 * P.index + 0] = sqrt(a);
+    norms[3 * P.index + 1] = m;
+    norms[3 * P.index + 2] = sqrt(c);
+}
+
+}  // namespace
+
+int64_t batch_residual_items(const Geo& g)
+{
+    return (g.ny * g.nz + kRowsPerItem - 1) / kRowsPerItem;
+}
+
+// Tile of each variant: (TX, TY) used to count a patch's work items.
+void batch_variant_tile(int stencil, int variant, int* tx, int* ty)
+{
+    static const int fd[3][2] = {{16, 16}, {32, 16}, {64, 16}};
+    static const int q1[3][2] = {{16, 8}, {32, 16}, {64, 16}};
+    const int v = variant < 0 ? 0 : (variant > 2 ? 2 : variant);
+    *tx = stencil == FD ? fd[v][0] : q1[v][0];
+    *ty = stencil == FD ? fd[v][1] : q1[v][1];
+}
+
+cs_status launch_batch_sweep(int dtype, int stencil, int variant, const BatchPatch* tab, int count,
+                             int64_t items, int phase, hipStream_t s)
+{
+    if (items <= 0) return CS_OK;
+    const dim3 grid((unsigned)items);
+#define CS_BFD(T, TX, TY, NT, D) \
+    hipLaunchKernelGGL((k_batch_fd3<T, TX, TY, NT, D>), grid, dim3(NT), 0, s, tab, count, phase)
+#define CS_BQ1(T, TX, TY, NT, WPE) \
+    hipLaunchKernelGGL((k_batch_q1_3<T, TX, TY, NT, WPE>), grid, dim3(NT), 0, s, tab, count, phase)
+    if (stencil == FD) {
+        if (dtype == 0) {
+            if (variant == 0) CS_BFD(double, 16, 16, 256, 1);
+            else if (variant == 1) CS_BFD(double, 32, 16, 256, 1);
+            else CS_BFD(double, 64, 16, 512, 1);
+        } else {
+            if (variant == 0) CS_BFD(float, 16, 16, 256, 1);
+            else if (variant == 1) CS_BFD(float, 32, 16, 256, 1);
+            else CS_BFD(float, 64, 16, 512, 1);
+        }
+    } else {
+        if (dtype == 0) {
+            if (variant == 0) CS_BQ1(double, 16, 8, 256, 3);
+            else if (variant == 1) CS_BQ1(double, 32, 16, 512, 3);
+            else CS_BQ1(double, 64, 16, 512, 3);
+        } else {
+            if (variant == 0) CS_BQ1(float, 16, 8, 256, 3);
+            else if (variant == 1) CS_BQ1(float, 32, 16, 512, 3);
+            else CS_BQ1(float, 64, 16, 512, 3);
+        }
+    }
+#undef CS_BFD
+#undef CS_BQ1
+    return check_launch("batched sweep");
+}
+
+cs_status launch_batch_halo(int dtype, const BatchPatch* tab, int count, hipStream_t s)
+{
+    if (count <= 0) return CS_OK;
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_batch_halo<double>, dim3(count), dim3(256), 0, s, tab);
+    else
+        hipLaunchKernelGGL(k_batch_halo<float>, dim3(count), dim3(256), 0, s, tab);
+    return check_launch("batched halo copy");
+}
+
+cs_status launch_batch_copyback(int dtype, const BatchPatch* tab, int count, int64_t res_items,
+                                hipStream_t s)
+{
+    if (res_items <= 0) return CS_OK;
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_batch_copyback<double>, dim3((unsigned)res_items), dim3(64, 4), 0, s,
+                           tab, count);
+    else
+        hipLaunchKernelGGL(k_batch_copyback<float>, dim3((unsigned)res_items), dim3(64, 4), 0, s,
+                           tab, count);
+    return check_launch("batched copy back");
+}
+
+cs_status launch_batch_residual(int dtype, int stencil, const BatchPatch* tab, int count,
+                                int64_t res_items, Partial* partials, double* norms, hipStream_t s)
+{
+    if (res_items <= 0) return CS_OK;
+    const dim3 grid((unsigned)res_items), blk(64, 4);
+    if (dtype == 0) {
+        if (stencil == FD)
+            hipLaunchKernelGGL((k_batch_residual<double, FD>), grid, blk, 0, s, tab, count, partials);
+        else
+            hipLaunchKernelGGL((k_batch_residual<double, Q1>), grid, blk, 0, s, tab, count, partials);
+    } else {
+        if (stencil == FD)
+            hipLaunchKernelGGL((k_batch_residual<float, FD>), grid, blk, 0, s, tab, count, partials);
+        else
+            hipLaunchKernelGGL((k_batch_residual<float, Q1>), grid, blk, 0, s, tab, count, partials);
+    }
+    cs_status st = check_launch("batched residual");
+    if (st != CS_OK) return st;
+    hipLaunchKernelGGL(k_batch_finish, dim3(count), dim3(64), 0, s, tab, partials, norms);
+    return check_launch("batched residual finish");
+}
+
+}  // namespace cs

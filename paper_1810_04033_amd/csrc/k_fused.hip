@@ -23,8 +23,7 @@
 // Workgroups are mapped XCD by XCD: consecutive tile indices (the xy tiles of
 // one z chunk) land on the same XCD so that the tiles' overlapping halo rows
 // are served from that XCD's L2.
-#include "cs_device.h"
-#include "cs_internal.h"
+#include "cs_tiles.h"
 
 #include <stdlib.h>
 
@@ -32,281 +31,14 @@ namespace cs {
 
 namespace {
 
-constexpr int kXcds = 8;
-
-// Logical work index of this workgroup such that the hardware's round-robin
-// placement of workgroups over the XCDs gives each XCD a contiguous range.
-__device__ inline int64_t xcd_ordered_block(int64_t nblocks)
-{
-    const int64_t b = blockIdx.x;
-    const int64_t per = nblocks / kXcds;
-    const int64_t rem = nblocks % kXcds;
-    const int64_t xcd = b % kXcds;
-    const int64_t slot = b / kXcds;
-    // XCDs [0, rem) hold per+1 blocks, the others per blocks
-    const int64_t start = xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per;
-    return start + slot;
-}
-
 template <typename T, int TX, int TY, int NT, int D>
-struct FdCfg {
-    static constexpr int W = TX + 4;           // region T+2, x extent
-    static constexpr int HH = TY + 4;          // region T+2, y extent
-    static constexpr int NCOL = W * HH;
-    static constexpr int M = (NCOL + NT - 1) / NT;  // columns per thread
-    // register planes k-2 .. k+1 in use plus D planes in flight
-    static constexpr int RING = 4 + D;
-};
-
-// Work split: tile index (x fastest) and z chunk, planes split evenly.
-struct FusedWork {
-    int tiles_x, tiles_y;
-    int chunks;
-    int64_t nblocks;
-};
-
-template <typename T, int TX, int TY, int NT, int D, bool NTS, bool NTB>
 __global__ void __launch_bounds__(NT)
 k_fused_fd3(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict__ b, Geo g,
             T h2, FusedWork wk)
 {
-    using C = FdCfg<T, TX, TY, NT, D>;
-    constexpr int W = C::W, M = C::M, NCOL = C::NCOL, R = C::RING;
-    // two LDS buffer sets (planes k and k-1), alternating with the step parity,
-    // so one barrier per plane step suffices
-    __shared__ T lds[2][2][NCOL];
-
-    const int64_t work = xcd_ordered_block(wk.nblocks);
-    const int64_t tiles = (int64_t)wk.tiles_x * wk.tiles_y;
-    const int64_t chunk = work / tiles;
-    const int64_t tile = work % tiles;
-    const int64_t x0 = 1 + (tile % wk.tiles_x) * TX;
-    const int64_t y0 = 1 + (tile / wk.tiles_x) * TY;
-    const int64_t z0 = 1 + (chunk * g.nz) / wk.chunks;
-    const int64_t z1 = 1 + ((chunk + 1) * g.nz) / wk.chunks;  // final planes [z0, z1)
-    const int tid = threadIdx.x;
-
-    int off[M];   // y*sy + x of the column (32-bit: checked on the host)
-    int flags[M]; // bit0 valid, bit1 interior in T+1, bit2 interior in T, bit3 colour parity
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-        const int c = tid + NT * m;
-        const int ly = c / W, lx = c % W;
-        const int64_t x = x0 - 2 + lx, y = y0 - 2 + ly;
-        const bool valid = c < NCOL && x >= 0 && x <= g.nx + 1 && y >= 0 && y <= g.ny + 1;
-        const bool interior = valid && x >= 1 && x <= g.nx && y >= 1 && y <= g.ny;
-        const bool t1 = interior && lx >= 1 && lx <= TX + 2 && ly >= 1 && ly <= TY + 2;
-        const bool t0 = interior && lx >= 2 && lx <= TX + 1 && ly >= 2 && ly <= TY + 1;
-        const int par = (int)(((x - 1) + (y - 1) + g.parity) & 1);
-        flags[m] = (valid ? 1 : 0) | (t1 ? 2 : 0) | (t0 ? 4 : 0) | (par << 3);
-        off[m] = valid ? (int)(y * g.sy + x) : 0;
-    }
-
-    // register rings: the slot of plane p is (p - z0 + 3) mod R for u and b
-    T U[R][M];
-    T B[R][M];
-    auto load_u = [&](int64_t k, T* v) {
-        const bool kin = k >= 0 && k <= g.nz + 1;
-        const T* sp = src + (kin ? k : 0) * g.sz;
-#pragma unroll
-        for (int m = 0; m < M; ++m) v[m] = (kin && (flags[m] & 1)) ? sp[off[m]] : T(0);
-    };
-    auto load_b = [&](int64_t k, T* v) {
-        const bool kin = k >= 1 && k <= g.nz;
-        const T* bp = b + (kin ? k : 0) * g.sz;
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-            if (NTB)
-                v[m] = (kin && (flags[m] & 2)) ? __builtin_nontemporal_load(bp + off[m]) : T(0);
-            else
-                v[m] = (kin && (flags[m] & 2)) ? bp[off[m]] : T(0);
-        }
-    };
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-        U[0][m] = T(0);
-        B[1][m] = T(0);
-    }
-#pragma unroll
-    for (int d = 0; d < D + 2; ++d) load_u(z0 - 2 + d, U[1 + d]);  // planes z0-2 .. z0-1+D
-#pragma unroll
-    for (int d = 0; d < D; ++d) load_b(z0 - 1 + d, B[2 + d]);      // b of z0-1 .. z0-2+D
-
-    for (int64_t kb = z0 - 1; kb <= z1; kb += R) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int64_t k = kb + r;
-            if (k > z1) break;
-            T* u_km2 = U[r % R];
-            T* u_km1 = U[(r + 1) % R];
-            T* u_k = U[(r + 2) % R];
-            T* u_kp1 = U[(r + 3) % R];
-            T* b_km1 = B[(r + 1) % R];
-            T* b_k = B[(r + 2) % R];
-            // prefetch plane k+1+D and b of plane k+D (used D steps later)
-            if (k + 1 + D <= z1 + 1) load_u(k + 1 + D, U[(r + 3 + D) % R]);
-            if (k + D <= z1) load_b(k + D, B[(r + 2 + D) % R]);
-            T* lk = lds[k & 1][0];
-            T* lkm1 = lds[k & 1][1];
-#pragma unroll
-            for (int m = 0; m < M; ++m) {
-                const int c = tid + NT * m;
-                if (c < NCOL) {
-                    lk[c] = u_k[m];
-                    lkm1[c] = u_km1[m];
-                }
-            }
-            __syncthreads();
-            const bool do_red = k >= 1 && k <= g.nz;
-            const bool do_black = k - 1 >= z0 && k - 1 < z1;
-            const int kc = (int)((k - 1) & 1);
-#pragma unroll
-            for (int m = 0; m < M; ++m) {
-                const int c = tid + NT * m;
-                const bool sel = (((flags[m] >> 3) + kc) & 1) == 0;
-                if (do_red && (flags[m] & 2) && sel) {
-                    const T zm = u_km1[m], zp = u_kp1[m];
-                    auto ld = [&](int ox, int oy, int oz) -> T {
-                        return oz < 0 ? zm : oz > 0 ? zp : lk[c + oy * W + ox];
-                    };
-                    u_k[m] = gs_value<T, 3, FD>(h2, b_k[m], ld);
-                }
-            }
-            T* dp = dst + (k - 1) * g.sz;
-#pragma unroll
-            for (int m = 0; m < M; ++m) {
-                const int c = tid + NT * m;
-                const bool sel = (((flags[m] >> 3) + kc) & 1) == 0;
-                // (x, y, k-1) is black exactly when (x, y, k) is red
-                if (do_black && (flags[m] & 4) && sel) {
-                    const T zm = u_km2[m], zp = u_k[m];
-                    auto ld = [&](int ox, int oy, int oz) -> T {
-                        return oz < 0 ? zm : oz > 0 ? zp : lkm1[c + oy * W + ox];
-                    };
-                    u_km1[m] = gs_value<T, 3, FD>(h2, b_km1[m], ld);
-                }
-                if (do_black && (flags[m] & 4)) {
-                    if (NTS)
-                        __builtin_nontemporal_store(u_km1[m], dp + off[m]);
-                    else
-                        dp[off[m]] = u_km1[m];
-                }
-            }
-        }
-    }
-}
-
-template <typename T, int TX, int TY, int NT, int D, bool NTS, bool NTB>
-cs_status fused_fd3_t(const Geo& g, const void* src, void* dst, const void* b, double h2,
-                      hipStream_t s)
-{
-    auto kern = k_fused_fd3<T, TX, TY, NT, D, NTS, NTB>;
-    FusedWork wk;
-    wk.tiles_x = (int)((g.nx + TX - 1) / TX);
-    wk.tiles_y = (int)((g.ny + TY - 1) / TY);
-    const int64_t tiles = (int64_t)wk.tiles_x * wk.tiles_y;
-    // one full wave of resident workgroups; chunks of at least 8 planes
-    int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, 0) != hipSuccess ||
-        hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-        (void)hipGetLastError();
-        per_cu = 2;
-        cus = 256;
-    }
-    const int64_t resident = (int64_t)(per_cu > 0 ? per_cu : 1) * cus;
-    int64_t chunks = resident / tiles;
-    if (chunks < 1) chunks = 1;
-    if (chunks > g.nz / 8) chunks = g.nz / 8 > 0 ? g.nz / 8 : 1;
-    wk.chunks = (int)chunks;
-    wk.nblocks = tiles * chunks;
-    hipLaunchKernelGGL(kern, dim3((unsigned)wk.nblocks), dim3(NT), 0, s, (const T*)src, (T*)dst,
-                       (const T*)b, g, (T)h2, wk);
-    return check_launch("fused 7-point sweep");
-}
-
-
-// ---------------------------------------------------------------------------
-// 8-colour sweep of the 27-point trilinear stencil.
-//
-// Colour = px + 2 py + 4 pz (parities of x, y, z).  The face weights of this
-// stencil are zero, so two colours that differ only in px never read each
-// other: colours {0,1} (py = 0, pz = 0), {2,3}, {4,5}, {6,7} are four row
-// phases A, B, C, D, each one a set of whole x-rows, and running a pair at
-// once equals running its two colours one after the other.  A and B live on
-// "even" planes (pz = 0), C and D on "odd" planes (pz = 1).  A reads only
-// values of the previous iterate; B reads the new A rows of its plane; C and D
-// read the final values of both neighbouring even planes, and D also the new C
-// rows.  The sweep therefore streams through z in double steps: even plane e
-// (A then B), then odd plane e-1 (C then D), after which planes e-1 and e are
-// final.  A tile needs a recomputed halo of 4 (A on T+3, B on T+2, C on T+1,
-// D on T).  Four planes (e-2 .. e+1) of the region T+4 live in LDS; the next
-// two planes are prefetched into registers.  Neighbour sums keep the
-// lexicographic offset order, so values equal the eight colour passes bit
-// for bit.
-// ---------------------------------------------------------------------------
-template <int TX, int TY, int NT, int HALO>
-struct Q1Phase {
-    static constexpr int W = TX + 8;
-    static constexpr int COLS = TX + 2 * HALO;
-    static constexpr int ROWS = (TY + 2 * HALO + 1) / 2;  // rows of one type, at most
-    static constexpr int P = (ROWS * COLS + NT - 1) / NT;  // points per thread, at most
-};
-
-// The points of one phase owned by a thread: rows of type rho inside T+halo.
-template <int TX, int TY, int NT, int HALO, int P>
-__device__ __forceinline__ void q1_make_pts(const Geo& g, int64_t x0, int64_t y0, int rho,
-                                            int* pc, int* poff, bool* pout)
-{
-    constexpr int W = TX + 8;
-    constexpr int COLS = TX + 2 * HALO;
-    const int ly_lo = 4 - HALO;
-    const int rt_lo = (int)((y0 - 4 + ly_lo - 1 + g.parity) & 1);
-    const int first = ly_lo + ((rho - rt_lo) & 1);
-    const int nrows = (TY + 2 * HALO - (first - ly_lo) + 1) / 2;
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-        const int sidx = (int)threadIdx.x + NT * i;
-        const int row = sidx / COLS, col = sidx % COLS;
-        const int ly = first + 2 * row, lx = 4 - HALO + col;
-        const int64_t x = x0 - 4 + lx, y = y0 - 4 + ly;
-        const bool ok = row < nrows && x >= 1 && x <= g.nx && y >= 1 && y <= g.ny;
-        pc[i] = ok ? ly * W + lx : -1;
-        poff[i] = ok ? (int)(y * g.sy + x) : 0;
-        pout[i] = ok && lx >= 4 && lx < 4 + TX && ly >= 4 && ly < 4 + TY;
-    }
-}
-
-template <typename T, int P>
-__device__ __forceinline__ void q1_load_b(const T* __restrict__ b, const Geo& g, int64_t k,
-                                          const int* pc, const int* poff, T* v)
-{
-    const bool kin = k >= 1 && k <= g.nz;
-    const T* bp = b + (kin ? k : 0) * g.sz;
-#pragma unroll
-    for (int i = 0; i < P; ++i) v[i] = (kin && pc[i] >= 0) ? bp[poff[i]] : T(0);
-}
-
-// One phase: update the listed points in place in plane slot lk (z neighbours
-// in lm and lp), writing the ones inside T to dst when `write`.
-template <typename T, int W, int P>
-__device__ __forceinline__ void q1_phase(bool active, const int* pc, const int* poff,
-                                         const bool* pout, const T* bv, const T* lm, T* lk,
-                                         const T* lp, T h2, T* dp, bool write)
-{
-    if (!active) return;
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-        const int c = pc[i];
-        if (c < 0) continue;
-        auto ld = [&](int ox, int oy, int oz) -> T {
-            const T* pl = oz < 0 ? lm : (oz > 0 ? lp : lk);
-            return pl[c + oy * W + ox];
-        };
-        const T v = gs_value<T, 3, Q1>(h2, bv[i], ld);
-        lk[c] = v;
-        if (write && pout[i]) dp[poff[i]] = v;
-    }
+    const TileBox tb = tile_box<TX, TY>(g, wk.tiles_x, wk.tiles_y, wk.chunks,
+                                        xcd_ordered_block(wk.nblocks));
+    fd3_tile<T, TX, TY, NT, D>(src, dst, b, g, h2, tb);
 }
 
 template <typename T, int TX, int TY, int NT, int WPE>
@@ -314,133 +46,22 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_fused_q1_3(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict__ b, Geo g,
              T h2, FusedWork wk)
 {
-    constexpr int W = TX + 8, HH = TY + 8, NCOL = W * HH;
-    constexpr int M = (NCOL + NT - 1) / NT;
-    using PA = Q1Phase<TX, TY, NT, 3>;
-    using PB = Q1Phase<TX, TY, NT, 2>;
-    using PC = Q1Phase<TX, TY, NT, 1>;
-    using PD = Q1Phase<TX, TY, NT, 0>;
-    __shared__ T L[4][NCOL];
-
-    const int64_t work = xcd_ordered_block(wk.nblocks);
-    const int64_t tiles = (int64_t)wk.tiles_x * wk.tiles_y;
-    const int64_t chunk = work / tiles;
-    const int64_t tile = work % tiles;
-    const int64_t x0 = 1 + (tile % wk.tiles_x) * TX;
-    const int64_t y0 = 1 + (tile / wk.tiles_x) * TY;
-    const int64_t z0 = 1 + (chunk * g.nz) / wk.chunks;
-    const int64_t z1 = 1 + ((chunk + 1) * g.nz) / wk.chunks;  // final planes [z0, z1)
-    const int tid = threadIdx.x;
-    const int par = g.parity;
-
-    // columns of the region T+4 (plane loads into LDS)
-    int coff[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-        const int c = tid + NT * m;
-        const int ly = c / W, lx = c % W;
-        const int64_t x = x0 - 4 + lx, y = y0 - 4 + ly;
-        const bool ok = c < NCOL && x >= 0 && x <= g.nx + 1 && y >= 0 && y <= g.ny + 1;
-        coff[m] = ok ? (int)(y * g.sy + x) : -1;
-    }
-    int ca[PA::P], oa[PA::P], cb[PB::P], ob[PB::P], cc[PC::P], oc[PC::P], cd[PD::P], od[PD::P];
-    bool wa[PA::P], wb[PB::P], wc[PC::P], wd[PD::P];
-    q1_make_pts<TX, TY, NT, 3, PA::P>(g, x0, y0, 0, ca, oa, wa);
-    q1_make_pts<TX, TY, NT, 2, PB::P>(g, x0, y0, 1, cb, ob, wb);
-    q1_make_pts<TX, TY, NT, 1, PC::P>(g, x0, y0, 0, cc, oc, wc);
-    q1_make_pts<TX, TY, NT, 0, PD::P>(g, x0, y0, 1, cd, od, wd);
-
-    auto is_even = [&](int64_t k) { return ((k - 1 + par) & 1) == 0; };
-    const int64_t e_first = is_even(z0 - 1) ? z0 - 1 : z0;
-    const int64_t e_last = is_even(z1) ? z1 : z1 - 1;
-
-    auto load_plane = [&](int64_t k, T* v) {
-        const bool kin = k >= 0 && k <= g.nz + 1;
-        const T* sp = src + (kin ? k : 0) * g.sz;
-#pragma unroll
-        for (int m = 0; m < M; ++m) v[m] = (kin && coff[m] >= 0) ? sp[coff[m]] : T(0);
-    };
-    auto store_plane = [&](const T* v, T* lp) {
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-            const int c = tid + NT * m;
-            if (c < NCOL) lp[c] = v[m];
-        }
-    };
-
-    // prefetched planes e, e+1 and the b values of the next double step; each
-    // double step is long (five barriers), so the prefetch has completed by the
-    // time the values move into place
-    T n0[M], n1[M];
-    T ba[PA::P], bb[PB::P], bc[PC::P], bd[PD::P];
-    {
-        T t[M];
-        load_plane(e_first - 1, t);
-        store_plane(t, L[(e_first - 1) & 3]);
-    }
-    load_plane(e_first, n0);
-    load_plane(e_first + 1, n1);
-    q1_load_b<T, PA::P>(b, g, e_first, ca, oa, ba);
-    q1_load_b<T, PB::P>(b, g, e_first, cb, ob, bb);
-    q1_load_b<T, PC::P>(b, g, e_first - 1, cc, oc, bc);
-    q1_load_b<T, PD::P>(b, g, e_first - 1, cd, od, bd);
-
-    for (int64_t e = e_first; e <= e_last; e += 2) {
-        T* lm2 = L[(e - 2) & 3];
-        T* lm1 = L[(e - 1) & 3];
-        T* l0 = L[e & 3];
-        T* lp1 = L[(e + 1) & 3];
-        store_plane(n0, l0);
-        store_plane(n1, lp1);
-        T ba_n[PA::P], bb_n[PB::P], bc_n[PC::P], bd_n[PD::P];
-        const bool more = e + 2 <= e_last;
-        if (more) {
-            load_plane(e + 2, n0);
-            load_plane(e + 3, n1);
-            q1_load_b<T, PA::P>(b, g, e + 2, ca, oa, ba_n);
-            q1_load_b<T, PB::P>(b, g, e + 2, cb, ob, bb_n);
-            q1_load_b<T, PC::P>(b, g, e + 1, cc, oc, bc_n);
-            q1_load_b<T, PD::P>(b, g, e + 1, cd, od, bd_n);
-        }
-        __syncthreads();
-        const bool ab = e >= 1 && e <= g.nz;
-        const bool wr_e = e >= z0 && e < z1;
-        T* dpe = dst + (ab ? e : 0) * g.sz;
-        q1_phase<T, W, PA::P>(ab, ca, oa, wa, ba, lm1, l0, lp1, h2, dpe, wr_e);
-        __syncthreads();
-        q1_phase<T, W, PB::P>(ab, cb, ob, wb, bb, lm1, l0, lp1, h2, dpe, wr_e);
-        __syncthreads();
-        const int64_t o = e - 1;
-        const bool cdo = o >= z0 && o < z1 && o >= 1 && o <= g.nz;
-        T* dpo = dst + (cdo ? o : 0) * g.sz;
-        q1_phase<T, W, PC::P>(cdo, cc, oc, wc, bc, lm2, lm1, l0, h2, dpo, true);
-        __syncthreads();
-        q1_phase<T, W, PD::P>(cdo, cd, od, wd, bd, lm2, lm1, l0, h2, dpo, true);
-        __syncthreads();
-        if (more) {
-#pragma unroll
-            for (int i = 0; i < PA::P; ++i) ba[i] = ba_n[i];
-#pragma unroll
-            for (int i = 0; i < PB::P; ++i) bb[i] = bb_n[i];
-#pragma unroll
-            for (int i = 0; i < PC::P; ++i) bc[i] = bc_n[i];
-#pragma unroll
-            for (int i = 0; i < PD::P; ++i) bd[i] = bd_n[i];
-        }
-    }
+    const TileBox tb = tile_box<TX, TY>(g, wk.tiles_x, wk.tiles_y, wk.chunks,
+                                        xcd_ordered_block(wk.nblocks));
+    q1_3_tile<T, TX, TY, NT>(src, dst, b, g, h2, tb);
 }
 
-template <typename T, int TX, int TY, int NT, int WPE>
-cs_status fused_q1_3_t(const Geo& g, const void* src, void* dst, const void* b, double h2,
-                       hipStream_t s)
+// Chunks so that the grid is one full wave of resident workgroups, each chunk
+// at least 8 planes deep.
+template <typename K>
+FusedWork plan_work(K kern, int nt, const Geo& g, int tx, int ty)
 {
-    auto kern = k_fused_q1_3<T, TX, TY, NT, WPE>;
     FusedWork wk;
-    wk.tiles_x = (int)((g.nx + TX - 1) / TX);
-    wk.tiles_y = (int)((g.ny + TY - 1) / TY);
+    wk.tiles_x = (int)((g.nx + tx - 1) / tx);
+    wk.tiles_y = (int)((g.ny + ty - 1) / ty);
     const int64_t tiles = (int64_t)wk.tiles_x * wk.tiles_y;
     int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, 0) != hipSuccess ||
         hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
         (void)hipGetLastError();
@@ -453,6 +74,26 @@ cs_status fused_q1_3_t(const Geo& g, const void* src, void* dst, const void* b, 
     if (chunks > g.nz / 8) chunks = g.nz / 8 > 0 ? g.nz / 8 : 1;
     wk.chunks = (int)chunks;
     wk.nblocks = tiles * chunks;
+    return wk;
+}
+
+template <typename T, int TX, int TY, int NT, int D>
+cs_status fused_fd3_t(const Geo& g, const void* src, void* dst, const void* b, double h2,
+                      hipStream_t s)
+{
+    auto kern = k_fused_fd3<T, TX, TY, NT, D>;
+    const FusedWork wk = plan_work(kern, NT, g, TX, TY);
+    hipLaunchKernelGGL(kern, dim3((unsigned)wk.nblocks), dim3(NT), 0, s, (const T*)src, (T*)dst,
+                       (const T*)b, g, (T)h2, wk);
+    return check_launch("fused 7-point sweep");
+}
+
+template <typename T, int TX, int TY, int NT, int WPE>
+cs_status fused_q1_3_t(const Geo& g, const void* src, void* dst, const void* b, double h2,
+                       hipStream_t s)
+{
+    auto kern = k_fused_q1_3<T, TX, TY, NT, WPE>;
+    const FusedWork wk = plan_work(kern, NT, g, TX, TY);
     hipLaunchKernelGGL(kern, dim3((unsigned)wk.nblocks), dim3(NT), 0, s, (const T*)src, (T*)dst,
                        (const T*)b, g, (T)h2, wk);
     return check_launch("fused 27-point sweep");
@@ -460,21 +101,21 @@ cs_status fused_q1_3_t(const Geo& g, const void* src, void* dst, const void* b, 
 
 // Tile variants of the fused kernels: COLSTEN_FUSED_VARIANT (7-point) and
 // COLSTEN_Q1_VARIANT (27-point), read once.
+int env_int(const char* name)
+{
+    const char* e = getenv(name);
+    return e ? atoi(e) : 0;
+}
+
 int fused_variant()
 {
-    static int v = [] {
-        const char* e = getenv("COLSTEN_FUSED_VARIANT");
-        return e ? atoi(e) : 0;
-    }();
+    static int v = env_int("COLSTEN_FUSED_VARIANT");
     return v;
 }
 
 int q1_variant()
 {
-    static int v = [] {
-        const char* e = getenv("COLSTEN_Q1_VARIANT");
-        return e ? atoi(e) : 0;
-    }();
+    static int v = env_int("COLSTEN_Q1_VARIANT");
     return v;
 }
 
@@ -483,6 +124,7 @@ int q1_variant()
 bool fused_supported(int dtype, int dim, int stencil, const Geo& g)
 {
     (void)dtype;
+    (void)stencil;
     // column offsets y*sy + x are 32-bit inside the kernels
     const bool small = (g.ny + 2) * g.sy < ((int64_t)1 << 31);
     return dim == 3 && small;
@@ -495,31 +137,27 @@ cs_status launch_fused_sweep(int dtype, int dim, int stencil, const Geo& g, cons
         set_error("fused sweep not available for this grid");
         return CS_EUNSUPPORTED;
     }
-#define CS_FD3(TX, TY, NT, D, NTS, NTB)                                                      \
-    return dtype == 0 ? fused_fd3_t<double, TX, TY, NT, D, NTS, NTB>(g, src, dst, b, h2, s)   \
-                      : fused_fd3_t<float, TX, TY, NT, D, NTS, NTB>(g, src, dst, b, h2, s)
+#define CS_FD3(TX, TY, NT, D)                                                    \
+    return dtype == 0 ? fused_fd3_t<double, TX, TY, NT, D>(g, src, dst, b, h2, s) \
+                      : fused_fd3_t<float, TX, TY, NT, D>(g, src, dst, b, h2, s)
 #define CS_Q13(TX, TY, NT, WPE)                                                   \
     return dtype == 0 ? fused_q1_3_t<double, TX, TY, NT, WPE>(g, src, dst, b, h2, s) \
                       : fused_q1_3_t<float, TX, TY, NT, WPE>(g, src, dst, b, h2, s)
     if (stencil == Q1) {
         switch (q1_variant()) {
-        case 1: CS_Q13(64, 16, 512, 4);
-        case 2: CS_Q13(64, 8, 256, 4);
-        case 3: CS_Q13(32, 32, 512, 3);
-        case 4: CS_Q13(128, 8, 512, 3);
+        case 1: CS_Q13(32, 32, 512, 3);
+        case 2: CS_Q13(128, 8, 512, 3);
         default: CS_Q13(64, 16, 512, 3);
         }
     }
-#undef CS_Q13
     switch (fused_variant()) {
-    case 1: CS_FD3(64, 16, 512, 1, true, false);
-    case 2: CS_FD3(64, 16, 512, 1, true, true);
-    case 3: CS_FD3(64, 16, 512, 2, true, false);
-    case 4: CS_FD3(128, 8, 512, 1, true, false);
-    case 5: CS_FD3(64, 32, 512, 1, true, false);
-    default: CS_FD3(64, 16, 512, 1, false, false);
+    case 1: CS_FD3(64, 16, 256, 1);
+    case 2: CS_FD3(128, 16, 512, 2);
+    case 3: CS_FD3(64, 32, 512, 2);
+    default: CS_FD3(64, 16, 512, 1);
     }
 #undef CS_FD3
+#undef CS_Q13
 }
 
 }  // namespace cs

@@ -1,0 +1,133 @@
+"""Batched patches: every patch of a batch against the oracle, the same patch
+alone and in a mix (bitwise), and the full 4096-patch workload on samples."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1810_04033_amd import colsten as C
+from paper_1810_04033_amd import inputs as I
+
+import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+NP = {torch.float64: np.float64, torch.float32: np.float32}
+TOL = {torch.float64: 1e-13, torch.float32: 1e-6}
+
+
+def _patch(n, st, dt, parity, seed, layout="aligned"):
+    u, b = G.case(3, n, seed)
+    h = 1.0 / (max(n) + 1)
+    ug, bg = G.upload(u, dt, layout), G.upload(b, dt, layout)
+    return dict(n=n, st=st, dt=dt, parity=parity, h=h, u0=u, b=b, ug=ug, bg=bg, tmp=C.grid_like(ug))
+
+
+def _batch(ps):
+    return C.Batch([(p["ug"], p["bg"], p["tmp"], p["st"], p["h"], p["parity"]) for p in ps])
+
+
+def _oracle(p, nsw):
+    uo, bo = p["u0"].astype(NP[p["dt"]]), p["b"].astype(NP[p["dt"]])
+    O.gs_sweeps(uo, bo, nsw, dim=3, stencil=p["st"], h=p["h"], parity=p["parity"])
+    return uo.astype(np.float64)
+
+
+SHAPES = [(1, 1, 1), (2, 3, 4), (5, 7, 3), (8, 8, 8), (16, 16, 16), (17, 9, 12), (24, 24, 24),
+          (33, 20, 18), (48, 48, 48), (64, 64, 64), (70, 13, 65), (40, 66, 9)]
+
+
+@pytest.mark.parametrize("nsw", [3, 4])
+def test_mixed_batch_matches_oracle(nsw):
+    ps = []
+    for i, n in enumerate(SHAPES):
+        for st in (C.CS_FD, C.CS_Q1):
+            dt = torch.float64 if (i + st) % 3 else torch.float32
+            ps.append(_patch(n, st, dt, (i // 2) % 2, seed=1000 + 7 * i + st,
+                             layout="odd" if i % 4 == 3 else "aligned"))
+    bt = _batch(ps)
+    bt.gs(nsw)
+    norms = bt.residual().cpu().numpy()
+    torch.cuda.synchronize()
+    for i, p in enumerate(ps):
+        ref = _oracle(p, nsw)
+        got = G.download(p["ug"])
+        assert G.relmax(got, ref) <= TOL[p["dt"]], (p["n"], p["st"], p["dt"])
+        want = O.residual(ref.astype(NP[p["dt"]]), p["b"].astype(NP[p["dt"]]), dim=3,
+                          stencil=p["st"], h=p["h"])
+        np.testing.assert_allclose(norms[i], want, rtol=1e-11 if p["dt"] == torch.float64 else 1e-5)
+
+
+def test_patch_alone_equals_patch_in_mix():
+    mix = [_patch(n, st, torch.float64, 0, seed=2000 + 3 * i + st)
+           for i, n in enumerate(SHAPES) for st in (C.CS_FD, C.CS_Q1)]
+    probe = [_patch((33, 20, 18), C.CS_Q1, torch.float64, 0, seed=77),
+             _patch((24, 24, 24), C.CS_FD, torch.float64, 1, seed=78)]
+    alone = [_patch(p["n"], p["st"], p["dt"], p["parity"], seed=s) for p, s in zip(probe, (77, 78))]
+    bt_mix = _batch(mix[:5] + probe[:1] + mix[5:] + probe[1:])
+    bt_mix.gs(5)
+    n_mix = bt_mix.residual().cpu().numpy()
+    for j, p in enumerate(alone):
+        ba = _batch([p])
+        ba.gs(5)
+        n_alone = ba.residual().cpu().numpy()
+        torch.cuda.synchronize()
+        assert torch.equal(p["ug"], probe[j]["ug"])
+        row = 5 if j == 0 else len(mix) + 1
+        assert np.array_equal(n_alone[0], n_mix[row])
+
+
+def test_batch_equals_single_grid_fused_path():
+    p = _patch((40, 33, 29), C.CS_Q1, torch.float64, 1, seed=90)
+    q = _patch((40, 33, 29), C.CS_Q1, torch.float64, 1, seed=90)
+    bt = _batch([p])
+    bt.gs(6)
+    g = C.Grid(q["ug"], q["bg"], dim=3, stencil=C.CS_Q1, h=q["h"], parity=1)
+    g.gs(6, tmp=q["tmp"])
+    torch.cuda.synchronize()
+    assert torch.equal(p["ug"], q["ug"])
+
+
+def test_bad_batches_are_rejected():
+    p = _patch((8, 8, 8), C.CS_FD, torch.float64, 0, seed=5)
+    with pytest.raises(C.ColstenError):
+        C.Batch([(p["ug"], p["bg"], p["ug"], C.CS_FD, p["h"], 0)])
+    d = C.describe(p["ug"], dim=3, stencil=C.CS_FD, h=p["h"])
+    d.n[2] = 100000
+    with pytest.raises(C.ColstenError):
+        C.cs_batch_create([d], [p["ug"].data_ptr()], [p["bg"].data_ptr()], [p["tmp"].data_ptr()])
+    with pytest.raises(C.ColstenError):
+        C.cs_batch_create([], [], [], [])
+
+
+def test_patch_workload_4096_sampled():
+    """4096 cubic patches, edges uniform over {8,16,24,32,48,64}, zero halo,
+    seeded uniform RHS (stream = patch id), u0 = 0, 20 red-black sweeps in one
+    batch; sampled patches compared with the oracle element by element, every
+    patch's norms checked against the initial ones."""
+    edges = I.patch_edges(3, 4096)
+    ps = []
+    for i, e in enumerate(edges):
+        u = C.empty_grid((e, e, e))
+        b = C.empty_grid((e, e, e))
+        bh = I.halo_array(I.uniform_field(I.stream_seed(3, i), (e, e, e)))
+        b.copy_(torch.from_numpy(bh))
+        ps.append((u, b, C.grid_like(u), C.CS_FD, 1.0 / (e + 1), 0))
+    bt = C.Batch(ps)
+    n0 = bt.residual().clone()
+    bt.gs(20)
+    n1 = bt.residual()
+    torch.cuda.synchronize()
+    n0, n1 = n0.cpu().numpy(), n1.cpu().numpy()
+    assert np.all(np.isfinite(n1)) and np.all(n1[:, 0] < n0[:, 0])
+    seen = {}
+    for i, e in enumerate(edges):
+        if seen.get(e, 0) >= (1 if e == 64 else 2):
+            continue
+        seen[e] = seen.get(e, 0) + 1
+        bh = I.halo_array(I.uniform_field(I.stream_seed(3, i), (e, e, e)))
+        uo = I.halo_array(np.zeros((e, e, e)))
+        O.gs_sweeps(uo, bh, 20, dim=3, stencil=O.FD, h=1.0 / (e + 1))
+        assert G.relmax(G.download(ps[i][0]), uo) <= 1e-13
+        np.testing.assert_allclose(n1[i], O.residual(uo, bh, dim=3, stencil=O.FD, h=1.0 / (e + 1)),
+                                   rtol=1e-11)
