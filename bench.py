@@ -44,6 +44,12 @@ def _args():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--per-colour", action="store_true",
                    help="run the GS rows as one launch per colour pass (no work array)")
+    p.add_argument("--workload", default="poisson3d",
+                   choices=["poisson3d", "patches", "refine", "serve"],
+                   help="poisson3d (default, the headline line); patches: 4096 batched patches; "
+                        "refine: FP32 sweeps in FP64 refinement to 1e-10; serve: request stream")
+    p.add_argument("--tune", action="store_true", help="patches: run the tile autotuner first")
+    p.add_argument("--refine-n", type=int, default=512, help="refine: interior edge")
     return p.parse_args()
 
 
@@ -92,12 +98,7 @@ def cpu_baseline():
                       "full 256^3 grid, sequential C oracle, %.1f s" % dt}
 
 
-def main():
-    a = _args()
-    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the coloured-sweep path is single-GPU "
-              "(see the sharding design); run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
+def run_poisson3d(a):
     import numpy as np
     import torch
 
@@ -230,6 +231,202 @@ def main():
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
+
+
+def run_patches(a):
+    """4096 cubic patches, edges uniform over {8,16,24,32,48,64} (seed 3), zero
+    halo, uniform[-1,1) RHS per patch (stream = patch id), u0 = 0, 20 red-black
+    7-point GS sweeps in FP64: one batched launch per sweep against one launch
+    per patch and colour (and one fused launch per patch and sweep)."""
+    import numpy as np
+    import torch
+
+    from paper_1810_04033_amd import colsten as C
+    from paper_1810_04033_amd import inputs as I
+    from paper_1810_04033_amd import tune as TU
+
+    torch.cuda.set_device(0)
+    sweeps = 20
+    tuned = TU.tune(C.CS_FD, torch.float64) if a.tune else TU.apply_cached(C.CS_FD, torch.float64)
+    edges = I.patch_edges(3, 4096)
+    ps = []
+    for i, e in enumerate(edges):
+        u = C.empty_grid((e, e, e))
+        b = C.empty_grid((e, e, e))
+        b.copy_(torch.from_numpy(I.halo_array(I.uniform_field(I.stream_seed(3, i), (e, e, e)))))
+        ps.append((u, b, C.grid_like(u), C.CS_FD, 1.0 / (e + 1), 0))
+    pts = sum(e ** 3 for e in edges)
+    bt = C.Batch(ps)
+    stream = torch.cuda.current_stream()
+
+    def reset():
+        for u, *_ in ps:
+            u.zero_()
+
+    for _ in range(a.warmup):
+        reset()
+        bt.gs(sweeps)
+    times = []
+    for _ in range(a.steps):
+        reset()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        bt.gs(sweeps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = sum(times) / len(times)
+    norms = bt.residual().cpu().numpy()
+    bt.close()
+
+    # one launch per patch per colour pass (in place), then one fused launch per sweep
+    base = {}
+    for mode in ("per_colour", "fused_per_patch"):
+        reset()
+        grids = [C.Grid(u, b, dim=3, stencil=C.CS_FD, h=h) for (u, b, t, st, h, par) in ps]
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for g, p in zip(grids, ps):
+            g.gs(sweeps, tmp=p[2] if mode == "fused_per_patch" else None)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        base[mode] = e0.elapsed_time(e1)
+        for g in grids:
+            g.close()
+
+    value = pts * sweeps / (ms * 1e-3) / 1e9
+    bytes_per_sweep = 24 * pts
+    achieved = bytes_per_sweep / (ms * 1e-3 / sweeps) / 1e9
+    out = {
+        "metric": "GLUP/s and patches/s (batched coloured GS on 4096 patches)",
+        "value": round(value, 3), "unit": "GLUP/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "4096 cubic patches, edge uniform over {8,16,24,32,48,64} (seed 3), "
+                               "FP64 7-point red-black GS, 20 sweeps per patch, zero Dirichlet halo",
+                   "points": pts, "sweeps": sweeps, "tile_policy": tuned},
+        "patches_per_s": round(4096 / (ms * 1e-3), 1),
+        "baseline_ms": {"one_launch_per_patch_per_colour": round(base["per_colour"], 3),
+                        "one_fused_launch_per_patch_per_sweep": round(base["fused_per_patch"], 3)},
+        "speedup_vs_per_patch_launches": round(base["per_colour"] / ms, 2),
+        "roofline": {"bound": "hbm", "kernel": "batched_gs_sweep_fd7", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "bytes_per_launch": int(bytes_per_sweep),
+                     "mean_launch_us": round(ms * 1e3 / sweeps, 3)},
+        "max_final_rel_residual": float(np.max(norms[:, 0] / norms[:, 2])),
+    }
+    if not a.no_cpu_baseline:
+        from oracle import oracle as O
+        t0 = time.perf_counter()
+        sample_pts = 0
+        for i in (0, 1, 2, 3, 4, 5, 6, 7):
+            e = edges[i]
+            bh = I.halo_array(I.uniform_field(I.stream_seed(3, i), (e, e, e)))
+            uo = I.halo_array(np.zeros((e, e, e)))
+            O.gs_sweeps(uo, bh, sweeps, dim=3, stencil=O.FD, h=1.0 / (e + 1))
+            sample_pts += e ** 3
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": sample_pts * sweeps / dt / 1e9, "unit": "GLUP/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "patches 0-7 of the same set, 20 sweeps each, sequential "
+                                         "C oracle, %.1f s" % dt}
+    print(json.dumps(out), flush=True)
+
+
+def run_refine(a):
+    """3D Poisson, n^3 interior (default 512), h = 1/(n+1), 27-point trilinear
+    8-colour GS.  RHS: 32 random Fourier modes (frequencies 1..32, N(0,1)
+    amplitudes) plus uniform[-1e-3, 1e-3] noise, seed 4.  FP32 sweeps inside
+    FP64 iterative refinement to 1e-10 relative residual, against FP64 sweeps
+    to the same tolerance; the final residual of each is recomputed by the
+    oracle in FP64 on the host."""
+    import numpy as np
+    import torch
+
+    from paper_1810_04033_amd import colsten as C
+    from paper_1810_04033_amd import inputs as I
+    from paper_1810_04033_amd import solve as S
+
+    torch.cuda.set_device(0)
+    n = a.refine_n
+    h = 1.0 / (n + 1)
+    tol = 1e-10
+    inner = 200
+    n3 = (n, n, n)
+    t0 = time.perf_counter()
+    b_host = I.halo_array(I.fourier_field(4, n))
+    gen_s = time.perf_counter() - t0
+    b = C.empty_grid(n3)
+    b.copy_(torch.from_numpy(b_host))
+    x = C.empty_grid(n3)
+    e = C.empty_grid(n3, dtype=torch.float32)
+    r32 = C.empty_grid(n3, dtype=torch.float32)
+    tmp32 = C.grid_like(e)
+    g64 = C.Grid(x, b, dim=3, stencil=C.CS_Q1, h=h)
+    g32 = C.Grid(e, r32, dim=3, stencil=C.CS_Q1, h=h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ir = S.ir_solve(g64, g32, tol, inner_sweeps=inner, tmp32=tmp32)
+    torch.cuda.synchronize()
+    ir_s = time.perf_counter() - t0
+    x_ir = x.detach().cpu().numpy()
+    del e, r32, tmp32
+    u = C.empty_grid(n3)
+    tmp = C.grid_like(u)
+    gp = C.Grid(u, b, dim=3, stencil=C.CS_Q1, h=h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fp = S.gs_solve(gp, tol, check_every=inner, tmp=tmp)
+    torch.cuda.synchronize()
+    fp_s = time.perf_counter() - t0
+    out = {
+        "metric": "seconds to 1e-10 relative residual (FP32 sweeps in FP64 refinement vs FP64 sweeps)",
+        "value": round(ir_s, 3), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(ir_s * 1e3, 1), "higher_is_better": False, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f32 sweeps / f64 residual and update", "data": "synthetic",
+        "config": {"workload": "3D Poisson %d^3, 27-point trilinear 8-colour GS, Fourier+noise RHS "
+                               "(seed 4), tol 1e-10, %d inner FP32 sweeps per refinement step"
+                               % (n, inner)},
+        "refine": {"seconds": round(ir_s, 3), "outer": ir.outer, "sweeps": ir.sweeps,
+                   "rel_residual_gpu": ir.rel_residual, "converged": ir.converged,
+                   "GLUP/s": round(n ** 3 * ir.sweeps / ir_s / 1e9, 2)},
+        "fp64": {"seconds": round(fp_s, 3), "sweeps": fp.sweeps, "rel_residual_gpu": fp.rel_residual,
+                 "converged": fp.converged, "GLUP/s": round(n ** 3 * fp.sweeps / fp_s / 1e9, 2)},
+        "speedup": round(fp_s / ir_s, 3), "rhs_generation_s": round(gen_s, 1),
+    }
+    if not a.no_cpu_baseline:
+        from oracle import oracle as O
+        t0 = time.perf_counter()
+        nr = O.residual(x_ir, b_host, dim=3, stencil=O.Q1, h=h)
+        out["refine"]["rel_residual_oracle_fp64"] = float(nr[0] / nr[2])
+        nf = O.residual(u.detach().cpu().numpy(), b_host, dim=3, stencil=O.Q1, h=h)
+        out["fp64"]["rel_residual_oracle_fp64"] = float(nf[0] / nf[2])
+        out["oracle_check_s"] = round(time.perf_counter() - t0, 1)
+    print(json.dumps(out), flush=True)
+
+
+def run_serve(a):
+    from paper_1810_04033_amd import serve as SV
+    SV.bench_main(a)
+
+
+def main():
+    a = _args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the coloured-sweep path is single-GPU "
+              "(see the sharding design); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if a.workload == "patches":
+        run_patches(a)
+    elif a.workload == "refine":
+        run_refine(a)
+    elif a.workload == "serve":
+        run_serve(a)
+    else:
+        run_poisson3d(a)
 
 
 if __name__ == "__main__":

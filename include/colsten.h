@@ -164,12 +164,12 @@ cs_status cs_batch_gs_sweeps(cs_batch bt, int32_t nsweeps, void* stream);
  * so its norms do not depend on the rest of the batch. */
 cs_status cs_batch_residual(cs_batch bt, double* norms, void* stream);
 
-/* Tile policy for batches created afterwards (process-wide): a patch with
- * n[0] <= small_max uses the small tile, n[0] <= mid_max the middle one,
- * else the large one (7-point: 16x16, 32x16, 64x16; 27-point: 16x8, 32x16,
- * 64x16).  Used by the autotuner.  Errors: CS_EINVAL for a bad stencil or
- * small_max > mid_max. */
-cs_status cs_batch_tile_policy(int32_t stencil, int32_t small_max, int32_t mid_max);
+/* Tile policy for batches created afterwards (process-wide, per stencil and
+ * dtype): a patch with n[0] <= small_max uses the small tile, n[0] <= mid_max
+ * the middle one, else the large one (7-point: 16x16, 32x16, 64x16;
+ * 27-point: 16x8, 32x16, 64x16).  Set by the autotuner.  Errors: CS_EINVAL
+ * for a bad stencil or dtype, or small_max > mid_max. */
+cs_status cs_batch_tile_policy(int32_t stencil, int32_t dtype, int32_t small_max, int32_t mid_max);
 
 /* *out = 1 if cs_gs_sweeps with a work array runs this grid's sweeps as fused
  * single passes, 0 if it falls back to one launch per colour. */

@@ -66,7 +66,7 @@ _SIGS = {
     "cs_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "cs_batch_gs_sweeps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "cs_batch_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
-    "cs_batch_tile_policy": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "cs_batch_tile_policy": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "cs_last_error": (ctypes.c_char_p, []),
 }
 
@@ -185,8 +185,8 @@ def cs_batch_residual(handle, norms_ptr, stream=None):
     _check(lib().cs_batch_residual(ctypes.c_void_p(handle), ctypes.c_void_p(norms_ptr), _stream(stream)))
 
 
-def cs_batch_tile_policy(stencil, small_max, mid_max):
-    _check(lib().cs_batch_tile_policy(int(stencil), int(small_max), int(mid_max)))
+def cs_batch_tile_policy(stencil, dtype, small_max, mid_max):
+    _check(lib().cs_batch_tile_policy(int(stencil), int(dtype), int(small_max), int(mid_max)))
 
 
 # --------------------------------------------------------------------------

@@ -23,13 +23,14 @@ struct Group {
     int64_t items = 0, res_items = 0, partial_base = 0;
 };
 
-int g_small_max[2] = {16, 16};
-int g_mid_max[2] = {40, 40};
+// [stencil][dtype]
+int g_small_max[2][2] = {{16, 16}, {16, 16}};
+int g_mid_max[2][2] = {{40, 40}, {40, 40}};
 
-int pick_variant(int stencil, int64_t nx)
+int pick_variant(int stencil, int dtype, int64_t nx)
 {
-    if (nx <= g_small_max[stencil]) return 0;
-    if (nx <= g_mid_max[stencil]) return 1;
+    if (nx <= g_small_max[stencil][dtype]) return 0;
+    if (nx <= g_mid_max[stencil][dtype]) return 1;
     return 2;
 }
 
@@ -58,14 +59,15 @@ static void free_batch(cs_batch_s* bt)
 
 extern "C" {
 
-cs_status cs_batch_tile_policy(int32_t stencil, int32_t small_max, int32_t mid_max)
+cs_status cs_batch_tile_policy(int32_t stencil, int32_t dtype, int32_t small_max, int32_t mid_max)
 {
-    if ((stencil != CS_FD && stencil != CS_Q1) || small_max < 0 || small_max > mid_max) {
+    if ((stencil != CS_FD && stencil != CS_Q1) || (dtype != CS_F64 && dtype != CS_F32) ||
+        small_max < 0 || small_max > mid_max) {
         set_error("bad tile policy");
         return CS_EINVAL;
     }
-    g_small_max[stencil] = small_max;
-    g_mid_max[stencil] = mid_max;
+    g_small_max[stencil][dtype] = small_max;
+    g_mid_max[stencil][dtype] = mid_max;
     return CS_OK;
 }
 
@@ -117,7 +119,7 @@ cs_status cs_batch_create(const cs_grid_desc* descs, void* const* u, const void*
         p.hh = d.h * d.h;
         p.h2 = d.dtype == CS_F32 ? (double)(float)p.hh : p.hh;
         p.index = i;
-        const int variant = pick_variant(d.stencil, d.n[0]);
+        const int variant = pick_variant(d.stencil, d.dtype, d.n[0]);
         int tx = 0, ty = 0;
         batch_variant_tile(d.stencil, variant, &tx, &ty);
         p.tiles_x = (int)((d.n[0] + tx - 1) / tx);

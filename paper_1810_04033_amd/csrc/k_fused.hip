@@ -51,6 +51,24 @@ k_fused_q1_3(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict
     q1_3_tile<T, TX, TY, NT>(src, dst, b, g, h2, tb);
 }
 
+// Resident workgroups of a kernel on the current device (queried once per
+// kernel; the library runs on devices of one kind).
+template <typename K>
+int64_t resident_blocks(K kern, int nt)
+{
+    static int64_t cached = 0;
+    if (cached > 0) return cached;
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, 0) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 256;
+    }
+    cached = (int64_t)(per_cu > 0 ? per_cu : 1) * cus;
+    return cached;
+}
+
 // Chunks so that the grid is one full wave of resident workgroups, each chunk
 // at least 8 planes deep.
 template <typename K>
@@ -60,15 +78,7 @@ FusedWork plan_work(K kern, int nt, const Geo& g, int tx, int ty)
     wk.tiles_x = (int)((g.nx + tx - 1) / tx);
     wk.tiles_y = (int)((g.ny + ty - 1) / ty);
     const int64_t tiles = (int64_t)wk.tiles_x * wk.tiles_y;
-    int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, 0) != hipSuccess ||
-        hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-        (void)hipGetLastError();
-        per_cu = 1;
-        cus = 256;
-    }
-    const int64_t resident = (int64_t)(per_cu > 0 ? per_cu : 1) * cus;
+    const int64_t resident = resident_blocks(kern, nt);
     int64_t chunks = resident / tiles;
     if (chunks < 1) chunks = 1;
     if (chunks > g.nz / 8) chunks = g.nz / 8 > 0 ? g.nz / 8 : 1;
