@@ -124,7 +124,7 @@ cs_status cs_batch_create(const cs_grid_desc* descs, void* const* u, const void*
         batch_variant_tile(d.stencil, variant, &tx, &ty);
         p.tiles_x = (int)((d.n[0] + tx - 1) / tx);
         p.tiles_y = (int)((d.n[1] + ty - 1) / ty);
-        p.chunks = (int)std::max<int64_t>(1, d.n[2] / 64);
+        p.chunks = 1;  // set below, once the batch's total tile count is known
         p.res_items = (int)batch_residual_items(p.g);
         // group key
         int k = -1;
@@ -142,6 +142,16 @@ cs_status cs_batch_create(const cs_grid_desc* descs, void* const* u, const void*
         }
         bt->groups[k].host.push_back(p);
     }
+    // z chunks: enough work items to fill the GPU (about 2048) when the batch
+    // holds few patches, never chunks thinner than 8 planes.  The split does
+    // not change any value: every point is computed the same way in any tile.
+    int64_t total_tiles = 0;
+    for (auto& gr : bt->groups)
+        for (auto& p : gr.host) total_tiles += (int64_t)p.tiles_x * p.tiles_y;
+    const int64_t want = (2048 + total_tiles - 1) / total_tiles;
+    for (auto& gr : bt->groups)
+        for (auto& p : gr.host)
+            p.chunks = (int)std::max<int64_t>(1, std::min<int64_t>(want, p.g.nz / 8));
     int64_t partial_total = 0;
     for (auto& gr : bt->groups) {
         std::stable_sort(gr.host.begin(), gr.host.end(), [](const BatchPatch& a, const BatchPatch& c) {
