@@ -64,7 +64,7 @@ def _source_sha(paths):
 def _traffic(kernel_key, sha):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
     if not os.path.exists(path):
         return None
     try:
@@ -199,7 +199,8 @@ def run_poisson3d(a):
     mean_launch_s = row_ms[dom] * 1e-3 / launches
     achieved = bytes_per_launch / mean_launch_s / 1e9
     if kernel.startswith("fused"):
-        src = ["paper_1810_04033_amd/csrc/k_fused.hip", "paper_1810_04033_amd/csrc/cs_device.h"]
+        src = ["paper_1810_04033_amd/csrc/k_fused.hip", "paper_1810_04033_amd/csrc/cs_tiles.h",
+               "paper_1810_04033_amd/csrc/cs_device.h"]
     elif kernel.startswith("jacobi"):
         src = ["paper_1810_04033_amd/csrc/k_stream.hip", "paper_1810_04033_amd/csrc/cs_device.h"]
     else:
@@ -351,6 +352,17 @@ def run_refine(a):
     from paper_1810_04033_amd import solve as S
 
     torch.cuda.set_device(0)
+
+    def say(msg):
+        print("[refine] " + msg, file=sys.stderr, flush=True)
+
+    last = [0.0]
+
+    def progress(sweeps, rel):
+        if time.perf_counter() - last[0] > 20.0:
+            last[0] = time.perf_counter()
+            say("%d sweeps, relative residual %.3e" % (sweeps, rel))
+
     n = a.refine_n
     h = 1.0 / (n + 1)
     tol = 1e-10
@@ -369,7 +381,8 @@ def run_refine(a):
     g32 = C.Grid(e, r32, dim=3, stencil=C.CS_Q1, h=h)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ir = S.ir_solve(g64, g32, tol, inner_sweeps=inner, tmp32=tmp32)
+    say("refinement solve, n = %d" % n)
+    ir = S.ir_solve(g64, g32, tol, inner_sweeps=inner, tmp32=tmp32, progress=progress)
     torch.cuda.synchronize()
     ir_s = time.perf_counter() - t0
     x_ir = x.detach().cpu().numpy()
@@ -379,7 +392,8 @@ def run_refine(a):
     gp = C.Grid(u, b, dim=3, stencil=C.CS_Q1, h=h)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    fp = S.gs_solve(gp, tol, check_every=inner, tmp=tmp)
+    say("refinement done in %.1f s; FP64 solve" % ir_s)
+    fp = S.gs_solve(gp, tol, check_every=inner, tmp=tmp, progress=progress)
     torch.cuda.synchronize()
     fp_s = time.perf_counter() - t0
     out = {
@@ -399,8 +413,10 @@ def run_refine(a):
     }
     if not a.no_cpu_baseline:
         from oracle import oracle as O
+        say("FP64 done in %.1f s; oracle residual checks" % fp_s)
         t0 = time.perf_counter()
         nr = O.residual(x_ir, b_host, dim=3, stencil=O.Q1, h=h)
+        say("oracle check 1 of 2 done")
         out["refine"]["rel_residual_oracle_fp64"] = float(nr[0] / nr[2])
         nf = O.residual(u.detach().cpu().numpy(), b_host, dim=3, stencil=O.Q1, h=h)
         out["fp64"]["rel_residual_oracle_fp64"] = float(nf[0] / nf[2])

@@ -30,9 +30,11 @@ class SolveResult:
     history: list = field(default_factory=list)
 
 
-def gs_solve(grid, tol, *, check_every=10, tmp=None, max_sweeps=10 ** 7, stream=None):
+def gs_solve(grid, tol, *, check_every=10, tmp=None, max_sweeps=10 ** 7, stream=None,
+             progress=None):
     """FP64 (or FP32) Gauss-Seidel sweeps until ||b - A u|| / ||b|| <= tol,
-    checked every `check_every` sweeps."""
+    checked every `check_every` sweeps.  progress(sweeps, rel) is called
+    after every check when given."""
     norms = grid.residual(stream=stream)
     n = norms.cpu().tolist()
     rel = n[0] / n[2] if n[2] > 0 else n[0]
@@ -45,12 +47,15 @@ def gs_solve(grid, tol, *, check_every=10, tmp=None, max_sweeps=10 ** 7, stream=
         n = grid.residual(stream=stream).cpu().tolist()
         rel = n[0] / n[2] if n[2] > 0 else n[0]
         hist.append(rel)
+        if progress is not None:
+            progress(sweeps, rel)
         if not math.isfinite(rel):
             break
     return SolveResult(rel <= tol, sweeps, 0, rel, hist)
 
 
-def ir_solve(g64, g32, tol, *, inner_sweeps, tmp32=None, max_outer=10 ** 6, stream=None):
+def ir_solve(g64, g32, tol, *, inner_sweeps, tmp32=None, max_outer=10 ** 6, stream=None,
+             progress=None):
     """FP32 Gauss-Seidel sweeps inside FP64 iterative refinement.
 
     Step i: r_i = b - A x_i (FP64) with r32 = fl32(r_i / s_i) and e = 0 in the
@@ -68,6 +73,8 @@ def ir_solve(g64, g32, tol, *, inner_sweeps, tmp32=None, max_outer=10 ** 6, stre
         n = norms.cpu().tolist()
         rel = n[0] / n[2] if n[2] > 0 else n[0]
         hist.append(rel)
+        if progress is not None:
+            progress(sweeps, rel)
         if rel <= tol or not math.isfinite(rel) or outer == max_outer:
             return SolveResult(rel <= tol, sweeps, outer, rel, hist)
         g32.gs(inner_sweeps, tmp=tmp32, stream=stream)
