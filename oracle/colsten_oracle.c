@@ -9,8 +9,9 @@
  * library.
  *
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC
- * (no contraction of a*b+c into an FMA, so every operation below is one
- *  IEEE-754 round-to-nearest-even operation in the order written).
+ * (no implicit contraction: every operation below, including each explicit
+ *  fma() call, is one IEEE-754 round-to-nearest-even operation in the order
+ *  written).
  *
  * Data (paper Sec. 2, "The studied stencil codes"): a d-dimensional Cartesian
  * mesh of fixed size stored as a plain d-dimensional array holding one scalar
@@ -42,11 +43,15 @@
  * interior point q of colour c, z-y-x order with x innermost,
  *     u_q <- (h^2 b_q - sum_{o != 0} S_o u_{q+o}) / S_0
  * where the neighbour sum runs over offsets in lexicographic (oz, oy, ox)
- * order and skips zero weights.  A sweep is the colour passes 0..c-1 in order.
+ * order, skips zero weights, and accumulates each term with one fused
+ * multiply-add (acc <- fma(S_o, u_{q+o}, acc), one rounding per term; the
+ * paper leaves the rounding open).  A sweep is the colour passes 0..c-1 in
+ * order.
  *
  * Separate-output update (Sec. 2: a separate output array as in a mat-vec):
- * weighted Jacobi  u'_q = u_q + w (h^2 b_q - sum_o S_o u_{q+o}) / S_0  and the
- * residual  r_q = b_q - (sum_o S_o u_{q+o}) / h^2, both reading only the old u.
+ * weighted Jacobi  u'_q = u_q + w (h^2 b_q - sum_o S_o u_{q+o}) / S_0  (the
+ * final multiply-add fused as well) and the residual
+ * r_q = b_q - (sum_o S_o u_{q+o}) / h^2, both reading only the old u.
  */
 #include <math.h>
 #include <stddef.h>
@@ -179,7 +184,7 @@ static double og_offsum(const og_grid* g, const double* u, int64_t q)
                 if (ox == 0 && oy == 0 && oz == 0) continue;
                 double w = og_weight(g->stencil, g->dim, ox, oy, oz);
                 if (w == 0.0) continue;
-                acc += w * u[q + oz * g->sz + oy * g->sy + ox];
+                acc = fma(w, u[q + oz * g->sz + oy * g->sy + ox], acc);
             }
     return acc;
 }
@@ -194,7 +199,7 @@ static double og_fullsum(const og_grid* g, const double* u, int64_t q)
             for (int ox = -1; ox <= 1; ++ox) {
                 double w = og_weight(g->stencil, g->dim, ox, oy, oz);
                 if (w == 0.0) continue;
-                acc += w * u[q + oz * g->sz + oy * g->sy + ox];
+                acc = fma(w, u[q + oz * g->sz + oy * g->sy + ox], acc);
             }
     return acc;
 }
@@ -209,7 +214,7 @@ static float og_offsum_f32(const og_grid* g, const float* u, int64_t q)
                 if (ox == 0 && oy == 0 && oz == 0) continue;
                 float w = og_weight_f32(g->stencil, g->dim, ox, oy, oz);
                 if (w == 0.0f) continue;
-                acc += w * u[q + oz * g->sz + oy * g->sy + ox];
+                acc = fmaf(w, u[q + oz * g->sz + oy * g->sy + ox], acc);
             }
     return acc;
 }
@@ -223,7 +228,7 @@ static float og_fullsum_f32(const og_grid* g, const float* u, int64_t q)
             for (int ox = -1; ox <= 1; ++ox) {
                 float w = og_weight_f32(g->stencil, g->dim, ox, oy, oz);
                 if (w == 0.0f) continue;
-                acc += w * u[q + oz * g->sz + oy * g->sy + ox];
+                acc = fmaf(w, u[q + oz * g->sz + oy * g->sy + ox], acc);
             }
     return acc;
 }
@@ -332,7 +337,7 @@ void og_jacobi_sweeps_f64(int dim, int stencil, int parity, int64_t nx, int64_t 
                 for (int64_t i = 1; i <= g.nx; ++i) {
                     int64_t q = og_index(&g, i, j, k);
                     double su = og_fullsum(&g, src, q);
-                    dst[q] = src[q] + omega * ((h2 * b[q] - su) / w0);
+                    dst[q] = fma(omega, (h2 * b[q] - su) / w0, src[q]);
                 }
         double* t = src; src = dst; dst = t;
     }
@@ -357,7 +362,7 @@ void og_jacobi_sweeps_f32(int dim, int stencil, int parity, int64_t nx, int64_t 
                 for (int64_t i = 1; i <= g.nx; ++i) {
                     int64_t q = og_index(&g, i, j, k);
                     float su = og_fullsum_f32(&g, src, q);
-                    dst[q] = src[q] + om * ((h2 * b[q] - su) / w0);
+                    dst[q] = fmaf(om, (h2 * b[q] - su) / w0, src[q]);
                 }
         float* t = src; src = dst; dst = t;
     }
@@ -421,7 +426,7 @@ void og_residual_f32in(int dim, int stencil, int parity, int64_t nx, int64_t ny,
                         for (int ox = -1; ox <= 1; ++ox) {
                             double w = og_weight(stencil, dim, ox, oy, oz);
                             if (w == 0.0) continue;
-                            su += w * (double)u[q + oz * g.sz + oy * g.sy + ox];
+                            su = fma(w, (double)u[q + oz * g.sz + oy * g.sy + ox], su);
                         }
                 double bq = (double)b[q];
                 double rq = bq - su / h2;

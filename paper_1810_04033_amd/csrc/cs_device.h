@@ -5,11 +5,14 @@
 // Hazelwood & Weinzierl, arXiv:1810.04033; the 27-point entries are the
 // assembled trilinear element stiffness: faces 0, edges -1/6, corners -1/12).
 //
-// The library is compiled with -ffp-contract=off: `acc += w * v` is one
-// rounded multiply and one rounded add.  Neighbour sums visit the offsets in
-// lexicographic (oz, oy, ox) order and skip zero weights, so a kernel using
-// these helpers rounds exactly like a plain sequential evaluation of
-//     u_q <- (h^2 b_q - sum_{o != 0} S_o u_{q+o}) / S_0 .
+// The library is compiled with -ffp-contract=off, so the only fused
+// operations are the explicit fused multiply-adds below.  Neighbour sums visit
+// the offsets in lexicographic (oz, oy, ox) order, skip zero weights and add
+// each term with one fused multiply-add (acc <- fma(S_o, u_{q+o}, acc)), so a
+// kernel using these helpers rounds exactly like a plain sequential
+// evaluation of
+//     u_q <- (h^2 b_q - sum_{o != 0} S_o u_{q+o}) / S_0
+// written the same way.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -40,6 +43,9 @@ __host__ __device__ constexpr int num_colours()
     return ST == FD ? 2 : (1 << DIM);
 }
 
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // sum_{o} S_o * ld(ox, oy, oz) over the nonzero weights, lexicographic
 // (oz, oy, ox) order; the centre is included iff CENTRE.
 template <typename T, int DIM, int ST, bool CENTRE, typename Load>
@@ -55,7 +61,7 @@ __device__ __forceinline__ T ordered_sum(const Load& ld)
                 if (!CENTRE && ox == 0 && oy == 0 && oz == 0) continue;
                 const T w = weight<T, DIM, ST>(ox, oy, oz);
                 if (w == T(0)) continue;
-                acc += w * ld(ox, oy, oz);
+                acc = fma_t(w, (T)ld(ox, oy, oz), acc);
             }
         }
     }
@@ -71,12 +77,13 @@ __device__ __forceinline__ T gs_value(T h2, T bq, const Load& ld)
     return (rhs - acc) / weight<T, DIM, ST>(0, 0, 0);
 }
 
-// Weighted Jacobi value: u_q + omega * (h^2 b_q - sum_o S_o u_{q+o}) / S_0.
+// Weighted Jacobi value: u_q + omega * (h^2 b_q - sum_o S_o u_{q+o}) / S_0,
+// the last multiply-add fused.
 template <typename T, int DIM, int ST, typename Load>
 __device__ __forceinline__ T jacobi_value(T h2, T omega, T bq, T uq, const Load& ld)
 {
     const T su = ordered_sum<T, DIM, ST, true>(ld);
-    return uq + omega * ((h2 * bq - su) / weight<T, DIM, ST>(0, 0, 0));
+    return fma_t(omega, (h2 * bq - su) / weight<T, DIM, ST>(0, 0, 0), uq);
 }
 
 }  // namespace cs

@@ -396,4 +396,209 @@ __device__ __forceinline__ void q1_3_tile(const T* __restrict__ src, T* __restri
     }
 }
 
+// ---------------------------------------------------------------------------
+// The same 27-point sweep with two x-adjacent points per thread.
+//
+// Points of one row phase are taken in pairs (x, x+1) whose left neighbour
+// column x-1 is even in LDS, over the full width of T+3 in every phase (the
+// extra ring points of the inner phases are computed but never used: they are
+// written neither outside the interior nor to dst, and no point that is used
+// reads them).  A pair reads 4 columns x-1..x+2 of the 8 neighbour rows,
+// 32 values instead of 2 x 20, in 16-byte LDS loads; each point's sum is the
+// same ordered fused multiply-add chain as the single-point form.
+// ---------------------------------------------------------------------------
+template <int TX, int TY, int NT, int HALO>
+struct Q1Pairs {
+    static constexpr int W = TX + 8;
+    static constexpr int NPC = (TX + 6) / 2;             // pair columns across T+3
+    static constexpr int ROWS = (TY + 2 * HALO + 1) / 2;  // rows of one type, at most
+    static constexpr int P = (ROWS * NPC + NT - 1) / NT;  // pairs per thread, at most
+};
+
+// flags: bit0/bit1 left/right point interior, bit2/bit3 left/right inside T
+template <int TX, int TY, int NT, int HALO, int P>
+__device__ __forceinline__ void q1_make_pairs(const Geo& g, int64_t x0, int64_t y0, int rho,
+                                              int* pc, int* poff, int* pfl)
+{
+    constexpr int W = TX + 8;
+    constexpr int NPC = (TX + 6) / 2;
+    const int ly_lo = 4 - HALO;
+    const int rt_lo = (int)((y0 - 4 + ly_lo - 1 + g.parity) & 1);
+    const int first = ly_lo + ((rho - rt_lo) & 1);
+    const int nrows = (TY + 2 * HALO - (first - ly_lo) + 1) / 2;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const int sidx = (int)threadIdx.x + NT * i;
+        const int row = sidx / NPC, pcol = sidx % NPC;
+        const int ly = first + 2 * row, lx = 1 + 2 * pcol;
+        const int64_t x = x0 - 4 + lx, y = y0 - 4 + ly;
+        const bool rowok = row < nrows && y >= 1 && y <= g.ny;
+        const bool in0 = rowok && x >= 1 && x <= g.nx;
+        const bool in1 = rowok && x + 1 >= 1 && x + 1 <= g.nx;
+        const bool ty_in = ly >= 4 && ly < 4 + TY;
+        const bool out0 = in0 && ty_in && lx >= 4 && lx < 4 + TX;
+        const bool out1 = in1 && ty_in && lx + 1 >= 4 && lx + 1 < 4 + TX;
+        pc[i] = (in0 || in1) ? ly * W + lx : -1;
+        poff[i] = (in0 || in1) ? (int)(y * g.sy + x) : 0;
+        pfl[i] = (in0 ? 1 : 0) | (in1 ? 2 : 0) | (out0 ? 4 : 0) | (out1 ? 8 : 0);
+    }
+}
+
+template <typename T, int P>
+__device__ __forceinline__ void q1_load_b_pairs(const T* __restrict__ b, const Geo& g, int64_t k,
+                                                const int* poff, const int* pfl, T* v)
+{
+    const bool kin = k >= 1 && k <= g.nz;
+    const T* bp = b + (kin ? k : 0) * g.sz;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        v[2 * i] = (kin && (pfl[i] & 1)) ? bp[poff[i]] : T(0);
+        v[2 * i + 1] = (kin && (pfl[i] & 2)) ? bp[poff[i] + 1] : T(0);
+    }
+}
+
+template <typename T, int W, int P>
+__device__ __forceinline__ void q1_phase_pairs(bool active, const int* pc, const int* poff,
+                                               const int* pfl, const T* bv, const T* lm, T* lk,
+                                               const T* lp, T h2, T* dp, bool write)
+{
+    if (!active) return;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const int c = pc[i];
+        if (c < 0) continue;
+        T v[3][3][4];
+#pragma unroll
+        for (int oz = -1; oz <= 1; ++oz) {
+            const T* pl = oz < 0 ? lm : (oz > 0 ? lp : lk);
+#pragma unroll
+            for (int oy = -1; oy <= 1; ++oy) {
+                if (oz == 0 && oy == 0) continue;
+                const int base = c - 1 + oy * W;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) v[oz + 1][oy + 1][k] = pl[base + k];
+            }
+        }
+        auto ld0 = [&](int ox, int oy, int oz) -> T { return v[oz + 1][oy + 1][ox + 1]; };
+        auto ld1 = [&](int ox, int oy, int oz) -> T { return v[oz + 1][oy + 1][ox + 2]; };
+        const T a0 = gs_value<T, 3, Q1>(h2, bv[2 * i], ld0);
+        const T a1 = gs_value<T, 3, Q1>(h2, bv[2 * i + 1], ld1);
+        const int fl = pfl[i];
+        if (fl & 1) lk[c] = a0;
+        if (fl & 2) lk[c + 1] = a1;
+        if (write && (fl & 4)) dp[poff[i]] = a0;
+        if (write && (fl & 8)) dp[poff[i] + 1] = a1;
+    }
+}
+
+template <typename T, int TX, int TY, int NT>
+__device__ __forceinline__ void q1_3_tile_pairs(const T* __restrict__ src, T* __restrict__ dst,
+                                                const T* __restrict__ b, const Geo& g, T h2,
+                                                const TileBox& tb)
+{
+    static_assert(TX % 2 == 0, "pairs need an even tile width");
+    constexpr int W = TX + 8, HH = TY + 8, NCOL = W * HH;
+    constexpr int M = (NCOL + NT - 1) / NT;
+    using PA = Q1Pairs<TX, TY, NT, 3>;
+    using PB = Q1Pairs<TX, TY, NT, 2>;
+    using PC = Q1Pairs<TX, TY, NT, 1>;
+    using PD = Q1Pairs<TX, TY, NT, 0>;
+    __shared__ __attribute__((aligned(16))) T L[4][NCOL];
+    const int64_t x0 = tb.x0, y0 = tb.y0, z0 = tb.z0, z1 = tb.z1;
+    const int tid = threadIdx.x;
+    const int par = g.parity;
+
+    int coff[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int c = tid + NT * m;
+        const int ly = c / W, lx = c % W;
+        const int64_t x = x0 - 4 + lx, y = y0 - 4 + ly;
+        const bool ok = c < NCOL && x >= 0 && x <= g.nx + 1 && y >= 0 && y <= g.ny + 1;
+        coff[m] = ok ? (int)(y * g.sy + x) : -1;
+    }
+    int ca[PA::P], oa[PA::P], fa[PA::P], cb[PB::P], ob[PB::P], fb[PB::P];
+    int cc[PC::P], oc[PC::P], fc[PC::P], cd[PD::P], od[PD::P], fd[PD::P];
+    q1_make_pairs<TX, TY, NT, 3, PA::P>(g, x0, y0, 0, ca, oa, fa);
+    q1_make_pairs<TX, TY, NT, 2, PB::P>(g, x0, y0, 1, cb, ob, fb);
+    q1_make_pairs<TX, TY, NT, 1, PC::P>(g, x0, y0, 0, cc, oc, fc);
+    q1_make_pairs<TX, TY, NT, 0, PD::P>(g, x0, y0, 1, cd, od, fd);
+
+    auto is_even = [&](int64_t k) { return ((k - 1 + par) & 1) == 0; };
+    const int64_t e_first = is_even(z0 - 1) ? z0 - 1 : z0;
+    const int64_t e_last = is_even(z1) ? z1 : z1 - 1;
+
+    auto load_plane = [&](int64_t k, T* v) {
+        const bool kin = k >= 0 && k <= g.nz + 1;
+        const T* sp = src + (kin ? k : 0) * g.sz;
+#pragma unroll
+        for (int m = 0; m < M; ++m) v[m] = (kin && coff[m] >= 0) ? sp[coff[m]] : T(0);
+    };
+    auto store_plane = [&](const T* v, T* lp) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int c = tid + NT * m;
+            if (c < NCOL) lp[c] = v[m];
+        }
+    };
+
+    T n0[M], n1[M];
+    T ba[2 * PA::P], bb[2 * PB::P], bc[2 * PC::P], bd[2 * PD::P];
+    {
+        T t[M];
+        load_plane(e_first - 1, t);
+        store_plane(t, L[(e_first - 1) & 3]);
+    }
+    load_plane(e_first, n0);
+    load_plane(e_first + 1, n1);
+    q1_load_b_pairs<T, PA::P>(b, g, e_first, oa, fa, ba);
+    q1_load_b_pairs<T, PB::P>(b, g, e_first, ob, fb, bb);
+    q1_load_b_pairs<T, PC::P>(b, g, e_first - 1, oc, fc, bc);
+    q1_load_b_pairs<T, PD::P>(b, g, e_first - 1, od, fd, bd);
+
+    for (int64_t e = e_first; e <= e_last; e += 2) {
+        T* lm2 = L[(e - 2) & 3];
+        T* lm1 = L[(e - 1) & 3];
+        T* l0 = L[e & 3];
+        T* lp1 = L[(e + 1) & 3];
+        store_plane(n0, l0);
+        store_plane(n1, lp1);
+        T ba_n[2 * PA::P], bb_n[2 * PB::P], bc_n[2 * PC::P], bd_n[2 * PD::P];
+        const bool more = e + 2 <= e_last;
+        if (more) {
+            load_plane(e + 2, n0);
+            load_plane(e + 3, n1);
+            q1_load_b_pairs<T, PA::P>(b, g, e + 2, oa, fa, ba_n);
+            q1_load_b_pairs<T, PB::P>(b, g, e + 2, ob, fb, bb_n);
+            q1_load_b_pairs<T, PC::P>(b, g, e + 1, oc, fc, bc_n);
+            q1_load_b_pairs<T, PD::P>(b, g, e + 1, od, fd, bd_n);
+        }
+        __syncthreads();
+        const bool ab = e >= 1 && e <= g.nz;
+        const bool wr_e = e >= z0 && e < z1;
+        T* dpe = dst + (ab ? e : 0) * g.sz;
+        q1_phase_pairs<T, W, PA::P>(ab, ca, oa, fa, ba, lm1, l0, lp1, h2, dpe, wr_e);
+        __syncthreads();
+        q1_phase_pairs<T, W, PB::P>(ab, cb, ob, fb, bb, lm1, l0, lp1, h2, dpe, wr_e);
+        __syncthreads();
+        const int64_t o = e - 1;
+        const bool cdo = o >= z0 && o < z1 && o >= 1 && o <= g.nz;
+        T* dpo = dst + (cdo ? o : 0) * g.sz;
+        q1_phase_pairs<T, W, PC::P>(cdo, cc, oc, fc, bc, lm2, lm1, l0, h2, dpo, true);
+        __syncthreads();
+        q1_phase_pairs<T, W, PD::P>(cdo, cd, od, fd, bd, lm2, lm1, l0, h2, dpo, true);
+        __syncthreads();
+        if (more) {
+#pragma unroll
+            for (int i = 0; i < 2 * PA::P; ++i) ba[i] = ba_n[i];
+#pragma unroll
+            for (int i = 0; i < 2 * PB::P; ++i) bb[i] = bb_n[i];
+#pragma unroll
+            for (int i = 0; i < 2 * PC::P; ++i) bc[i] = bc_n[i];
+#pragma unroll
+            for (int i = 0; i < 2 * PD::P; ++i) bd[i] = bd_n[i];
+        }
+    }
+}
+
 }  // namespace cs

@@ -41,14 +41,17 @@ k_fused_fd3(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict_
     fd3_tile<T, TX, TY, NT, D>(src, dst, b, g, h2, tb);
 }
 
-template <typename T, int TX, int TY, int NT, int WPE>
+template <typename T, int TX, int TY, int NT, int WPE, bool PAIRS>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_fused_q1_3(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict__ b, Geo g,
              T h2, FusedWork wk)
 {
     const TileBox tb = tile_box<TX, TY>(g, wk.tiles_x, wk.tiles_y, wk.chunks,
                                         xcd_ordered_block(wk.nblocks));
-    q1_3_tile<T, TX, TY, NT>(src, dst, b, g, h2, tb);
+    if (PAIRS)
+        q1_3_tile_pairs<T, TX, TY, NT>(src, dst, b, g, h2, tb);
+    else
+        q1_3_tile<T, TX, TY, NT>(src, dst, b, g, h2, tb);
 }
 
 // Resident workgroups of a kernel on the current device (queried once per
@@ -98,11 +101,11 @@ cs_status fused_fd3_t(const Geo& g, const void* src, void* dst, const void* b, d
     return check_launch("fused 7-point sweep");
 }
 
-template <typename T, int TX, int TY, int NT, int WPE>
+template <typename T, int TX, int TY, int NT, int WPE, bool PAIRS>
 cs_status fused_q1_3_t(const Geo& g, const void* src, void* dst, const void* b, double h2,
                        hipStream_t s)
 {
-    auto kern = k_fused_q1_3<T, TX, TY, NT, WPE>;
+    auto kern = k_fused_q1_3<T, TX, TY, NT, WPE, PAIRS>;
     const FusedWork wk = plan_work(kern, NT, g, TX, TY);
     hipLaunchKernelGGL(kern, dim3((unsigned)wk.nblocks), dim3(NT), 0, s, (const T*)src, (T*)dst,
                        (const T*)b, g, (T)h2, wk);
@@ -150,14 +153,18 @@ cs_status launch_fused_sweep(int dtype, int dim, int stencil, const Geo& g, cons
 #define CS_FD3(TX, TY, NT, D)                                                    \
     return dtype == 0 ? fused_fd3_t<double, TX, TY, NT, D>(g, src, dst, b, h2, s) \
                       : fused_fd3_t<float, TX, TY, NT, D>(g, src, dst, b, h2, s)
-#define CS_Q13(TX, TY, NT, WPE)                                                   \
-    return dtype == 0 ? fused_q1_3_t<double, TX, TY, NT, WPE>(g, src, dst, b, h2, s) \
-                      : fused_q1_3_t<float, TX, TY, NT, WPE>(g, src, dst, b, h2, s)
+#define CS_Q13(TX, TY, NT, WPE, PAIRS)                                                   \
+    return dtype == 0 ? fused_q1_3_t<double, TX, TY, NT, WPE, PAIRS>(g, src, dst, b, h2, s) \
+                      : fused_q1_3_t<float, TX, TY, NT, WPE, PAIRS>(g, src, dst, b, h2, s)
     if (stencil == Q1) {
         switch (q1_variant()) {
-        case 1: CS_Q13(32, 32, 512, 3);
-        case 2: CS_Q13(128, 8, 512, 3);
-        default: CS_Q13(64, 16, 512, 3);
+        case 1: CS_Q13(64, 16, 512, 3, false);
+        case 2: CS_Q13(64, 12, 256, 3, true);
+        case 3: CS_Q13(32, 16, 128, 5, true);
+        case 4: CS_Q13(64, 8, 128, 4, true);
+        case 5: CS_Q13(128, 8, 256, 2, true);
+        case 6: CS_Q13(32, 32, 256, 3, true);
+        default: CS_Q13(64, 16, 256, 2, true);
         }
     }
     switch (fused_variant()) {

@@ -21,8 +21,8 @@ MUTANTS = {
         "    if (nnz == 0) return 8.0 / 3.0;\n    if (nnz == 1) return 0.0;",
         "    if (nnz == 0) return 8.0 / 3.0;\n    if (nnz == 1) return -1.0 / 12.0;"),
     "sign_of_neighbour_sum": (
-        "acc += w * u[q + oz * g->sz + oy * g->sy + ox];",
-        "acc -= w * u[q + oz * g->sz + oy * g->sy + ox];"),
+        "acc = fma(w, u[q + oz * g->sz + oy * g->sy + ox], acc);",
+        "acc = fma(-w, u[q + oz * g->sz + oy * g->sy + ox], acc);"),
     "transposed_strides": (
         "return (g->dim == 3 ? k * g->sz : 0) + j * g->sy + i;",
         "return (g->dim == 3 ? k * g->sy : 0) + j * g->sz + i;"),
@@ -39,8 +39,8 @@ MUTANTS = {
         "c |= (int)((j - 1 + parity) & 1) << 1;",
         "c |= (int)((i - 1 + parity) & 1) << 1;"),
     "jacobi_weight_dropped": (
-        "dst[q] = src[q] + omega * ((h2 * b[q] - su) / w0);",
-        "dst[q] = src[q] + ((h2 * b[q] - su) / w0);"),
+        "dst[q] = fma(omega, (h2 * b[q] - su) / w0, src[q]);",
+        "dst[q] = (h2 * b[q] - su) / w0 + src[q];"),
     "residual_scaled_wrongly": (
         "double rq = b[q] - su / h2;\n                if (r) r[q] = rq;",
         "double rq = b[q] - su * h2;\n                if (r) r[q] = rq;"),
