@@ -45,8 +45,11 @@
  * where the neighbour sum runs over offsets in lexicographic (oz, oy, ox)
  * order, skips zero weights, and accumulates each term with one fused
  * multiply-add (acc <- fma(S_o, u_{q+o}, acc), one rounding per term; the
- * paper leaves the rounding open).  A sweep is the colour passes 0..c-1 in
- * order.
+ * paper leaves the rounding open).  The quotient by S_0 is the exact quotient
+ * rounded once: for the d-linear stencils S_0 = 8/3 has the binary inverse
+ * 3/8, so x / S_0 is formed as x * 0.375 (a division by the rounded 8/3 would
+ * round twice); the FD centre 2d is exact and divides directly.  A sweep is
+ * the colour passes 0..c-1 in order.
  *
  * Separate-output update (Sec. 2: a separate output array as in a mat-vec):
  * weighted Jacobi  u'_q = u_q + w (h^2 b_q - sum_o S_o u_{q+o}) / S_0  (the
@@ -233,23 +236,35 @@ static float og_fullsum_f32(const og_grid* g, const float* u, int64_t q)
     return acc;
 }
 
+/* x / S_0, the exact quotient rounded once: x * (3/8) for the d-linear
+ * stencils (S_0 = 8/3), x / (2d) for the FD stencils. */
+static double og_over_centre(int stencil, int dim, double x)
+{
+    if (stencil == 1) return x * 0.375;
+    return x / (2.0 * dim);
+}
+
+static float og_over_centre_f32(int stencil, int dim, float x)
+{
+    if (stencil == 1) return x * 0.375f;
+    return x / (float)(2 * dim);
+}
+
 /* Gauss-Seidel point update, in situ. */
 static void og_update(const og_grid* g, double* u, const double* b, int64_t q)
 {
     double h2 = g->h * g->h;
-    double w0 = og_weight(g->stencil, g->dim, 0, 0, 0);
     double rhs = h2 * b[q];
     double acc = og_offsum(g, u, q);
-    u[q] = (rhs - acc) / w0;
+    u[q] = og_over_centre(g->stencil, g->dim, rhs - acc);
 }
 
 static void og_update_f32(const og_grid* g, float* u, const float* b, int64_t q)
 {
     float h2 = (float)(g->h * g->h);
-    float w0 = og_weight_f32(g->stencil, g->dim, 0, 0, 0);
     float rhs = h2 * b[q];
     float acc = og_offsum_f32(g, u, q);
-    u[q] = (rhs - acc) / w0;
+    u[q] = og_over_centre_f32(g->stencil, g->dim, rhs - acc);
 }
 
 /* ------------------------------------------------------------------ */
@@ -327,7 +342,6 @@ void og_jacobi_sweeps_f64(int dim, int stencil, int parity, int64_t nx, int64_t 
 {
     og_grid g = og_make(dim, stencil, parity, nx, ny, nz, sy, sz, h);
     double h2 = h * h;
-    double w0 = og_weight(stencil, dim, 0, 0, 0);
     memcpy(tmp, u, (size_t)total_len * sizeof(double));
     double* src = u;
     double* dst = tmp;
@@ -337,7 +351,7 @@ void og_jacobi_sweeps_f64(int dim, int stencil, int parity, int64_t nx, int64_t 
                 for (int64_t i = 1; i <= g.nx; ++i) {
                     int64_t q = og_index(&g, i, j, k);
                     double su = og_fullsum(&g, src, q);
-                    dst[q] = fma(omega, (h2 * b[q] - su) / w0, src[q]);
+                    dst[q] = fma(omega, og_over_centre(stencil, dim, h2 * b[q] - su), src[q]);
                 }
         double* t = src; src = dst; dst = t;
     }
@@ -351,7 +365,6 @@ void og_jacobi_sweeps_f32(int dim, int stencil, int parity, int64_t nx, int64_t 
 {
     og_grid g = og_make(dim, stencil, parity, nx, ny, nz, sy, sz, h);
     float h2 = (float)(h * h);
-    float w0 = og_weight_f32(stencil, dim, 0, 0, 0);
     float om = (float)omega;
     memcpy(tmp, u, (size_t)total_len * sizeof(float));
     float* src = u;
@@ -362,7 +375,7 @@ void og_jacobi_sweeps_f32(int dim, int stencil, int parity, int64_t nx, int64_t 
                 for (int64_t i = 1; i <= g.nx; ++i) {
                     int64_t q = og_index(&g, i, j, k);
                     float su = og_fullsum_f32(&g, src, q);
-                    dst[q] = fmaf(om, (h2 * b[q] - su) / w0, src[q]);
+                    dst[q] = fmaf(om, og_over_centre_f32(stencil, dim, h2 * b[q] - su), src[q]);
                 }
         float* t = src; src = dst; dst = t;
     }

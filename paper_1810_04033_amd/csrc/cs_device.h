@@ -12,7 +12,7 @@
 // kernel using these helpers rounds exactly like a plain sequential
 // evaluation of
 //     u_q <- (h^2 b_q - sum_{o != 0} S_o u_{q+o}) / S_0
-// written the same way.
+// written the same way, with the quotient by S_0 formed as in over_centre.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -43,6 +43,15 @@ __host__ __device__ constexpr int num_colours()
     return ST == FD ? 2 : (1 << DIM);
 }
 
+// Store of a value that no thread of the same launch reads again (the new
+// iterate of a sweep): a nontemporal store, which keeps the caches for the
+// halo rows that neighbouring tiles re-read.
+template <typename T>
+__device__ __forceinline__ void st_stream(T* p, T v)
+{
+    __builtin_nontemporal_store(v, p);
+}
+
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
@@ -68,13 +77,23 @@ __device__ __forceinline__ T ordered_sum(const Load& ld)
     return acc;
 }
 
+// x / S_0 as the exact quotient rounded once: the d-linear centre 8/3 has the
+// binary inverse 3/8, so the quotient is the product x * 0.375; the FD centre
+// 2d divides directly.
+template <typename T, int DIM, int ST>
+__device__ __forceinline__ T over_centre(T x)
+{
+    if (ST == Q1) return x * T(0.375);
+    return x / T(2 * DIM);
+}
+
 // Gauss-Seidel value of one point from its neighbours (centre excluded).
 template <typename T, int DIM, int ST, typename Load>
 __device__ __forceinline__ T gs_value(T h2, T bq, const Load& ld)
 {
     const T rhs = h2 * bq;
     const T acc = ordered_sum<T, DIM, ST, false>(ld);
-    return (rhs - acc) / weight<T, DIM, ST>(0, 0, 0);
+    return over_centre<T, DIM, ST>(rhs - acc);
 }
 
 // Weighted Jacobi value: u_q + omega * (h^2 b_q - sum_o S_o u_{q+o}) / S_0,
@@ -83,7 +102,7 @@ template <typename T, int DIM, int ST, typename Load>
 __device__ __forceinline__ T jacobi_value(T h2, T omega, T bq, T uq, const Load& ld)
 {
     const T su = ordered_sum<T, DIM, ST, true>(ld);
-    return fma_t(omega, (h2 * bq - su) / weight<T, DIM, ST>(0, 0, 0), uq);
+    return fma_t(omega, over_centre<T, DIM, ST>(h2 * bq - su), uq);
 }
 
 }  // namespace cs

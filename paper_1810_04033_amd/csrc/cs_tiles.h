@@ -192,7 +192,7 @@ __device__ __forceinline__ void fd3_tile(const T* __restrict__ src, T* __restric
                     };
                     u_km1[m] = gs_value<T, 3, FD>(h2, b_km1[m], ld);
                 }
-                if (do_black && (flags[m] & 4)) dp[off[m]] = u_km1[m];
+                if (do_black && (flags[m] & 4)) st_stream(dp + off[m], u_km1[m]);
             }
         }
     }
@@ -277,7 +277,7 @@ __device__ __forceinline__ void q1_phase(bool active, const int* pc, const int* 
         };
         const T v = gs_value<T, 3, Q1>(h2, bv[i], ld);
         lk[c] = v;
-        if (write && pout[i]) dp[poff[i]] = v;
+        if (write && pout[i]) st_stream(dp + poff[i], v);
     }
 }
 
@@ -458,9 +458,9 @@ __device__ __forceinline__ void q1_load_b_pairs(const T* __restrict__ b, const G
 }
 
 template <typename T, int W, int P>
-__device__ __forceinline__ void q1_phase_pairs(bool active, const int* pc, const int* poff,
-                                               const int* pfl, const T* bv, const T* lm, T* lk,
-                                               const T* lp, T h2, T* dp, bool write)
+__device__ __forceinline__ void q1_phase_pairs(bool active, const int* pc, const T* bv,
+                                               const T* lm, T* lk, const T* lp, const int* pfl,
+                                               T h2, T* out)
 {
     if (!active) return;
 #pragma unroll
@@ -486,8 +486,21 @@ __device__ __forceinline__ void q1_phase_pairs(bool active, const int* pc, const
         const int fl = pfl[i];
         if (fl & 1) lk[c] = a0;
         if (fl & 2) lk[c + 1] = a1;
-        if (write && (fl & 4)) dp[poff[i]] = a0;
-        if (write && (fl & 8)) dp[poff[i] + 1] = a1;
+        out[2 * i] = a0;
+        out[2 * i + 1] = a1;
+    }
+}
+
+// Writes the tile points of one row phase (flags bit2/bit3) to dp.
+template <typename T, int P>
+__device__ __forceinline__ void q1_store_pairs(bool write, T* dp, const int* poff, const int* pfl,
+                                               const T* out)
+{
+    if (!write) return;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        if (pfl[i] & 4) st_stream(dp + poff[i], out[2 * i]);
+        if (pfl[i] & 8) st_stream(dp + poff[i] + 1, out[2 * i + 1]);
     }
 }
 
@@ -574,19 +587,24 @@ __device__ __forceinline__ void q1_3_tile_pairs(const T* __restrict__ src, T* __
             q1_load_b_pairs<T, PD::P>(b, g, e + 1, od, fd, bd_n);
         }
         __syncthreads();
+        T ra[2 * PA::P], rb[2 * PB::P], rc[2 * PC::P], rd[2 * PD::P];
         const bool ab = e >= 1 && e <= g.nz;
-        const bool wr_e = e >= z0 && e < z1;
+        const bool wr_e = ab && e >= z0 && e < z1;
         T* dpe = dst + (ab ? e : 0) * g.sz;
-        q1_phase_pairs<T, W, PA::P>(ab, ca, oa, fa, ba, lm1, l0, lp1, h2, dpe, wr_e);
+        q1_phase_pairs<T, W, PA::P>(ab, ca, ba, lm1, l0, lp1, fa, h2, ra);
+        q1_store_pairs<T, PA::P>(wr_e, dpe, oa, fa, ra);
         __syncthreads();
-        q1_phase_pairs<T, W, PB::P>(ab, cb, ob, fb, bb, lm1, l0, lp1, h2, dpe, wr_e);
+        q1_phase_pairs<T, W, PB::P>(ab, cb, bb, lm1, l0, lp1, fb, h2, rb);
+        q1_store_pairs<T, PB::P>(wr_e, dpe, ob, fb, rb);
         __syncthreads();
         const int64_t o = e - 1;
         const bool cdo = o >= z0 && o < z1 && o >= 1 && o <= g.nz;
         T* dpo = dst + (cdo ? o : 0) * g.sz;
-        q1_phase_pairs<T, W, PC::P>(cdo, cc, oc, fc, bc, lm2, lm1, l0, h2, dpo, true);
+        q1_phase_pairs<T, W, PC::P>(cdo, cc, bc, lm2, lm1, l0, fc, h2, rc);
+        q1_store_pairs<T, PC::P>(cdo, dpo, oc, fc, rc);
         __syncthreads();
-        q1_phase_pairs<T, W, PD::P>(cdo, cd, od, fd, bd, lm2, lm1, l0, h2, dpo, true);
+        q1_phase_pairs<T, W, PD::P>(cdo, cd, bd, lm2, lm1, l0, fd, h2, rd);
+        q1_store_pairs<T, PD::P>(cdo, dpo, od, fd, rd);
         __syncthreads();
         if (more) {
 #pragma unroll

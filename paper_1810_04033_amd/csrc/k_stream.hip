@@ -161,7 +161,7 @@ k_stream3(const S* __restrict__ src, S* __restrict__ dst, const S* __restrict__ 
                 return (A)pl[c + oy * W + ox];
             };
             if (MODE == MODE_JACOBI) {
-                dp[poff[i]] = jacobi_value<A, 3, ST>(h2, omega, (A)bcur[i], (A)l0[c], ld);
+                st_stream(dp + poff[i], (S)jacobi_value<A, 3, ST>(h2, omega, (A)bcur[i], (A)l0[c], ld));
             } else {
                 const double su = ordered_sum<double, 3, ST, true>(ld);
                 const double bq = (double)bcur[i];

@@ -27,8 +27,11 @@ MUTANTS = {
         "return (g->dim == 3 ? k * g->sz : 0) + j * g->sy + i;",
         "return (g->dim == 3 ? k * g->sy : 0) + j * g->sz + i;"),
     "swapped_update_operands": (
-        "    u[q] = (rhs - acc) / w0;\n}\n\nstatic void og_update_f32",
-        "    u[q] = (acc - rhs) / w0;\n}\n\nstatic void og_update_f32"),
+        "    u[q] = og_over_centre(g->stencil, g->dim, rhs - acc);\n}",
+        "    u[q] = og_over_centre(g->stencil, g->dim, acc - rhs);\n}"),
+    "wrong_q1_centre": (
+        "    if (stencil == 1) return x * 0.375;\n    return x / (2.0 * dim);",
+        "    if (stencil == 1) return x / 3.0;\n    return x / (2.0 * dim);"),
     "dropped_plus_x_neighbour": (
         "            for (int ox = -1; ox <= 1; ++ox) {\n                if (ox == 0 && oy == 0 && oz == 0) continue;\n                double w",
         "            for (int ox = -1; ox <= 0; ++ox) {\n                if (ox == 0 && oy == 0 && oz == 0) continue;\n                double w"),
@@ -39,8 +42,8 @@ MUTANTS = {
         "c |= (int)((j - 1 + parity) & 1) << 1;",
         "c |= (int)((i - 1 + parity) & 1) << 1;"),
     "jacobi_weight_dropped": (
-        "dst[q] = fma(omega, (h2 * b[q] - su) / w0, src[q]);",
-        "dst[q] = (h2 * b[q] - su) / w0 + src[q];"),
+        "dst[q] = fma(omega, og_over_centre(stencil, dim, h2 * b[q] - su), src[q]);",
+        "dst[q] = og_over_centre(stencil, dim, h2 * b[q] - su) + src[q];"),
     "residual_scaled_wrongly": (
         "double rq = b[q] - su / h2;\n                if (r) r[q] = rq;",
         "double rq = b[q] - su * h2;\n                if (r) r[q] = rq;"),
