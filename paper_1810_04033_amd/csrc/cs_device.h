@@ -77,14 +77,28 @@ __device__ __forceinline__ T ordered_sum(const Load& ld)
     return acc;
 }
 
-// x / S_0 as the exact quotient rounded once: the d-linear centre 8/3 has the
-// binary inverse 3/8, so the quotient is the product x * 0.375; the FD centre
-// 2d divides directly.
+// x / S_0 as the exact quotient rounded once.
+//  - d-linear stencils: S_0 = 8/3 has the binary inverse 3/8, so the quotient
+//    is the product x * 0.375.
+//  - 2D FD: S_0 = 4, a power of two: x * 0.25 is the quotient.
+//  - 3D FD: S_0 = 6.  q = RN(x z) with z = RN(1/6) is within two ulps of
+//    x/6, so the residual r = x - 6q is exact in one fused multiply-add, and
+//    q' = RN(q + r z) = RN(x/6 + e) with |e| <= |r| |z - 1/6|, about
+//    2^-p ulp(x/6) (p = 53 or 24).  For a divisor 3 * 2^k the exact quotient
+//    of a p-bit x lies at least ulp(x/6) / 6 away from every rounding
+//    midpoint (|8m - 3(2k+1)| >= 1 for integers m, k), so q' = RN(x/6) for
+//    every x whose quotient is normal, up to the sign of a zero result: three
+//    operations instead of a full division (Markstein's correction step for
+//    a constant divisor).
 template <typename T, int DIM, int ST>
 __device__ __forceinline__ T over_centre(T x)
 {
     if (ST == Q1) return x * T(0.375);
-    return x / T(2 * DIM);
+    if (DIM == 2) return x * T(0.25);
+    constexpr T z = T(1) / T(6);
+    const T q = x * z;
+    const T r = fma_t(-q, T(6), x);
+    return fma_t(r, z, q);
 }
 
 // Gauss-Seidel value of one point from its neighbours (centre excluded).
