@@ -569,53 +569,51 @@ __device__ __forceinline__ void q1_3_tile_pairs(const T* __restrict__ src, T* __
     q1_load_b_pairs<T, PC::P>(b, g, e_first - 1, oc, fc, bc);
     q1_load_b_pairs<T, PD::P>(b, g, e_first - 1, od, fd, bd);
 
-    for (int64_t e = e_first; e <= e_last; e += 2) {
+    // One double step e with the b values of this step in cb* and the next
+    // step's loaded into nb*; the loop alternates the two register sets, so
+    // no prefetched value is copied (a copy would wait for its load).
+    T ba2[2 * PA::P], bb2[2 * PB::P], bc2[2 * PC::P], bd2[2 * PD::P];
+    auto step = [&](int64_t e, const T* cba, const T* cbb, const T* cbc, const T* cbd, T* nba,
+                    T* nbb, T* nbc, T* nbd) {
         T* lm2 = L[(e - 2) & 3];
         T* lm1 = L[(e - 1) & 3];
         T* l0 = L[e & 3];
         T* lp1 = L[(e + 1) & 3];
         store_plane(n0, l0);
         store_plane(n1, lp1);
-        T ba_n[2 * PA::P], bb_n[2 * PB::P], bc_n[2 * PC::P], bd_n[2 * PD::P];
-        const bool more = e + 2 <= e_last;
-        if (more) {
+        if (e + 2 <= e_last) {
             load_plane(e + 2, n0);
             load_plane(e + 3, n1);
-            q1_load_b_pairs<T, PA::P>(b, g, e + 2, oa, fa, ba_n);
-            q1_load_b_pairs<T, PB::P>(b, g, e + 2, ob, fb, bb_n);
-            q1_load_b_pairs<T, PC::P>(b, g, e + 1, oc, fc, bc_n);
-            q1_load_b_pairs<T, PD::P>(b, g, e + 1, od, fd, bd_n);
+            q1_load_b_pairs<T, PA::P>(b, g, e + 2, oa, fa, nba);
+            q1_load_b_pairs<T, PB::P>(b, g, e + 2, ob, fb, nbb);
+            q1_load_b_pairs<T, PC::P>(b, g, e + 1, oc, fc, nbc);
+            q1_load_b_pairs<T, PD::P>(b, g, e + 1, od, fd, nbd);
         }
         __syncthreads();
         T ra[2 * PA::P], rb[2 * PB::P], rc[2 * PC::P], rd[2 * PD::P];
         const bool ab = e >= 1 && e <= g.nz;
         const bool wr_e = ab && e >= z0 && e < z1;
         T* dpe = dst + (ab ? e : 0) * g.sz;
-        q1_phase_pairs<T, W, PA::P>(ab, ca, ba, lm1, l0, lp1, fa, h2, ra);
+        q1_phase_pairs<T, W, PA::P>(ab, ca, cba, lm1, l0, lp1, fa, h2, ra);
         q1_store_pairs<T, PA::P>(wr_e, dpe, oa, fa, ra);
         __syncthreads();
-        q1_phase_pairs<T, W, PB::P>(ab, cb, bb, lm1, l0, lp1, fb, h2, rb);
+        q1_phase_pairs<T, W, PB::P>(ab, cb, cbb, lm1, l0, lp1, fb, h2, rb);
         q1_store_pairs<T, PB::P>(wr_e, dpe, ob, fb, rb);
         __syncthreads();
         const int64_t o = e - 1;
         const bool cdo = o >= z0 && o < z1 && o >= 1 && o <= g.nz;
         T* dpo = dst + (cdo ? o : 0) * g.sz;
-        q1_phase_pairs<T, W, PC::P>(cdo, cc, bc, lm2, lm1, l0, fc, h2, rc);
+        q1_phase_pairs<T, W, PC::P>(cdo, cc, cbc, lm2, lm1, l0, fc, h2, rc);
         q1_store_pairs<T, PC::P>(cdo, dpo, oc, fc, rc);
         __syncthreads();
-        q1_phase_pairs<T, W, PD::P>(cdo, cd, bd, lm2, lm1, l0, fd, h2, rd);
+        q1_phase_pairs<T, W, PD::P>(cdo, cd, cbd, lm2, lm1, l0, fd, h2, rd);
         q1_store_pairs<T, PD::P>(cdo, dpo, od, fd, rd);
         __syncthreads();
-        if (more) {
-#pragma unroll
-            for (int i = 0; i < 2 * PA::P; ++i) ba[i] = ba_n[i];
-#pragma unroll
-            for (int i = 0; i < 2 * PB::P; ++i) bb[i] = bb_n[i];
-#pragma unroll
-            for (int i = 0; i < 2 * PC::P; ++i) bc[i] = bc_n[i];
-#pragma unroll
-            for (int i = 0; i < 2 * PD::P; ++i) bd[i] = bd_n[i];
-        }
+    };
+    for (int64_t e = e_first; e <= e_last; e += 4) {
+        step(e, ba, bb, bc, bd, ba2, bb2, bc2, bd2);
+        if (e + 2 > e_last) break;
+        step(e + 2, ba2, bb2, bc2, bd2, ba, bb, bc, bd);
     }
 }
 
