@@ -45,9 +45,10 @@ def _args():
     p.add_argument("--per-colour", action="store_true",
                    help="run the GS rows as one launch per colour pass (no work array)")
     p.add_argument("--workload", default="poisson3d",
-                   choices=["poisson3d", "patches", "refine", "serve"],
+                   choices=["poisson3d", "patches", "refine", "serve", "expensive"],
                    help="poisson3d (default, the headline line); patches: 4096 batched patches; "
-                        "refine: FP32 sweeps in FP64 refinement to 1e-10; serve: request stream")
+                        "refine: FP32 sweeps in FP64 refinement to 1e-10; serve: request stream; "
+                        "expensive: sweeps with the S(k) stencil cost")
     p.add_argument("--tune", action="store_true", help="patches: run the tile autotuner first")
     p.add_argument("--refine-n", type=int, default=512, help="refine: interior edge")
     return p.parse_args()
@@ -424,6 +425,127 @@ def run_refine(a):
     print(json.dumps(out), flush=True)
 
 
+EXPENSIVE_CASES = (
+    # name, dim, stencil, interior n (x first), kmax, hetero
+    ("fd5_2d_k100", 2, 0, (2048, 2048), 100, 0),
+    ("fd5_2d_hetero", 2, 0, (2048, 2048), 100, 1),
+    ("q1_27_3d_k100", 3, 1, (128, 128, 128), 100, 0),
+    ("q1_27_3d_hetero", 3, 1, (128, 128, 128), 100, 1),
+)
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9  # lane-instructions per second
+
+
+def _expensive_counts(name, sha):
+    """FP64 flops per sweep of one expensive case from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "expensive_valu.txt")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except ValueError:
+        return None
+    rec = data.get(name)
+    if not rec or rec.get("source_sha") != sha:
+        return None
+    return rec
+
+
+def run_expensive(a):
+    """Gauss-Seidel sweeps with the expensive stencil evaluation S(k) (Sec. 2; the
+    load patterns of Sec. 4): every nonzero stencil entry costs k evaluations of
+    sin, with k = 100 everywhere or k running linearly 0..99 over the mesh.
+    2D 5-point on 2048^2 and 3D 27-point on 128^3, FP64, one launch per colour.
+    The iterate equals the k = 0 iterate bit for bit (tested)."""
+    import numpy as np
+    import torch
+
+    from paper_1810_04033_amd import colsten as C
+    from paper_1810_04033_amd import inputs as I
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    sweeps = 3
+    rows = {}
+    total_updates = 0
+    total_ms = 0.0
+    sha = _source_sha(["paper_1810_04033_amd/csrc/k_basic.hip", "paper_1810_04033_amd/csrc/cs_device.h"])
+    for name, dim, st, n, kmax, het in EXPENSIVE_CASES:
+        shape = tuple(reversed(n))
+        u = C.empty_grid(n)
+        b = C.empty_grid(n)
+        b.copy_(torch.from_numpy(I.halo_array(I.uniform_field(I.stream_seed(6, len(rows)), shape))))
+        g = C.Grid(u, b, dim=dim, stencil=st, h=1.0 / (max(n) + 1))
+        for _ in range(a.warmup):
+            g.gs_cost(1, kmax, hetero=bool(het))
+        torch.cuda.synchronize()
+        u.zero_()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(a.steps):
+            g.gs_cost(sweeps, kmax, hetero=bool(het))
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / (a.steps * sweeps)
+        pts = int(np.prod(n))
+        entries = (5 if st == 0 else 9) if dim == 2 else (7 if st == 0 else 21)
+        # sin evaluations per sweep: entries * sum over points of k(l)
+        if het:
+            ks = (kmax * np.arange(pts, dtype=np.int64)) // pts
+            sins = entries * int(ks.sum())
+        else:
+            sins = entries * kmax * pts
+        rec = _expensive_counts(name, sha)
+        rows[name] = {"grid": list(n), "stencil": ["fd", "q1"][st], "kmax": kmax, "hetero": bool(het),
+                      "ms_per_sweep": round(ms, 4), "GLUP/s": round(pts / ms / 1e6, 4),
+                      "Gsin/s": round(sins / ms / 1e6, 1),
+                      "fp64_TFLOP/s": None if rec is None else round(rec["fp64_flops_per_sweep"] / ms / 1e9, 2),
+                      "valu_issue_frac": None if rec is None else
+                      round(rec["valu_lane_instr_per_sweep"] / (ms * 1e-3) / VALU_ISSUE_PEAK, 4)}
+        total_updates += pts
+        total_ms += ms
+        g.close()
+        del u, b
+    dom = max(rows, key=lambda r: rows[r]["ms_per_sweep"])
+    achieved = rows[dom]["fp64_TFLOP/s"]
+    out = {
+        "metric": "GLUP/s (coloured GS with the expensive stencil evaluation S(k))",
+        "value": round(total_updates / total_ms / 1e6, 4), "unit": "GLUP/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(total_ms * sweeps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "S(k) sweeps: each nonzero stencil entry recomputed with k sin "
+                               "evaluations adding exact zeros; 2D 5-point 2048^2 and 3D 27-point "
+                               "128^3, k = 100 or k linear 0..99 over the mesh, FP64, %d sweeps "
+                               "per case per step" % sweeps},
+        "rows": rows,
+        "roofline": {"bound": "alu", "kernel": "colour_pass_cost_" + dom,
+                     "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": None if achieved is None else round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
+                     "traffic": None, "valu_issue_frac": rows[dom]["valu_issue_frac"],
+                     "source_sha": sha,
+                     "note": "FP64 flops and VALU lane-instructions per sweep from rocprofv3 "
+                             "SQ_INSTS_VALU* counters (profiles/expensive_valu.txt) over the live "
+                             "sweep time; VALU issue peak 256 CU x 4 SIMD x 16 lanes x 2.4 GHz"},
+    }
+    if not a.no_cpu_baseline:
+        from oracle import oracle as O
+        n = (2048, 256)
+        shape = tuple(reversed(n))
+        bh = I.halo_array(I.uniform_field(I.stream_seed(6, 0), shape))
+        uo = I.halo_array(np.zeros(shape))
+        t0 = time.perf_counter()
+        O.gs_sweeps_cost(uo, bh, 1, 100, 0, dim=2, stencil=O.FD, h=1.0 / 2049)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 2048 * 256 / dt / 1e9, "unit": "GLUP/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "one S(k) sweep, k = 100, 2D 5-point on 2048 x 256 (1/8 of "
+                                         "the fd5_2d_k100 grid), sequential C oracle, %.1f s" % dt}
+    print(json.dumps(out), flush=True)
+
+
 def run_serve(a):
     from paper_1810_04033_amd import serve as SV
     SV.bench_main(a)
@@ -441,6 +563,8 @@ def main():
         run_refine(a)
     elif a.workload == "serve":
         run_serve(a)
+    elif a.workload == "expensive":
+        run_expensive(a)
     else:
         run_poisson3d(a)
 

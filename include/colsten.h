@@ -101,8 +101,8 @@ cs_status cs_colour_pass(cs_grid g, int32_t colour, void* stream);
 /* nsweeps full Gauss-Seidel sweeps, each the colours 0..c-1 in order.
  * u_tmp: NULL, or a caller-owned device array with exactly u's layout.  With
  * u_tmp the library runs each sweep as one fused pass over memory that reads
- * u (or u_tmp) and writes the other array (same result as the colour passes,
- * up to rounding order); the halo of u_tmp is overwritten with u's halo, and
+ * u (or u_tmp) and writes the other array (the same iterate as the colour
+ * passes, rounded identically); the halo of u_tmp is overwritten with u's halo, and
  * the result ends in u.  Without u_tmp, each sweep is c in-place colour
  * passes.  nsweeps == 0 is a no-op.  Errors: CS_EINVAL (nsweeps < 0). */
 cs_status cs_gs_sweeps(cs_grid g, int32_t nsweeps, void* u_tmp, void* stream);
@@ -113,6 +113,18 @@ cs_status cs_gs_sweeps(cs_grid g, int32_t nsweeps, void* u_tmp, void* stream);
  * its halo is overwritten with u's halo.  The result ends in u.
  * Errors: CS_EINVAL (u_tmp NULL, nsweeps < 0, omega not finite). */
 cs_status cs_jacobi_sweeps(cs_grid g, double omega, int32_t nsweeps, void* u_tmp, void* stream);
+
+/* nsweeps Gauss-Seidel sweeps (colour passes 0..c-1, one launch each) with
+ * the expensive stencil evaluation S(k) of Sec. 2, sized as in Sec. 4: every
+ * nonzero stencil entry of every update is recomputed from k evaluations of
+ * sin whose contributions are exact zeros, so the iterate equals that of
+ * cs_gs_sweeps (without u_tmp) bit for bit while the arithmetic per update
+ * grows with k.  hetero == 0: k = kmax at every point; hetero == 1:
+ * k = floor(kmax * l / N) over the lexicographic interior index l of the N
+ * interior points (the load runs linearly over the mesh).
+ * Errors: CS_EINVAL (nsweeps < 0, kmax outside [0, 100000], hetero not 0/1). */
+cs_status cs_gs_sweeps_cost(cs_grid g, int32_t nsweeps, int32_t kmax, int32_t hetero,
+                            void* stream);
 
 /* Residual r_q = b_q - (S u)_q / h^2 over the interior.  r: NULL or a device
  * array with u's layout and dtype (halo untouched).  norms: device pointer to

@@ -329,6 +329,65 @@ void og_gs_sweeps_f32(int dim, int stencil, int parity, int64_t nx, int64_t ny,
 }
 
 /* ------------------------------------------------------------------ */
+/* Expensive stencil evaluation S(k) (Sec. 2; load patterns of Sec. 4)  */
+/* ------------------------------------------------------------------ */
+
+/* Sec. 2 lets every stencil entry cost k floating-point operations; Sec. 4
+ * realises it by adding k evaluations of sin to each prescribed entry, with k
+ * either fixed or running linearly over the mesh.  Here the added terms are
+ * z * sin(t a + j_o c), t = 1..k, with z = +0 and j_o = (oz+1)*9 + (oy+1)*3 +
+ * (ox+1) the entry's index: each is a signed zero for finite arguments, so
+ * S_o(k) == S_o exactly and the iterate is the k = 0 iterate, while the cost
+ * grows with k. */
+static double og_cost_entry(double w, int jo, int kq, double z, double a, double c)
+{
+    double s = w;
+    for (int t = 1; t <= kq; ++t) s = s + z * sin((double)t * a + (double)jo * c);
+    return s;
+}
+
+static void og_update_cost(const og_grid* g, double* u, const double* b, int64_t q, int kq,
+                           double z, double a, double c)
+{
+    int zr = g->dim == 3 ? 1 : 0;
+    double acc = 0.0;
+    for (int oz = -zr; oz <= zr; ++oz)
+        for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+                if (ox == 0 && oy == 0 && oz == 0) continue;
+                double w = og_weight(g->stencil, g->dim, ox, oy, oz);
+                if (w == 0.0) continue;
+                int jo = (oz + 1) * 9 + (oy + 1) * 3 + (ox + 1);
+                acc = fma(og_cost_entry(w, jo, kq, z, a, c), u[q + oz * g->sz + oy * g->sy + ox], acc);
+            }
+    double w0 = og_weight(g->stencil, g->dim, 0, 0, 0);
+    double x = (g->h * g->h * b[q] - acc) + (og_cost_entry(w0, 13, kq, z, a, c) - w0);
+    u[q] = og_over_centre(g->stencil, g->dim, x);
+}
+
+/* nsweeps sweeps with S(k): k = kmax everywhere (hetero = 0) or
+ * k = floor(kmax * l / N) over the lexicographic interior index l. */
+void og_gs_sweeps_cost_f64(int dim, int stencil, int parity, int64_t nx, int64_t ny,
+                           int64_t nz, int64_t sy, int64_t sz, double h,
+                           double* u, const double* b, int nsweeps, int kmax, int hetero,
+                           double z, double a, double c)
+{
+    og_grid g = og_make(dim, stencil, parity, nx, ny, nz, sy, sz, h);
+    int nc = og_num_colours(stencil, dim);
+    int64_t npts = g.nx * g.ny * g.nz;
+    for (int s = 0; s < nsweeps; ++s)
+        for (int col = 0; col < nc; ++col)
+            for (int64_t k = 1; k <= g.nz; ++k)
+                for (int64_t j = 1; j <= g.ny; ++j)
+                    for (int64_t i = 1; i <= g.nx; ++i) {
+                        if (og_colour(stencil, dim, parity, i, j, k) != col) continue;
+                        int64_t l = ((k - 1) * g.ny + (j - 1)) * g.nx + (i - 1);
+                        int kq = hetero ? (int)((int64_t)kmax * l / npts) : kmax;
+                        og_update_cost(&g, u, b, og_index(&g, i, j, k), kq, z, a, c);
+                    }
+}
+
+/* ------------------------------------------------------------------ */
 /* Weighted Jacobi (separate output array)                              */
 /* ------------------------------------------------------------------ */
 

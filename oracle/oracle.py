@@ -66,6 +66,8 @@ def _load():
     for name in ("og_gs_sweeps_f64", "og_gs_sweeps_f32"):
         getattr(lib, name).restype = None
         getattr(lib, name).argtypes = geo + [vp, vp, i32]
+    lib.og_gs_sweeps_cost_f64.restype = None
+    lib.og_gs_sweeps_cost_f64.argtypes = geo + [vp, vp, i32, i32, i32, f64, f64, f64]
     for name in ("og_jacobi_sweeps_f64", "og_jacobi_sweeps_f32"):
         getattr(lib, name).restype = None
         getattr(lib, name).argtypes = geo + [vp, vp, vp, f64, i32, i64]
@@ -162,6 +164,16 @@ def gs_sweeps(u, b, nsweeps, *, dim, stencil, h, parity=0):
     lib = _load()
     fn = lib.og_gs_sweeps_f64 if u.dtype == np.float64 else lib.og_gs_sweeps_f32
     fn(*_args(u, dim, stencil, parity, h), _ptr(u), _ptr(b), int(nsweeps))
+
+
+def gs_sweeps_cost(u, b, nsweeps, kmax, hetero, *, dim, stencil, h, parity=0,
+                   z=0.0, a=1.0 / 1024.0, c=1.0 / 128.0):
+    """FP64 sweeps with the expensive stencil evaluation S(k), in situ."""
+    _check_same(u, b)
+    assert u.dtype == np.float64
+    lib = _load()
+    lib.og_gs_sweeps_cost_f64(*_args(u, dim, stencil, parity, h), _ptr(u), _ptr(b), int(nsweeps),
+                              int(kmax), int(hetero), float(z), float(a), float(c))
 
 
 def _like(u):

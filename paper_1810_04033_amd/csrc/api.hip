@@ -249,6 +249,31 @@ cs_status cs_gs_sweeps(cs_grid g, int32_t nsweeps, void* u_tmp, void* stream)
     return CS_OK;
 }
 
+cs_status cs_gs_sweeps_cost(cs_grid g, int32_t nsweeps, int32_t kmax, int32_t hetero, void* stream)
+{
+    cs_status st = check_grid(g);
+    if (st != CS_OK) return st;
+    if (nsweeps < 0) { set_error("nsweeps must be >= 0"); return CS_EINVAL; }
+    if (kmax < 0 || kmax > 100000) { set_error("kmax %d outside [0, 100000]", kmax); return CS_EINVAL; }
+    if (hetero != 0 && hetero != 1) { set_error("hetero must be 0 or 1"); return CS_EINVAL; }
+    const int dt = g->d.dtype, dim = g->d.dim, sten = g->d.stencil;
+    const Geo& geo = g->geo;
+    StencilCost cost;
+    cost.kmax = kmax;
+    cost.hetero = hetero;
+    cost.npts = geo.nx * geo.ny * geo.nz;
+    cost.zero = 0.0;
+    cost.a = 1.0 / 1024.0;
+    cost.c = 1.0 / 128.0;
+    const int nc = sten == CS_FD ? 2 : (1 << dim);
+    for (int32_t it = 0; it < nsweeps; ++it)
+        for (int c = 0; c < nc; ++c)
+            if ((st = launch_colour_pass(dt, dim, sten, geo, g->u, g->b, h2_of(g), c,
+                                         (hipStream_t)stream, &cost)) != CS_OK)
+                return st;
+    return CS_OK;
+}
+
 cs_status cs_jacobi_sweeps(cs_grid g, double omega, int32_t nsweeps, void* u_tmp, void* stream)
 {
     cs_status st = check_grid(g);

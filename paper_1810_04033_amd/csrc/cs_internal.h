@@ -15,6 +15,16 @@ struct Geo {
     int parity;
 };
 
+// Cost of the expensive stencil evaluation S(k): kmax sin evaluations per
+// entry (hetero: linearly 0..kmax-1 over the lexicographic interior index of
+// npts points); zero, a, c are the run-time constants of the added terms.
+struct StencilCost {
+    int kmax;
+    int hetero;
+    int64_t npts;
+    double zero, a, c;
+};
+
 // Residual partial sums written by each block of the first reduction stage.
 struct Partial {
     double sum_r2;
@@ -34,7 +44,8 @@ cs_status check_launch(const char* what);
 // ---- launchers (kernels in k_basic.hip / k_fused.hip) --------------------
 // dtype 0 = double, 1 = float.  All return CS_OK or CS_EHIP.
 cs_status launch_colour_pass(int dtype, int dim, int stencil, const Geo& g, void* u,
-                             const void* b, double h2, int colour, hipStream_t s);
+                             const void* b, double h2, int colour, hipStream_t s,
+                             const StencilCost* cost = nullptr);
 cs_status launch_jacobi(int dtype, int dim, int stencil, const Geo& g, const void* src,
                         void* dst, const void* b, double h2, double omega, hipStream_t s);
 cs_status launch_halo_copy(int dtype, int dim, const Geo& g, const void* src, void* dst,

@@ -22,10 +22,28 @@ __host__ __device__ inline int64_t count_step2(int64_t i0, int64_t n)
     return i0 <= n ? (n - i0) / 2 + 1 : 0;
 }
 
-template <typename T, int DIM, int ST>
+__device__ __forceinline__ double sin_t(double x) { return sin(x); }
+__device__ __forceinline__ float sin_t(float x) { return sinf(x); }
+
+// Expensive stencil evaluation S(k) (Sec. 2 and Sec. 4): every nonzero entry
+// S_o used by an update is recomputed as S_o + sum_{t=1..k} zero * sin(t a + j_o c)
+// with j_o the entry's index and zero = +0, a, c run-time arguments.  For
+// finite arguments every added term is a signed zero, so S_o(k) equals S_o bit
+// for bit and the iterate is the k = 0 iterate, while each entry costs k sin
+// evaluations.  hetero: k = floor(kmax * l / N) over the lexicographic
+// interior index l (the load runs linearly over the mesh), else k = kmax.
+template <typename T>
+__device__ __forceinline__ T costly_entry(T w, int jo, int kq, T zero, T a, T c)
+{
+    T s = w;
+    for (int t = 1; t <= kq; ++t) s = s + zero * sin_t(T(t) * a + T(jo) * c);
+    return s;
+}
+
+template <typename T, int DIM, int ST, bool COST>
 __global__ void __launch_bounds__(kBX* kBY)
 k_colour_pass(T* __restrict__ u, const T* __restrict__ b, Geo g, T h2, int colour,
-              int64_t rows_y, int64_t rows_z, int64_t xblocks)
+              int64_t rows_y, int64_t rows_z, int64_t xblocks, StencilCost cost)
 {
     const int64_t bid = blockIdx.x;
     const int64_t xb = bid % xblocks;
@@ -50,7 +68,33 @@ k_colour_pass(T* __restrict__ u, const T* __restrict__ b, Geo g, T h2, int colou
     const int64_t q = (DIM == 3 ? k * g.sz : 0) + j * g.sy + i;
     const int64_t sy = g.sy, sz = g.sz;
     auto ld = [&](int ox, int oy, int oz) { return u[q + oz * sz + oy * sy + ox]; };
-    u[q] = gs_value<T, DIM, ST>(h2, b[q], ld);
+    if (!COST) {
+        u[q] = gs_value<T, DIM, ST>(h2, b[q], ld);
+        return;
+    }
+    int kq = cost.kmax;
+    if (cost.hetero) {
+        const int64_t l = ((DIM == 3 ? (k - 1) * g.ny : 0) + (j - 1)) * g.nx + (i - 1);
+        kq = (int)((int64_t)cost.kmax * l / cost.npts);
+    }
+    const T zero = (T)cost.zero, a = (T)cost.a, c = (T)cost.c;
+    // the ordered sum of gs_value with run-time entries S_o(k) == S_o
+    T acc = T(0);
+#pragma unroll
+    for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz)
+#pragma unroll
+        for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+            for (int ox = -1; ox <= 1; ++ox) {
+                if (ox == 0 && oy == 0 && oz == 0) continue;
+                const T w = weight<T, DIM, ST>(ox, oy, oz);
+                if (w == T(0)) continue;
+                const int jo = (oz + 1) * 9 + (oy + 1) * 3 + (ox + 1);
+                acc = fma_t(costly_entry(w, jo, kq, zero, a, c), ld(ox, oy, oz), acc);
+            }
+    const T w0 = weight<T, DIM, ST>(0, 0, 0);
+    const T x = (h2 * b[q] - acc) + (costly_entry(w0, 13, kq, zero, a, c) - w0);
+    u[q] = over_centre<T, DIM, ST>(x);
 }
 
 template <typename T, int DIM, int ST>
@@ -257,7 +301,7 @@ k_residual_finish(const Partial* __restrict__ partials, int count, double* __res
 
 template <typename T, int DIM, int ST>
 cs_status colour_pass_t(const Geo& g, void* u, const void* b, double h2, int colour,
-                        hipStream_t s)
+                        const StencilCost* cost, hipStream_t s)
 {
     int64_t rows_y, rows_z, xcount;
     if (ST == FD) {
@@ -278,8 +322,14 @@ cs_status colour_pass_t(const Geo& g, void* u, const void* b, double h2, int col
         set_error("colour pass: grid too large (%lld blocks)", (long long)blocks);
         return CS_EUNSUPPORTED;
     }
-    hipLaunchKernelGGL((k_colour_pass<T, DIM, ST>), dim3((unsigned)blocks), dim3(kBX, kBY), 0, s,
-                       (T*)u, (const T*)b, g, (T)h2, colour, rows_y, rows_z, xblocks);
+    if (cost)
+        hipLaunchKernelGGL((k_colour_pass<T, DIM, ST, true>), dim3((unsigned)blocks),
+                           dim3(kBX, kBY), 0, s, (T*)u, (const T*)b, g, (T)h2, colour, rows_y,
+                           rows_z, xblocks, *cost);
+    else
+        hipLaunchKernelGGL((k_colour_pass<T, DIM, ST, false>), dim3((unsigned)blocks),
+                           dim3(kBX, kBY), 0, s, (T*)u, (const T*)b, g, (T)h2, colour, rows_y,
+                           rows_z, xblocks, StencilCost{});
     return check_launch("colour pass");
 }
 
@@ -377,9 +427,10 @@ cs_status launch_residual_finish(const Partial* partials, int count, double* nor
 }
 
 cs_status launch_colour_pass(int dtype, int dim, int stencil, const Geo& g, void* u,
-                             const void* b, double h2, int colour, hipStream_t s)
+                             const void* b, double h2, int colour, hipStream_t s,
+                             const StencilCost* cost)
 {
-    CS_DISPATCH(colour_pass_t, dtype, dim, stencil, g, u, b, h2, colour, s);
+    CS_DISPATCH(colour_pass_t, dtype, dim, stencil, g, u, b, h2, colour, cost, s);
 }
 
 cs_status launch_jacobi(int dtype, int dim, int stencil, const Geo& g, const void* src,
