@@ -45,7 +45,10 @@ __global__ void __launch_bounds__(kBX* kBY)
 k_colour_pass(T* __restrict__ u, const T* __restrict__ b, Geo g, T h2, int colour,
               int64_t rows_y, int64_t rows_z, int64_t xblocks, StencilCost cost)
 {
-    const int64_t bid = blockIdx.x;
+    // With a load that grows along the mesh, the blocks are taken in reverse
+    // order: the dearest rows start first and the cheap ones fill in behind
+    // them (longest-first list scheduling by the hardware dispatcher).
+    const int64_t bid = (COST && cost.hetero) ? (int64_t)gridDim.x - 1 - blockIdx.x : blockIdx.x;
     const int64_t xb = bid % xblocks;
     const int64_t row = (bid / xblocks) * kBY + threadIdx.y;
     if (row >= rows_y * rows_z) return;
