@@ -45,10 +45,11 @@ def _args():
     p.add_argument("--per-colour", action="store_true",
                    help="run the GS rows as one launch per colour pass (no work array)")
     p.add_argument("--workload", default="poisson3d",
-                   choices=["poisson3d", "patches", "refine", "serve", "expensive"],
+                   choices=["poisson3d", "patches", "refine", "serve", "expensive", "orderings"],
                    help="poisson3d (default, the headline line); patches: 4096 batched patches; "
                         "refine: FP32 sweeps in FP64 refinement to 1e-10; serve: request stream; "
-                        "expensive: sweeps with the S(k) stencil cost")
+                        "expensive: sweeps with the S(k) stencil cost; orderings: lexicographic "
+                        "wavefront GS beside coloured GS")
     p.add_argument("--tune", action="store_true", help="patches: run the tile autotuner first")
     p.add_argument("--refine-n", type=int, default=512, help="refine: interior edge")
     return p.parse_args()
@@ -546,6 +547,92 @@ def run_expensive(a):
     print(json.dumps(out), flush=True)
 
 
+ORDERING_CASES = (
+    # name, dim, stencil, interior n (x first)
+    ("fd5_2d_256", 2, 0, (256, 256)),
+    ("q1_9_2d_256", 2, 1, (256, 256)),
+    ("fd7_3d_128", 3, 0, (128, 128, 128)),
+    ("q1_27_3d_128", 3, 1, (128, 128, 128)),
+)
+
+
+def run_orderings(a):
+    """Lexicographic Gauss-Seidel (the task-graph iterate of Sec. 3, run as
+    hyperplane wavefronts, one launch per hyperplane) beside the coloured sweeps
+    (one launch per colour, and the fused single pass where it exists), FP64,
+    on the 2D 256^2 grid of the small workload and a 3D 128^3 grid."""
+    import numpy as np
+    import torch
+
+    from paper_1810_04033_amd import colsten as C
+    from paper_1810_04033_amd import inputs as I
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    sweeps = 5
+    rows = {}
+    lex_ms = lex_pts = 0.0
+    for idx, (name, dim, st, n) in enumerate(ORDERING_CASES):
+        shape = tuple(reversed(n))
+        u = C.empty_grid(n)
+        b = C.empty_grid(n)
+        b.copy_(torch.from_numpy(I.halo_array(I.uniform_field(I.stream_seed(7, idx), shape))))
+        tmp = C.grid_like(u)
+        g = C.Grid(u, b, dim=dim, stencil=st, h=1.0 / (max(n) + 1))
+        modes = {"lexicographic_wavefront": lambda k: g.gs_lex(k),
+                 "coloured_per_colour": lambda k: g.gs(k)}
+        if g.fused:
+            modes["coloured_fused"] = lambda k: g.gs(k, tmp=tmp)
+        pts = int(np.prod(n))
+        row = {"grid": list(n)}
+        for mode, fn in modes.items():
+            fn(max(a.warmup, 1))
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(a.steps):
+                fn(sweeps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / (a.steps * sweeps)
+            row[mode] = {"ms_per_sweep": round(ms, 4), "GLUP/s": round(pts / ms / 1e6, 3)}
+            if mode == "lexicographic_wavefront":
+                lex_ms += ms
+                lex_pts += pts
+        wj, wk = (1, 1) if st == 0 else (2, 4)
+        row["launches_per_sweep_lexicographic"] = n[0] + wj * n[1] + (wk * n[2] if dim == 3 else 0) - (
+            wj + (wk if dim == 3 else 0))
+        rows[name] = row
+        g.close()
+        del u, b, tmp
+    out = {
+        "metric": "GLUP/s (lexicographic Gauss-Seidel by hyperplane wavefronts)",
+        "value": round(lex_pts / lex_ms / 1e6, 4), "unit": "GLUP/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(lex_ms * sweeps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "lexicographic GS (one launch per hyperplane) against coloured GS "
+                               "on 2D 256^2 and 3D 128^3, both stencils, FP64, %d sweeps per mode "
+                               "per step" % sweeps},
+        "rows": rows,
+    }
+    if not a.no_cpu_baseline:
+        from oracle import oracle as O
+        n = (128, 128, 16)
+        shape = tuple(reversed(n))
+        bh = I.halo_array(I.uniform_field(I.stream_seed(7, 2), shape))
+        uo = I.halo_array(np.zeros(shape))
+        t0 = time.perf_counter()
+        O.lex_sweeps(uo, bh, 5, dim=3, stencil=O.FD, h=1.0 / 129)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 5 * int(np.prod(n)) / dt / 1e9, "unit": "GLUP/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "5 lexicographic 7-point sweeps on 128 x 128 x 16, sequential "
+                                         "C oracle, %.2f s" % dt}
+    print(json.dumps(out), flush=True)
+
+
 def run_serve(a):
     from paper_1810_04033_amd import serve as SV
     SV.bench_main(a)
@@ -565,6 +652,8 @@ def main():
         run_serve(a)
     elif a.workload == "expensive":
         run_expensive(a)
+    elif a.workload == "orderings":
+        run_orderings(a)
     else:
         run_poisson3d(a)
 

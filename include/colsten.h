@@ -114,6 +114,15 @@ cs_status cs_gs_sweeps(cs_grid g, int32_t nsweeps, void* u_tmp, void* stream);
  * Errors: CS_EINVAL (u_tmp NULL, nsweeps < 0, omega not finite). */
 cs_status cs_jacobi_sweeps(cs_grid g, double omega, int32_t nsweeps, void* u_tmp, void* stream);
 
+/* nsweeps lexicographic Gauss-Seidel sweeps: the iterate of the sequential
+ * in-place loop in z-y-x order (x innermost), which the task graph of Sec. 3
+ * preserves; no colouring, so a different iterate from cs_gs_sweeps.  Run as
+ * hyperplane wavefronts, one launch per hyperplane s = i + j + k (2d+1-point
+ * stencils) or s = i + 2j + 4k (3^d-point; 2D drops k), in increasing s:
+ * about (1 + 1 + 1) n or (1 + 2 + 4) n launches per sweep for an n^3 grid.
+ * The grid's parity is ignored.  Errors: CS_EINVAL (nsweeps < 0). */
+cs_status cs_gs_sweeps_lex(cs_grid g, int32_t nsweeps, void* stream);
+
 /* nsweeps Gauss-Seidel sweeps (colour passes 0..c-1, one launch each) with
  * the expensive stencil evaluation S(k) of Sec. 2, sized as in Sec. 4: every
  * nonzero stencil entry of every update is recomputed from k evaluations of

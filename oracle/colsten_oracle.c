@@ -329,6 +329,37 @@ void og_gs_sweeps_f32(int dim, int stencil, int parity, int64_t nx, int64_t ny,
 }
 
 /* ------------------------------------------------------------------ */
+/* Lexicographic Gauss-Seidel (the task-graph iterate of Sec. 3)        */
+/* ------------------------------------------------------------------ */
+
+/* Sec. 3's task graph keeps the issue order of the sequential loop: every
+ * point is updated in place, z-y-x order with x innermost, from the newest
+ * values of all its neighbours.  No colouring: a different iterate. */
+void og_lex_sweeps_f64(int dim, int stencil, int parity, int64_t nx, int64_t ny,
+                       int64_t nz, int64_t sy, int64_t sz, double h,
+                       double* u, const double* b, int nsweeps)
+{
+    og_grid g = og_make(dim, stencil, parity, nx, ny, nz, sy, sz, h);
+    for (int s = 0; s < nsweeps; ++s)
+        for (int64_t k = 1; k <= g.nz; ++k)
+            for (int64_t j = 1; j <= g.ny; ++j)
+                for (int64_t i = 1; i <= g.nx; ++i)
+                    og_update(&g, u, b, og_index(&g, i, j, k));
+}
+
+void og_lex_sweeps_f32(int dim, int stencil, int parity, int64_t nx, int64_t ny,
+                       int64_t nz, int64_t sy, int64_t sz, double h,
+                       float* u, const float* b, int nsweeps)
+{
+    og_grid g = og_make(dim, stencil, parity, nx, ny, nz, sy, sz, h);
+    for (int s = 0; s < nsweeps; ++s)
+        for (int64_t k = 1; k <= g.nz; ++k)
+            for (int64_t j = 1; j <= g.ny; ++j)
+                for (int64_t i = 1; i <= g.nx; ++i)
+                    og_update_f32(&g, u, b, og_index(&g, i, j, k));
+}
+
+/* ------------------------------------------------------------------ */
 /* Expensive stencil evaluation S(k) (Sec. 2; load patterns of Sec. 4)  */
 /* ------------------------------------------------------------------ */
 

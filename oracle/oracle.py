@@ -66,6 +66,9 @@ def _load():
     for name in ("og_gs_sweeps_f64", "og_gs_sweeps_f32"):
         getattr(lib, name).restype = None
         getattr(lib, name).argtypes = geo + [vp, vp, i32]
+    for name in ("og_lex_sweeps_f64", "og_lex_sweeps_f32"):
+        getattr(lib, name).restype = None
+        getattr(lib, name).argtypes = geo + [vp, vp, i32]
     lib.og_gs_sweeps_cost_f64.restype = None
     lib.og_gs_sweeps_cost_f64.argtypes = geo + [vp, vp, i32, i32, i32, f64, f64, f64]
     for name in ("og_jacobi_sweeps_f64", "og_jacobi_sweeps_f32"):
@@ -164,6 +167,14 @@ def gs_sweeps(u, b, nsweeps, *, dim, stencil, h, parity=0):
     lib = _load()
     fn = lib.og_gs_sweeps_f64 if u.dtype == np.float64 else lib.og_gs_sweeps_f32
     fn(*_args(u, dim, stencil, parity, h), _ptr(u), _ptr(b), int(nsweeps))
+
+
+def lex_sweeps(u, b, nsweeps, *, dim, stencil, h):
+    """nsweeps lexicographic Gauss-Seidel sweeps (z-y-x order, in place)."""
+    _check_same(u, b)
+    lib = _load()
+    fn = lib.og_lex_sweeps_f64 if u.dtype == np.float64 else lib.og_lex_sweeps_f32
+    fn(*_args(u, dim, stencil, 0, h), _ptr(u), _ptr(b), int(nsweeps))
 
 
 def gs_sweeps_cost(u, b, nsweeps, kmax, hetero, *, dim, stencil, h, parity=0,

@@ -57,6 +57,7 @@ _SIGS = {
     "cs_jacobi_sweeps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32,
                                         ctypes.c_void_p, ctypes.c_void_p]),
     "cs_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cs_gs_sweeps_lex": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "cs_gs_sweeps_cost": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p]),
     "cs_ir_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
@@ -145,6 +146,10 @@ def cs_colour_pass(handle, colour, stream=None):
 def cs_gs_sweeps(handle, nsweeps, u_tmp_ptr=0, stream=None):
     _check(lib().cs_gs_sweeps(ctypes.c_void_p(handle), int(nsweeps), ctypes.c_void_p(u_tmp_ptr),
                               _stream(stream)))
+
+
+def cs_gs_sweeps_lex(handle, nsweeps, stream=None):
+    _check(lib().cs_gs_sweeps_lex(ctypes.c_void_p(handle), int(nsweeps), _stream(stream)))
 
 
 def cs_gs_sweeps_cost(handle, nsweeps, kmax, hetero=0, stream=None):
@@ -294,6 +299,10 @@ class Grid:
 
     def gs(self, nsweeps, tmp=None, stream=None):
         cs_gs_sweeps(self.handle, nsweeps, 0 if tmp is None else tmp.data_ptr(), stream)
+
+    def gs_lex(self, nsweeps, stream=None):
+        """Lexicographic Gauss-Seidel sweeps (hyperplane wavefronts)."""
+        cs_gs_sweeps_lex(self.handle, nsweeps, stream)
 
     def gs_cost(self, nsweeps, kmax, hetero=False, stream=None):
         """Sweeps with the expensive stencil evaluation S(k) (one launch per colour)."""

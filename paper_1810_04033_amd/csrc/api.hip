@@ -249,6 +249,18 @@ cs_status cs_gs_sweeps(cs_grid g, int32_t nsweeps, void* u_tmp, void* stream)
     return CS_OK;
 }
 
+cs_status cs_gs_sweeps_lex(cs_grid g, int32_t nsweeps, void* stream)
+{
+    cs_status st = check_grid(g);
+    if (st != CS_OK) return st;
+    if (nsweeps < 0) { set_error("nsweeps must be >= 0"); return CS_EINVAL; }
+    for (int32_t it = 0; it < nsweeps; ++it)
+        if ((st = launch_lex_sweep(g->d.dtype, g->d.dim, g->d.stencil, g->geo, g->u, g->b, h2_of(g),
+                                   (hipStream_t)stream)) != CS_OK)
+            return st;
+    return CS_OK;
+}
+
 cs_status cs_gs_sweeps_cost(cs_grid g, int32_t nsweeps, int32_t kmax, int32_t hetero, void* stream)
 {
     cs_status st = check_grid(g);

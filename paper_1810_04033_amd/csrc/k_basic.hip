@@ -100,6 +100,32 @@ k_colour_pass(T* __restrict__ u, const T* __restrict__ b, Geo g, T h2, int colou
     u[q] = over_centre<T, DIM, ST>(x);
 }
 
+// Lexicographic Gauss-Seidel by hyperplane wavefronts (the task-graph
+// iterate of Sec. 3).  With hyperplane index s = i + wj j + wk k, every
+// neighbour that precedes a point in the natural (z, y, x) order lies on a
+// smaller s and every later one on a larger s: (wj, wk) = (1, 1) for the
+// 2d+1-point stencils, (2, 4) for the 3^d-point ones (an offset (1, -1, 0)
+// precedes, 1 - wj < 0; (1, 1, -1) precedes, 1 + wj - wk < 0).  So the points
+// of one hyperplane are independent and one launch per s, in increasing s,
+// reproduces the sequential sweep.  One thread per (j, k); i follows.
+template <typename T, int DIM, int ST>
+__global__ void __launch_bounds__(256)
+k_lex_plane(T* __restrict__ u, const T* __restrict__ b, Geo g, T h2, int64_t s, int64_t k_lo,
+            int64_t nk)
+{
+    constexpr int64_t WJ = ST == FD ? 1 : 2, WK = ST == FD ? 1 : 4;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.ny * nk) return;
+    const int64_t j = 1 + t % g.ny;
+    const int64_t k = DIM == 3 ? k_lo + t / g.ny : 1;
+    const int64_t i = s - WJ * j - (DIM == 3 ? WK * k : 0);
+    if (i < 1 || i > g.nx) return;
+    const int64_t q = (DIM == 3 ? k * g.sz : 0) + j * g.sy + i;
+    const int64_t sy = g.sy, sz = g.sz;
+    auto ld = [&](int ox, int oy, int oz) { return u[q + oz * sz + oy * sy + ox]; };
+    u[q] = gs_value<T, DIM, ST>(h2, b[q], ld);
+}
+
 template <typename T, int DIM, int ST>
 __global__ void __launch_bounds__(kBX* kBY)
 k_jacobi(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict__ b, Geo g, T h2,
@@ -337,6 +363,36 @@ cs_status colour_pass_t(const Geo& g, void* u, const void* b, double h2, int col
 }
 
 template <typename T, int DIM, int ST>
+cs_status lex_sweep_t(const Geo& g, void* u, const void* b, double h2, hipStream_t s)
+{
+    const int64_t wj = ST == FD ? 1 : 2, wk = ST == FD ? 1 : 4;
+    const int64_t s_lo = 1 + wj + (DIM == 3 ? wk : 0);
+    const int64_t s_hi = g.nx + wj * g.ny + (DIM == 3 ? wk * g.nz : 0);
+    for (int64_t sp = s_lo; sp <= s_hi; ++sp) {
+        // planes k with some i in [1, nx] and j in [1, ny] on this hyperplane
+        int64_t k_lo = 1, k_hi = 1;
+        if (DIM == 3) {
+            const int64_t r_hi = sp - 1 - wj;              // wk k <= s - 1 - wj
+            const int64_t r_lo = sp - g.nx - wj * g.ny;    // wk k >= s - nx - wj ny
+            k_hi = r_hi / wk;
+            k_lo = r_lo <= wk ? 1 : (r_lo + wk - 1) / wk;
+            if (k_hi > g.nz) k_hi = g.nz;
+            if (k_lo > k_hi) continue;
+        }
+        const int64_t nk = k_hi - k_lo + 1;
+        const int64_t threads = g.ny * nk;
+        const int64_t blocks = (threads + 255) / 256;
+        if (blocks > 0x7fffffff) {
+            set_error("lexicographic sweep: grid too large");
+            return CS_EUNSUPPORTED;
+        }
+        hipLaunchKernelGGL((k_lex_plane<T, DIM, ST>), dim3((unsigned)blocks), dim3(256), 0, s,
+                           (T*)u, (const T*)b, g, (T)h2, sp, k_lo, nk);
+    }
+    return check_launch("lexicographic sweep");
+}
+
+template <typename T, int DIM, int ST>
 cs_status jacobi_t(const Geo& g, const void* src, void* dst, const void* b, double h2,
                    double omega, hipStream_t s)
 {
@@ -434,6 +490,12 @@ cs_status launch_colour_pass(int dtype, int dim, int stencil, const Geo& g, void
                              const StencilCost* cost)
 {
     CS_DISPATCH(colour_pass_t, dtype, dim, stencil, g, u, b, h2, colour, cost, s);
+}
+
+cs_status launch_lex_sweep(int dtype, int dim, int stencil, const Geo& g, void* u, const void* b,
+                           double h2, hipStream_t s)
+{
+    CS_DISPATCH(lex_sweep_t, dtype, dim, stencil, g, u, b, h2, s);
 }
 
 cs_status launch_jacobi(int dtype, int dim, int stencil, const Geo& g, const void* src,

@@ -104,6 +104,19 @@ def gs_sweep(u_ext_flat, b_int, dim, stencil, n, h, parity):
     return out
 
 
+def gs_sweep_lex(u_ext_flat, b_int, dim, stencil, n, h):
+    """One lexicographic Gauss-Seidel sweep: (D + L) u_new = h^2 b - A_IB g - U u_old
+    in the natural (x fastest) ordering."""
+    a_ii, a_ib, cols, bcols = split(dim, stencil, n)
+    rhs = h * h * b_int - a_ib @ u_ext_flat[bcols]
+    lower = np.tril(a_ii)
+    upper = a_ii - lower
+    u_new = sla.solve_triangular(lower, rhs - upper @ u_ext_flat[cols], lower=True)
+    out = u_ext_flat.copy()
+    out[cols] = u_new
+    return out
+
+
 def residual(u_ext_flat, b_int, dim, stencil, n, h):
     s = operator_ext(dim, stencil, n)
     return b_int - (s @ u_ext_flat) / (h * h)

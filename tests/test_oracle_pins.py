@@ -293,6 +293,34 @@ def test_gs_sweep_matches_dense_triangular_solve(dim, stencil, n, parity):
     assert _relmax(u.ravel(), ref) <= 1e-14
 
 
+@pytest.mark.parametrize("dim,stencil,n", GS_SHAPES)
+def test_lexicographic_sweep_matches_dense_triangular_solve(dim, stencil, n):
+    # Sec. 3's task graph keeps the sequential issue order: natural-ordering GS
+    h = 1.0 / (max(n) + 1)
+    u = _halo(_rand_interior(15, n[::-1]))
+    u[0] = 0.3
+    b = _halo(_rand_interior(16, n[::-1]))
+    ref = u.ravel().copy()
+    for _ in range(3):
+        ref = BF.gs_sweep_lex(ref, O.interior(b).ravel(), dim, stencil, n, h)
+    O.lex_sweeps(u, b, 3, dim=dim, stencil=stencil, h=h)
+    assert _relmax(u.ravel(), ref) <= 1e-14
+
+
+@pytest.mark.parametrize("dim,stencil,n", GS_SHAPES)
+def test_lexicographic_and_coloured_iterates_differ(dim, stencil, n):
+    if np.prod(n) < 4 or (stencil == O.Q1 and max(n) <= 2):
+        # with every point its own colour, colour order is the natural order
+        pytest.skip("the orderings coincide on this grid")
+    h = 1.0 / (max(n) + 1)
+    u = _halo(_rand_interior(17, n[::-1]))
+    b = _halo(_rand_interior(18, n[::-1]))
+    lex, col = u.copy(), u.copy()
+    O.lex_sweeps(lex, b, 1, dim=dim, stencil=stencil, h=h)
+    O.gs_sweeps(col, b, 1, dim=dim, stencil=stencil, h=h)
+    assert not np.array_equal(lex, col)
+
+
 @pytest.mark.parametrize("dim,stencil", CASES)
 def test_order_inside_a_colour_does_not_matter(dim, stencil):
     n = (6, 5, 4)[:dim]
