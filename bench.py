@@ -560,7 +560,8 @@ def run_orderings(a):
     """Lexicographic Gauss-Seidel (the task-graph iterate of Sec. 3, run as
     hyperplane wavefronts, one launch per hyperplane) beside the coloured sweeps
     (one launch per colour, and the fused single pass where it exists), FP64,
-    on the 2D 256^2 grid of the small workload and a 3D 128^3 grid."""
+    on the 2D 256^2 grid of the small workload and a 3D 128^3 grid; the
+    launch-per-kernel modes also as captured HIP graphs of 5 sweeps."""
     import numpy as np
     import torch
 
@@ -579,14 +580,20 @@ def run_orderings(a):
         b.copy_(torch.from_numpy(I.halo_array(I.uniform_field(I.stream_seed(7, idx), shape))))
         tmp = C.grid_like(u)
         g = C.Grid(u, b, dim=dim, stencil=st, h=1.0 / (max(n) + 1))
+        graphs = {"lexicographic_wavefront_graph": C.Graph.of_grid(g, sweeps, lexicographic=True),
+                  "coloured_per_colour_graph": C.Graph.of_grid(g, sweeps)}
         modes = {"lexicographic_wavefront": lambda k: g.gs_lex(k),
-                 "coloured_per_colour": lambda k: g.gs(k)}
+                 "lexicographic_wavefront_graph": lambda k: [graphs["lexicographic_wavefront_graph"].launch()
+                                                             for _ in range(k // sweeps)],
+                 "coloured_per_colour": lambda k: g.gs(k),
+                 "coloured_per_colour_graph": lambda k: [graphs["coloured_per_colour_graph"].launch()
+                                                         for _ in range(k // sweeps)]}
         if g.fused:
             modes["coloured_fused"] = lambda k: g.gs(k, tmp=tmp)
         pts = int(np.prod(n))
         row = {"grid": list(n)}
         for mode, fn in modes.items():
-            fn(max(a.warmup, 1))
+            fn(sweeps * max(a.warmup, 1))
             torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -604,6 +611,8 @@ def run_orderings(a):
         row["launches_per_sweep_lexicographic"] = n[0] + wj * n[1] + (wk * n[2] if dim == 3 else 0) - (
             wj + (wk if dim == 3 else 0))
         rows[name] = row
+        for gr in graphs.values():
+            gr.close()
         g.close()
         del u, b, tmp
     out = {

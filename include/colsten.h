@@ -192,6 +192,31 @@ cs_status cs_batch_residual(cs_batch bt, double* norms, void* stream);
  * for a bad stencil or dtype, or small_max > mid_max. */
 cs_status cs_batch_tile_policy(int32_t stencil, int32_t dtype, int32_t small_max, int32_t mid_max);
 
+/* ---- Captured sweep sequences (HIP graphs) -------------------------------
+ * A fixed number of sweeps recorded once into a HIP graph and replayed with
+ * one launch call, for callers that repeat the same sweeps many times on small
+ * grids, batches or the hyperplane wavefronts, where per-kernel launch cost
+ * dominates.  The graph captures the grid's (or batch's) arrays, which must
+ * stay allocated until cs_graph_destroy; each launch continues from the
+ * current contents of u.  Capture uses a private stream of the library and
+ * records kernel nodes only. */
+typedef struct cs_graph_s* cs_graph;
+
+/* Record nsweeps sweeps of g: cs_gs_sweeps(g, nsweeps, u_tmp) if
+ * lexicographic == 0, cs_gs_sweeps_lex(g, nsweeps) if 1 (u_tmp must then be
+ * NULL).  Errors: CS_EINVAL (nsweeps < 1, bad flag), the errors of the
+ * recorded call, CS_EHIP if capture or instantiation fails. */
+cs_status cs_graph_gs(cs_grid g, int32_t nsweeps, void* u_tmp, int32_t lexicographic, cs_graph* out);
+
+/* Record cs_batch_gs_sweeps(bt, nsweeps). */
+cs_status cs_graph_batch_gs(cs_batch bt, int32_t nsweeps, cs_graph* out);
+
+/* Enqueue one replay on stream (same device as the capture). */
+cs_status cs_graph_launch(cs_graph gr, void* stream);
+
+/* Release the graph.  NULL is a no-op; pending replays must have finished. */
+cs_status cs_graph_destroy(cs_graph gr);
+
 /* *out = 1 if cs_gs_sweeps with a work array runs this grid's sweeps as fused
  * single passes, 0 if it falls back to one launch per colour. */
 cs_status cs_gs_fused(cs_grid g, int32_t* out);

@@ -70,6 +70,11 @@ _SIGS = {
     "cs_batch_gs_sweeps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "cs_batch_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "cs_batch_tile_policy": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "cs_graph_gs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_void_p)]),
+    "cs_graph_batch_gs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+    "cs_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "cs_graph_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "cs_last_error": (ctypes.c_char_p, []),
 }
 
@@ -316,6 +321,42 @@ class Grid:
         out = self.norms if norms is None else norms
         cs_residual(self.handle, 0 if r is None else r.data_ptr(), out.data_ptr(), stream)
         return out
+
+
+class Graph:
+    """A captured sequence of sweeps (HIP graph); launch() replays it."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep  # the captured arrays stay referenced while the graph lives
+
+    @classmethod
+    def of_grid(cls, grid, nsweeps, tmp=None, lexicographic=False):
+        h = ctypes.c_void_p()
+        _check(lib().cs_graph_gs(ctypes.c_void_p(grid.handle), int(nsweeps),
+                                 ctypes.c_void_p(0 if tmp is None else tmp.data_ptr()),
+                                 1 if lexicographic else 0, ctypes.byref(h)))
+        return cls(h.value, (grid, tmp))
+
+    @classmethod
+    def of_batch(cls, batch, nsweeps):
+        h = ctypes.c_void_p()
+        _check(lib().cs_graph_batch_gs(ctypes.c_void_p(batch.handle), int(nsweeps), ctypes.byref(h)))
+        return cls(h.value, (batch,))
+
+    def launch(self, stream=None):
+        _check(lib().cs_graph_launch(ctypes.c_void_p(self.handle), _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            _check(lib().cs_graph_destroy(ctypes.c_void_p(self.handle)))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:
