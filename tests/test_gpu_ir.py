@@ -92,3 +92,31 @@ def test_refinement_rejects_bad_arguments():
                    C.empty_grid((8, 8, 8), dtype=torch.float32), dim=3, stencil=C.CS_Q1, h=1.0 / 9)
     with pytest.raises(C.ColstenError):
         C.cs_ir_update(g64.handle, other.handle, 1.0)
+
+
+def test_config_refinement_512_full_size():
+    """The mixed-precision workload at its full size (512^3, 27-point,
+    Fourier + noise RHS of seed 4), in the launch configuration the benchmark
+    times (fused sweeps with work arrays): one FP64 sweep, and one refinement
+    step with one FP32 inner sweep, element by element against the oracle."""
+    n, h = 512, 1.0 / 513
+    st = C.CS_Q1
+    b_host = I.halo_array(I.fourier_field(4, n))
+    # FP64 fused sweep from u0 = 0
+    g64, g32 = _grids(b_host, 3, st, h)
+    tmp = C.grid_like(g64.u)
+    g64.gs(1, tmp=tmp)
+    torch.cuda.synchronize()
+    uo = np.zeros_like(b_host)
+    O.gs_sweeps(uo, b_host, 1, dim=3, stencil=st, h=h)
+    assert G.relmax(G.download(g64.u), uo) <= 1e-13
+    del tmp, uo
+    # one refinement step: FP64 residual and scaled FP32 copy, one FP32 sweep, FP64 update
+    g64.u.zero_()
+    tmp32 = C.grid_like(g32.u)
+    res = S.ir_solve(g64, g32, 0.0, inner_sweeps=1, tmp32=tmp32, max_outer=1)
+    x_ref, hist_ref, it_ref = O.ir_solve(b_host, 0.0, dim=3, stencil=st, h=h,
+                                         inner_sweeps=1, max_outer=1)
+    assert res.outer == it_ref == 1
+    assert G.relmax(G.download(g64.u), x_ref) <= 1e-13
+    np.testing.assert_allclose(res.history, hist_ref, rtol=1e-11)
