@@ -26,6 +26,8 @@
 #pragma once
 
 #include "cs_device.h"
+
+#include <type_traits>
 #include "cs_internal.h"
 
 namespace cs {
@@ -397,7 +399,11 @@ __device__ __forceinline__ void q1_3_tile(const T* __restrict__ src, T* __restri
 }
 
 // ---------------------------------------------------------------------------
-// The same 27-point sweep with two x-adjacent points per thread.
+// The same 27-point sweep with two x-adjacent points per thread.  The finished
+// planes leave through LDS: the tile's rows of planes e-1 and e, final after
+// double step e, are stored during double step e+2 by whole wavefronts per row
+// (full cache lines), instead of each pair storing its two points.  A fifth
+// LDS slot keeps them until then.
 //
 // Points of one row phase are taken in pairs (x, x+1) whose left neighbour
 // column x-1 is even in LDS, over the full width of T+3 in every phase (the
@@ -460,47 +466,55 @@ __device__ __forceinline__ void q1_load_b_pairs(const T* __restrict__ b, const G
 template <typename T, int W, int P>
 __device__ __forceinline__ void q1_phase_pairs(bool active, const int* pc, const T* bv,
                                                const T* lm, T* lk, const T* lp, const int* pfl,
-                                               T h2, T* out)
+                                               T h2)
 {
+    // The two points of a pair form the lanes of a 2-vector: the terms with
+    // ox = -1 and ox = +1 are the aligned column pairs (x-1, x) and (x+1, x+2)
+    // as loaded, the ox = 0 term is (x, x+1).  Each lane runs the ordered
+    // fused multiply-add chain of gs_value (same offsets, same weights), so
+    // both points round exactly as the single-point form.
+    typedef T v2 __attribute__((ext_vector_type(2)));
     if (!active) return;
 #pragma unroll
     for (int i = 0; i < P; ++i) {
         const int c = pc[i];
         if (c < 0) continue;
-        T v[3][3][4];
+        v2 lo[3][3], hi[3][3];  // columns (x-1, x) and (x+1, x+2) of each row
 #pragma unroll
         for (int oz = -1; oz <= 1; ++oz) {
             const T* pl = oz < 0 ? lm : (oz > 0 ? lp : lk);
 #pragma unroll
             for (int oy = -1; oy <= 1; ++oy) {
                 if (oz == 0 && oy == 0) continue;
-                const int base = c - 1 + oy * W;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) v[oz + 1][oy + 1][k] = pl[base + k];
+                // c - 1 and W are even: 16-byte aligned for FP64
+                const v2* row = reinterpret_cast<const v2*>(pl + (c - 1 + oy * W));
+                lo[oz + 1][oy + 1] = row[0];
+                hi[oz + 1][oy + 1] = row[1];
             }
         }
-        auto ld0 = [&](int ox, int oy, int oz) -> T { return v[oz + 1][oy + 1][ox + 1]; };
-        auto ld1 = [&](int ox, int oy, int oz) -> T { return v[oz + 1][oy + 1][ox + 2]; };
-        const T a0 = gs_value<T, 3, Q1>(h2, bv[2 * i], ld0);
-        const T a1 = gs_value<T, 3, Q1>(h2, bv[2 * i + 1], ld1);
+        v2 acc = {T(0), T(0)};
+#pragma unroll
+        for (int oz = -1; oz <= 1; ++oz)
+#pragma unroll
+            for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+                for (int ox = -1; ox <= 1; ++ox) {
+                    if (ox == 0 && oy == 0 && oz == 0) continue;
+                    const T w = weight<T, 3, Q1>(ox, oy, oz);
+                    if (w == T(0)) continue;
+                    const v2 a = lo[oz + 1][oy + 1], bb = hi[oz + 1][oy + 1];
+                    const v2 val = ox < 0 ? a : (ox > 0 ? bb : (v2){a.y, bb.x});
+                    const v2 wv = {w, w};
+                    acc = __builtin_elementwise_fma(wv, val, acc);
+                }
+        const v2 bq = {bv[2 * i], bv[2 * i + 1]};
+        const v2 h2v = {h2, h2};
+        const v2 x = h2v * bq - acc;
+        const T a0 = over_centre<T, 3, Q1>(x.x);
+        const T a1 = over_centre<T, 3, Q1>(x.y);
         const int fl = pfl[i];
         if (fl & 1) lk[c] = a0;
         if (fl & 2) lk[c + 1] = a1;
-        out[2 * i] = a0;
-        out[2 * i + 1] = a1;
-    }
-}
-
-// Writes the tile points of one row phase (flags bit2/bit3) to dp.
-template <typename T, int P>
-__device__ __forceinline__ void q1_store_pairs(bool write, T* dp, const int* poff, const int* pfl,
-                                               const T* out)
-{
-    if (!write) return;
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-        if (pfl[i] & 4) st_stream(dp + poff[i], out[2 * i]);
-        if (pfl[i] & 8) st_stream(dp + poff[i] + 1, out[2 * i + 1]);
     }
 }
 
@@ -516,10 +530,39 @@ __device__ __forceinline__ void q1_3_tile_pairs(const T* __restrict__ src, T* __
     using PB = Q1Pairs<TX, TY, NT, 2>;
     using PC = Q1Pairs<TX, TY, NT, 1>;
     using PD = Q1Pairs<TX, TY, NT, 0>;
-    __shared__ __attribute__((aligned(16))) T L[4][NCOL];
+    // five plane slots: the planes e-2 .. e+1 a double step reads, and the
+    // finished planes e-1 and e of the previous double step, which are written
+    // out from LDS while the next step already fills its own two slots
+    constexpr int NS = 5;
+    __shared__ __attribute__((aligned(16))) T L[NS][NCOL];
     const int64_t x0 = tb.x0, y0 = tb.y0, z0 = tb.z0, z1 = tb.z1;
+    auto slot = [&](int64_t p) -> T* {
+        const int k = (int)(p - z0 + 3 * NS) % NS;  // p >= z0 - 3
+        return (T*)__builtin_assume_aligned(L[k], 16);
+    };
     const int tid = threadIdx.x;
     const int par = g.parity;
+
+    // output points of the tile, whole rows per wavefront: LDS index and
+    // in-plane offset; bit i of omask marks a point inside the grid
+    constexpr int PO = (TX * TY + NT - 1) / NT;
+    static_assert(PO <= 32, "output mask is 32 bits");
+    int olds[PO], oglb[PO];
+    unsigned omask = 0;
+#pragma unroll
+    for (int i = 0; i < PO; ++i) {
+        const int p = tid + NT * i;
+        const int ty = p / TX, tx = p % TX;
+        const bool ok = p < TX * TY && x0 + tx <= g.nx && y0 + ty <= g.ny;
+        olds[i] = (4 + ty) * W + 4 + tx;
+        oglb[i] = ok ? (int)((y0 + ty) * g.sy + x0 + tx) : 0;
+        omask |= ok ? 1u << i : 0u;
+    }
+    auto write_plane = [&](const T* lp, T* dp) {
+#pragma unroll
+        for (int i = 0; i < PO; ++i)
+            if ((omask >> i) & 1u) st_stream(dp + oglb[i], lp[olds[i]]);
+    };
 
     int coff[M];
 #pragma unroll
@@ -560,7 +603,7 @@ __device__ __forceinline__ void q1_3_tile_pairs(const T* __restrict__ src, T* __
     {
         T t[M];
         load_plane(e_first - 1, t);
-        store_plane(t, L[(e_first - 1) & 3]);
+        store_plane(t, slot(e_first - 1));
     }
     load_plane(e_first, n0);
     load_plane(e_first + 1, n1);
@@ -573,12 +616,16 @@ __device__ __forceinline__ void q1_3_tile_pairs(const T* __restrict__ src, T* __
     // step's loaded into nb*; the loop alternates the two register sets, so
     // no prefetched value is copied (a copy would wait for its load).
     T ba2[2 * PA::P], bb2[2 * PB::P], bc2[2 * PC::P], bd2[2 * PD::P];
+    // planes finished by the previous double step, written out during the
+    // next one (after its first barrier) so that the stores have a whole step
+    // to drain before the next wait on the prefetched loads
+    int64_t pend_e = -1, pend_o = -1;
     auto step = [&](int64_t e, const T* cba, const T* cbb, const T* cbc, const T* cbd, T* nba,
                     T* nbb, T* nbc, T* nbd) {
-        T* lm2 = L[(e - 2) & 3];
-        T* lm1 = L[(e - 1) & 3];
-        T* l0 = L[e & 3];
-        T* lp1 = L[(e + 1) & 3];
+        T* lm2 = slot(e - 2);
+        T* lm1 = slot(e - 1);
+        T* l0 = slot(e);
+        T* lp1 = slot(e + 1);
         store_plane(n0, l0);
         store_plane(n1, lp1);
         if (e + 2 <= e_last) {
@@ -590,31 +637,31 @@ __device__ __forceinline__ void q1_3_tile_pairs(const T* __restrict__ src, T* __
             q1_load_b_pairs<T, PD::P>(b, g, e + 1, od, fd, nbd);
         }
         __syncthreads();
-        T ra[2 * PA::P], rb[2 * PB::P], rc[2 * PC::P], rd[2 * PD::P];
+        if (pend_e >= 0) write_plane(slot(pend_e), dst + pend_e * g.sz);
+        if (pend_o >= 0) write_plane(slot(pend_o), dst + pend_o * g.sz);
         const bool ab = e >= 1 && e <= g.nz;
-        const bool wr_e = ab && e >= z0 && e < z1;
-        T* dpe = dst + (ab ? e : 0) * g.sz;
-        q1_phase_pairs<T, W, PA::P>(ab, ca, cba, lm1, l0, lp1, fa, h2, ra);
-        q1_store_pairs<T, PA::P>(wr_e, dpe, oa, fa, ra);
+        q1_phase_pairs<T, W, PA::P>(ab, ca, cba, lm1, l0, lp1, fa, h2);
         __syncthreads();
-        q1_phase_pairs<T, W, PB::P>(ab, cb, cbb, lm1, l0, lp1, fb, h2, rb);
-        q1_store_pairs<T, PB::P>(wr_e, dpe, ob, fb, rb);
+        q1_phase_pairs<T, W, PB::P>(ab, cb, cbb, lm1, l0, lp1, fb, h2);
         __syncthreads();
         const int64_t o = e - 1;
         const bool cdo = o >= z0 && o < z1 && o >= 1 && o <= g.nz;
-        T* dpo = dst + (cdo ? o : 0) * g.sz;
-        q1_phase_pairs<T, W, PC::P>(cdo, cc, cbc, lm2, lm1, l0, fc, h2, rc);
-        q1_store_pairs<T, PC::P>(cdo, dpo, oc, fc, rc);
+        q1_phase_pairs<T, W, PC::P>(cdo, cc, cbc, lm2, lm1, l0, fc, h2);
         __syncthreads();
-        q1_phase_pairs<T, W, PD::P>(cdo, cd, cbd, lm2, lm1, l0, fd, h2, rd);
-        q1_store_pairs<T, PD::P>(cdo, dpo, od, fd, rd);
+        q1_phase_pairs<T, W, PD::P>(cdo, cd, cbd, lm2, lm1, l0, fd, h2);
         __syncthreads();
+        // planes e (rows A, B) and e-1 (rows C, D) are final; their slots are
+        // not refilled before the top of double step e+4
+        pend_e = (ab && e >= z0 && e < z1) ? e : -1;
+        pend_o = cdo ? o : -1;
     };
     for (int64_t e = e_first; e <= e_last; e += 4) {
         step(e, ba, bb, bc, bd, ba2, bb2, bc2, bd2);
         if (e + 2 > e_last) break;
         step(e + 2, ba2, bb2, bc2, bd2, ba, bb, bc, bd);
     }
+    if (pend_e >= 0) write_plane(slot(pend_e), dst + pend_e * g.sz);
+    if (pend_o >= 0) write_plane(slot(pend_o), dst + pend_o * g.sz);
 }
 
 }  // namespace cs
