@@ -97,11 +97,33 @@ __device__ __forceinline__ void fd3_tile(const T* __restrict__ src, T* __restric
     // two LDS buffer sets (planes k and k-1), alternating with the step parity,
     // so one barrier per plane step suffices
     __shared__ T lds[2][2][NCOL];
+    // final values of plane k-1 (tile T only), written at step k and stored to
+    // dst by whole rows at step k+1, alternating with the step parity
+    __shared__ T lout[2][TX * TY];
     const int64_t x0 = tb.x0, y0 = tb.y0, z0 = tb.z0, z1 = tb.z1;
     const int tid = threadIdx.x;
 
+    constexpr int PO = (TX * TY + NT - 1) / NT;
+    static_assert(PO <= 32, "output mask is 32 bits");
+    int oglb[PO];
+    unsigned omask = 0;
+#pragma unroll
+    for (int i = 0; i < PO; ++i) {
+        const int p = tid + NT * i;
+        const int ty = p / TX, tx = p % TX;
+        const bool ok = p < TX * TY && x0 + tx <= g.nx && y0 + ty <= g.ny;
+        oglb[i] = ok ? (int)((y0 + ty) * g.sy + x0 + tx) : 0;
+        omask |= ok ? 1u << i : 0u;
+    }
+    auto write_rows = [&](const T* lo, T* dp) {
+#pragma unroll
+        for (int i = 0; i < PO; ++i)
+            if ((omask >> i) & 1u) st_stream(dp + oglb[i], lo[tid + NT * i]);
+    };
+
     int off[M];   // y*sy + x of the column (32-bit: checked on the host)
     int flags[M]; // bit0 valid, bit1 interior in T+1, bit2 interior in T, bit3 colour parity
+    int oidx[M];  // index of the column in the tile T (row-major), for the output rows
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int c = tid + NT * m;
@@ -114,6 +136,7 @@ __device__ __forceinline__ void fd3_tile(const T* __restrict__ src, T* __restric
         const int par = (int)(((x - 1) + (y - 1) + g.parity) & 1);
         flags[m] = (valid ? 1 : 0) | (t1 ? 2 : 0) | (t0 ? 4 : 0) | (par << 3);
         off[m] = valid ? (int)(y * g.sy + x) : 0;
+        oidx[m] = (ly - 2) * TX + (lx - 2);
     }
 
     // register rings: the slot of plane p is (p - z0 + 3) mod R for u and b
@@ -166,6 +189,8 @@ __device__ __forceinline__ void fd3_tile(const T* __restrict__ src, T* __restric
                 }
             }
             __syncthreads();
+            // plane k-2, finished at step k-1
+            if (k - 2 >= z0 && k - 2 < z1) write_rows(lout[(k - 1) & 1], dst + (k - 2) * g.sz);
             const bool do_red = k >= 1 && k <= g.nz;
             const bool do_black = k - 1 >= z0 && k - 1 < z1;
             const int kc = (int)((k - 1) & 1);
@@ -181,7 +206,7 @@ __device__ __forceinline__ void fd3_tile(const T* __restrict__ src, T* __restric
                     u_k[m] = gs_value<T, 3, FD>(h2, b_k[m], ld);
                 }
             }
-            T* dp = dst + (k - 1) * g.sz;
+            T* lo = lout[k & 1];
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 const int c = tid + NT * m;
@@ -194,10 +219,13 @@ __device__ __forceinline__ void fd3_tile(const T* __restrict__ src, T* __restric
                     };
                     u_km1[m] = gs_value<T, 3, FD>(h2, b_km1[m], ld);
                 }
-                if (do_black && (flags[m] & 4)) st_stream(dp + off[m], u_km1[m]);
+                if (do_black && (flags[m] & 4)) lo[oidx[m]] = u_km1[m];
             }
         }
     }
+    // the last plane, z1 - 1, was finished at step z1
+    __syncthreads();
+    if (z1 - 1 >= z0) write_rows(lout[z1 & 1], dst + (z1 - 1) * g.sz);
 }
 
 // ---------------------------------------------------------------------------
