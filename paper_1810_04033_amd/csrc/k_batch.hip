@@ -60,7 +60,7 @@ k_batch_q1_3(const BatchPatch* __restrict__ tab, int count, int phase)
     const TileBox tb = tile_box<TX, TY>(P.g, P.tiles_x, P.tiles_y, P.chunks, w - P.item_begin);
     const T* src = (const T*)(phase ? P.tmp : P.u);
     T* dst = (T*)(phase ? P.u : P.tmp);
-    q1_3_tile<T, TX, TY, NT>(src, dst, (const T*)P.b, P.g, (T)P.h2, tb);
+    q1_3_tile_pairs<T, TX, TY, NT>(src, dst, (const T*)P.b, P.g, (T)P.h2, tb);
 }
 
 // Halo copy u -> tmp, one workgroup per patch.
@@ -232,13 +232,13 @@ cs_status launch_batch_sweep(int dtype, int stencil, int variant, const BatchPat
         }
     } else {
         if (dtype == 0) {
-            if (variant == 0) CS_BQ1(double, 16, 8, 256, 3);
-            else if (variant == 1) CS_BQ1(double, 32, 16, 512, 3);
-            else CS_BQ1(double, 64, 16, 512, 3);
+            if (variant == 0) CS_BQ1(double, 16, 8, 128, 2);
+            else if (variant == 1) CS_BQ1(double, 32, 16, 256, 2);
+            else CS_BQ1(double, 64, 16, 256, 2);
         } else {
-            if (variant == 0) CS_BQ1(float, 16, 8, 256, 3);
-            else if (variant == 1) CS_BQ1(float, 32, 16, 512, 3);
-            else CS_BQ1(float, 64, 16, 512, 3);
+            if (variant == 0) CS_BQ1(float, 16, 8, 128, 2);
+            else if (variant == 1) CS_BQ1(float, 32, 16, 256, 2);
+            else CS_BQ1(float, 64, 16, 256, 2);
         }
     }
 #undef CS_BFD
