@@ -1,8 +1,9 @@
 """The pins must catch plausible mistakes in the oracle.
 
 Each case copies the oracle's C source, plants one mistake (a dropped term, a
-wrong sign, a transposed index, a wrong colour, a misplaced weight), compiles
-the copy on the CPU and runs the pin suite against it.  The suite has to fail.
+wrong sign, a transposed index, a wrong colour, a misplaced weight, a wrong
+sweep order, a nonzero cost term), compiles the copy on the CPU and runs the
+pin suites against it.  They have to fail.
 """
 import os
 import subprocess
@@ -50,6 +51,12 @@ MUTANTS = {
     "neumaier_compensation_sign": (
         "if (fabs(*s) >= fabs(x)) *c += (*s - t) + x;",
         "if (fabs(*s) >= fabs(x)) *c += (t - *s) + x;"),
+    "lex_sweep_reversed_x": (
+        "                for (int64_t i = 1; i <= g.nx; ++i)\n                    og_update(&g, u, b, og_index(&g, i, j, k));",
+        "                for (int64_t i = g.nx; i >= 1; --i)\n                    og_update(&g, u, b, og_index(&g, i, j, k));"),
+    "cost_terms_not_zero": (
+        "s = s + z * sin(",
+        "s = s + (z + 1e-3) * sin("),
     "gs_skips_last_colour": (
         "        for (int c = 0; c < nc; ++c)\n            og_colour_pass_f64(",
         "        for (int c = 0; c < nc - 1; ++c)\n            og_colour_pass_f64("),
@@ -69,6 +76,7 @@ def test_pins_reject_mutant(name, tmp_path):
                     "-o", str(lib), str(csrc), "-lm"], check=True)
     env = dict(os.environ, COLSTEN_ORACLE_LIB=str(lib))
     proc = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                           os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                           os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                           os.path.join(ROOT, "tests", "test_oracle_cost.py")],
                           cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert proc.returncode != 0, "the pins accepted mutant %s:\n%s" % (name, proc.stdout[-2000:])
