@@ -14,6 +14,7 @@
 #include "cs_device.h"
 #include "cs_internal.h"
 
+#include <stdint.h>
 #include <type_traits>
 
 namespace cs {
@@ -191,6 +192,160 @@ k_stream3(const S* __restrict__ src, S* __restrict__ dst, const S* __restrict__ 
     }
 }
 
+// Weighted Jacobi with the 27-point stencil, two x-adjacent points per thread.
+// The pair (x, x+1) reads columns x-1..x+2 of the nine neighbour rows as 16-byte
+// LDS loads and runs the two ordered fused multiply-add chains as the lanes of
+// a 2-vector (the ox = -1 and +1 terms are the loaded column pairs, the ox = 0
+// term a lane shuffle), so each point rounds exactly as jacobi_value.  The
+// pair is stored as one 16-byte nontemporal store when the row layout makes
+// it aligned (the library's padded layout does), else as two.
+template <typename S, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT)
+k_jacobi3_q1_pairs(const S* __restrict__ src, S* __restrict__ dst, const S* __restrict__ b, Geo g,
+                   double h2d, double omegad, StreamWork wk)
+{
+    typedef S v2 __attribute__((ext_vector_type(2)));
+    static_assert(TX % 2 == 0 && (TX / 2) * TY == NT, "one pair per thread");
+    constexpr int W = TX + 2, HH = TY + 2, NCOL = W * HH;
+    constexpr int M = (NCOL + NT - 1) / NT;
+    constexpr int R = 5;
+    __shared__ __attribute__((aligned(16))) S L[R][NCOL];
+
+    const int64_t work = xcd_block(wk.nblocks);
+    const int64_t tiles = (int64_t)wk.tiles_x * wk.tiles_y;
+    const int64_t chunk = work / tiles;
+    const int64_t tile = work % tiles;
+    const int64_t x0 = 1 + (tile % wk.tiles_x) * TX;
+    const int64_t y0 = 1 + (tile / wk.tiles_x) * TY;
+    const int64_t z0 = 1 + (chunk * g.nz) / wk.chunks;
+    const int64_t z1 = 1 + ((chunk + 1) * g.nz) / wk.chunks;
+    const int tid = threadIdx.x;
+
+    int coff[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int c = tid + NT * m;
+        const int ly = c / W, lx = c % W;
+        const int64_t x = x0 - 1 + lx, y = y0 - 1 + ly;
+        const bool ok = c < NCOL && x >= 0 && x <= g.nx + 1 && y >= 0 && y <= g.ny + 1;
+        coff[m] = ok ? (int)(y * g.sy + x) : -1;
+    }
+    // this thread's pair: points (x, x+1) of row y
+    const int tx = 2 * (tid % (TX / 2)), ty = tid / (TX / 2);
+    const int64_t x = x0 + tx, y = y0 + ty;
+    const bool in0 = x <= g.nx && y <= g.ny, in1 = x + 1 <= g.nx && y <= g.ny;
+    const int cl = (ty + 1) * W + tx;  // column x-1 of the pair's row: even
+    const int poff = in0 ? (int)(y * g.sy + x) : 0;
+
+    auto load_plane = [&](int64_t k, S* v) {
+        const bool kin = k >= 0 && k <= g.nz + 1;
+        const S* sp = src + (kin ? k : 0) * g.sz;
+#pragma unroll
+        for (int m = 0; m < M; ++m) v[m] = (kin && coff[m] >= 0) ? sp[coff[m]] : S(0);
+    };
+    auto store_plane = [&](const S* v, S* lp) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int c = tid + NT * m;
+            if (c < NCOL) lp[c] = v[m];
+        }
+    };
+    auto load_b = [&](int64_t k, v2& v) {
+        const bool kin = k >= 1 && k <= g.nz;
+        const S* bp = b + (kin ? k : 0) * g.sz;
+        v.x = (kin && in0) ? bp[poff] : S(0);
+        v.y = (kin && in1) ? bp[poff + 1] : S(0);
+    };
+    auto slot = [&](int64_t k) { return (int)((k - z0 + 2 * R) % R); };
+
+    S pre[M];
+    v2 bcur, bnxt;
+    {
+        S t[M];
+        load_plane(z0 - 1, t);
+        store_plane(t, L[slot(z0 - 1)]);
+        load_plane(z0, t);
+        store_plane(t, L[slot(z0)]);
+    }
+    load_plane(z0 + 1, pre);
+    load_b(z0, bcur);
+
+    const S h2 = (S)h2d, omega = (S)omegad;
+    const v2 h2v = {h2, h2}, omv = {omega, omega};
+    for (int64_t k = z0; k < z1; ++k) {
+        store_plane(pre, L[slot(k + 1)]);
+        if (k + 2 <= z1) load_plane(k + 2, pre);
+        if (k + 1 < z1) load_b(k + 1, bnxt);
+        __syncthreads();
+        const S* pls[3] = {L[slot(k - 1)], L[slot(k)], L[slot(k + 1)]};
+        v2 lo[3][3], hi[3][3];
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+            for (int oy = 0; oy < 3; ++oy) {
+                const v2* row = reinterpret_cast<const v2*>(pls[oz] + cl + (oy - 1) * W);
+                lo[oz][oy] = row[0];
+                hi[oz][oy] = row[1];
+            }
+        v2 acc = {S(0), S(0)};
+#pragma unroll
+        for (int oz = -1; oz <= 1; ++oz)
+#pragma unroll
+            for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+                for (int ox = -1; ox <= 1; ++ox) {
+                    const S w = weight<S, 3, Q1>(ox, oy, oz);
+                    if (w == S(0)) continue;
+                    const v2 a = lo[oz + 1][oy + 1], c2 = hi[oz + 1][oy + 1];
+                    const v2 val = ox < 0 ? a : (ox > 0 ? c2 : (v2){a.y, c2.x});
+                    const v2 wv = {w, w};
+                    acc = __builtin_elementwise_fma(wv, val, acc);
+                }
+        const v2 ctr = {lo[1][1].y, hi[1][1].x};  // u at (x, y, k), (x+1, y, k)
+        const v2 q = h2v * bcur - acc;
+        const v2 sc = {over_centre<S, 3, Q1>(q.x), over_centre<S, 3, Q1>(q.y)};
+        const v2 out = __builtin_elementwise_fma(omv, sc, ctr);
+        S* dp = dst + k * g.sz + poff;
+        if (in0 && in1 && (((uintptr_t)dp & (2 * sizeof(S) - 1)) == 0)) {
+            __builtin_nontemporal_store(out, reinterpret_cast<v2*>(dp));
+        } else {
+            if (in0) st_stream(dp, out.x);
+            if (in1) st_stream(dp + 1, out.y);
+        }
+        bcur = bnxt;
+    }
+}
+
+// Workgroups that fit the device at once for kernel kern (queried once per
+// kernel by the caller) and the z-chunking that fills them.
+template <typename K>
+int64_t resident_of(K kern, int nt)
+{
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, 0) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        per_cu = 2;
+        cus = 256;
+    }
+    return (int64_t)(per_cu > 0 ? per_cu : 1) * cus;
+}
+
+StreamWork chunk_tiles(const Geo& g, int tx, int ty, int64_t resident)
+{
+    StreamWork wk;
+    wk.tiles_x = (int)((g.nx + tx - 1) / tx);
+    wk.tiles_y = (int)((g.ny + ty - 1) / ty);
+    const int64_t tiles = (int64_t)wk.tiles_x * wk.tiles_y;
+    int64_t chunks = resident / tiles;
+    if (chunks < 1) chunks = 1;
+    if (chunks > g.nz / 4) chunks = g.nz / 4 > 0 ? g.nz / 4 : 1;
+    wk.chunks = (int)chunks;
+    wk.nblocks = tiles * chunks;
+    return wk;
+}
+
 template <typename S, int ST, int MODE, int TX, int TY, int NT>
 StreamWork plan(const Geo& g, int max_blocks)
 {
@@ -225,6 +380,14 @@ cs_status jacobi3_t(const Geo& g, const void* src, void* dst, const void* b, dou
                     double omega, hipStream_t s)
 {
     constexpr int TX = 64, TY = 8, NT = 256;
+    if (ST == Q1) {
+        auto kern = k_jacobi3_q1_pairs<S, TX, TY, NT>;
+        static const int64_t resident = resident_of(kern, NT);
+        const StreamWork wk = chunk_tiles(g, TX, TY, resident);
+        hipLaunchKernelGGL(kern, dim3((unsigned)wk.nblocks), dim3(NT), 0, s, (const S*)src, (S*)dst,
+                           (const S*)b, g, h2, omega, wk);
+        return check_launch("streaming jacobi (27-point pairs)");
+    }
     const StreamWork wk = plan<S, ST, MODE_JACOBI, TX, TY, NT>(g, 1 << 30);
     hipLaunchKernelGGL((k_stream3<S, ST, MODE_JACOBI, TX, TY, NT>), dim3((unsigned)wk.nblocks),
                        dim3(NT), 0, s, (const S*)src, (S*)dst, (const S*)b, g, h2, omega, wk,
