@@ -135,6 +135,17 @@ cs_status cs_gs_sweeps_lex(cs_grid g, int32_t nsweeps, void* stream);
 cs_status cs_gs_sweeps_cost(cs_grid g, int32_t nsweeps, int32_t kmax, int32_t hetero,
                             void* stream);
 
+/* Operator application y = A u = (S u) / h^2 at the interior points (the
+ * separate-output-array mat-vec of Sec. 2).  cellwise == 0: stencil form, the
+ * ordered neighbour sum; y's halo is untouched.  cellwise == 1 (d-linear
+ * stencils only): the element-wise form, every cell adding its element
+ * stiffness times its 2^d vertex values into those vertices, in 2^d cell-colour
+ * passes whose cells share no vertex (race-free accumulation into vertices);
+ * the same operator up to summation order, and y's halo receives partial sums.
+ * y: caller-owned device array with u's layout and dtype, distinct from u and b.
+ * Errors: CS_EINVAL (bad y, cellwise not 0/1, cellwise with CS_FD). */
+cs_status cs_apply(cs_grid g, void* y, int32_t cellwise, void* stream);
+
 /* Residual r_q = b_q - (S u)_q / h^2 over the interior.  r: NULL or a device
  * array with u's layout and dtype (halo untouched).  norms: device pointer to
  * 3 doubles receiving ||r||_2, max |r| and ||b||_2 (unweighted sums over

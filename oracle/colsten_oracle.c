@@ -592,6 +592,41 @@ void og_q1_apply_cellwise(int dim, int64_t nx, int64_t ny, int64_t nz,
             }
 }
 
+/* The same cell-wise accumulation in 2^d cell-colour passes: colour of the
+ * cell with lower corner (i, j, k) = (i mod 2) + 2 (j mod 2) + 4 (k mod 2);
+ * cells of one colour share no vertex, so a pass has no write conflict (the
+ * race-free accumulation into vertices by cell colouring).  Colours 0..2^d-1
+ * in order, z-y-x within a colour; each vertex therefore receives its 2^d
+ * contributions in colour order. */
+void og_q1_apply_cellwise_coloured(int dim, int64_t nx, int64_t ny, int64_t nz,
+                                   int64_t sy, int64_t sz, const double* u, double* out)
+{
+    int nv = 1 << dim;
+    int64_t kz = dim == 3 ? nz : 0;
+    for (int col = 0; col < nv; ++col)
+        for (int64_t k = 0; k <= kz; ++k)
+            for (int64_t j = 0; j <= ny; ++j)
+                for (int64_t i = 0; i <= nx; ++i) {
+                    int cc = (int)(i & 1) + 2 * (int)(j & 1) + (dim == 3 ? 4 * (int)(k & 1) : 0);
+                    if (cc != col) continue;
+                    for (int a = 0; a < nv; ++a) {
+                        int64_t qa = (i + (a & 1)) + (j + ((a >> 1) & 1)) * sy
+                                   + (dim == 3 ? (k + ((a >> 2) & 1)) * sz : 0);
+                        double acc = 0.0;
+                        for (int bb = 0; bb < nv; ++bb) {
+                            int64_t qb = (i + (bb & 1)) + (j + ((bb >> 1) & 1)) * sy
+                                       + (dim == 3 ? (k + ((bb >> 2) & 1)) * sz : 0);
+                            int x = a ^ bb;
+                            int ndiff = (x & 1) + ((x >> 1) & 1) + ((x >> 2) & 1);
+                            double kab = og_q1_kref(dim, ndiff);
+                            if (kab == 0.0) continue;
+                            acc += kab * u[qb];
+                        }
+                        out[qa] += acc;
+                    }
+                }
+}
+
 /* (S u)_q by the stencil form, for comparison with the cell-wise form. */
 void og_apply_stencil(int dim, int stencil, int64_t nx, int64_t ny, int64_t nz,
                       int64_t sy, int64_t sz, const double* u, double* out)

@@ -82,6 +82,8 @@ def _load():
     lib.og_q1_kref.argtypes = [i32, i32]
     lib.og_q1_apply_cellwise.restype = None
     lib.og_q1_apply_cellwise.argtypes = [i32, i64, i64, i64, i64, i64, vp, vp]
+    lib.og_q1_apply_cellwise_coloured.restype = None
+    lib.og_q1_apply_cellwise_coloured.argtypes = [i32, i64, i64, i64, i64, i64, vp, vp]
     lib.og_apply_stencil.restype = None
     lib.og_apply_stencil.argtypes = [i32, i32, i64, i64, i64, i64, i64, vp, vp]
     _lib = lib
@@ -232,6 +234,15 @@ def q1_apply_cellwise(u, *, dim):
     out = _like(u)[0]
     nx, ny, nz, sy, sz = _geometry(u, dim)
     _load().og_q1_apply_cellwise(dim, nx, ny, nz, sy, sz, _ptr(u), _ptr(out))
+    return out
+
+
+def q1_apply_cellwise_coloured(u, *, dim):
+    """(S u) at interior points by element-wise accumulation in 2^d cell-colour
+    passes (each vertex receives its cell contributions in colour order)."""
+    out = _like(u)[0]
+    nx, ny, nz, sy, sz = _geometry(u, dim)
+    _load().og_q1_apply_cellwise_coloured(dim, nx, ny, nz, sy, sz, _ptr(u), _ptr(out))
     return out
 
 

@@ -57,6 +57,7 @@ _SIGS = {
     "cs_jacobi_sweeps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32,
                                         ctypes.c_void_p, ctypes.c_void_p]),
     "cs_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cs_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "cs_gs_sweeps_lex": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "cs_gs_sweeps_cost": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p]),
@@ -151,6 +152,10 @@ def cs_colour_pass(handle, colour, stream=None):
 def cs_gs_sweeps(handle, nsweeps, u_tmp_ptr=0, stream=None):
     _check(lib().cs_gs_sweeps(ctypes.c_void_p(handle), int(nsweeps), ctypes.c_void_p(u_tmp_ptr),
                               _stream(stream)))
+
+
+def cs_apply(handle, y_ptr, cellwise=0, stream=None):
+    _check(lib().cs_apply(ctypes.c_void_p(handle), ctypes.c_void_p(y_ptr), int(cellwise), _stream(stream)))
 
 
 def cs_gs_sweeps_lex(handle, nsweeps, stream=None):
@@ -304,6 +309,10 @@ class Grid:
 
     def gs(self, nsweeps, tmp=None, stream=None):
         cs_gs_sweeps(self.handle, nsweeps, 0 if tmp is None else tmp.data_ptr(), stream)
+
+    def apply(self, y, cellwise=False, stream=None):
+        """y = A u at the interior (stencil form, or element-wise by cell colours)."""
+        cs_apply(self.handle, y.data_ptr(), 1 if cellwise else 0, stream)
 
     def gs_lex(self, nsweeps, stream=None):
         """Lexicographic Gauss-Seidel sweeps (hyperplane wavefronts)."""

@@ -249,6 +249,21 @@ cs_status cs_gs_sweeps(cs_grid g, int32_t nsweeps, void* u_tmp, void* stream)
     return CS_OK;
 }
 
+cs_status cs_apply(cs_grid g, void* y, int32_t cellwise, void* stream)
+{
+    cs_status st = check_grid(g);
+    if (st != CS_OK) return st;
+    if (!y) { set_error("y is NULL"); return CS_EINVAL; }
+    if ((st = check_tmp(g, y)) != CS_OK) return st;
+    if (cellwise != 0 && cellwise != 1) { set_error("cellwise must be 0 or 1"); return CS_EINVAL; }
+    if (cellwise && g->d.stencil != CS_Q1) {
+        set_error("the cell-wise form exists for the d-linear stencils only");
+        return CS_EINVAL;
+    }
+    return launch_apply(g->d.dtype, g->d.dim, g->d.stencil, g->geo, g->u, y, h2_of(g), cellwise,
+                        (hipStream_t)stream);
+}
+
 cs_status cs_gs_sweeps_lex(cs_grid g, int32_t nsweeps, void* stream)
 {
     cs_status st = check_grid(g);

@@ -145,6 +145,94 @@ k_jacobi(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict__ b
     dst[q] = jacobi_value<T, DIM, ST>(h2, omega, b[q], src[q], ld);
 }
 
+// Operator application y = A u = (S u) / h^2 at interior points (the
+// separate-output-array mat-vec of Sec. 2), stencil form: the full ordered
+// sum of the plain definition.
+template <typename T, int DIM, int ST>
+__global__ void __launch_bounds__(kBX* kBY)
+k_apply(const T* __restrict__ u, T* __restrict__ y, Geo g, T h2, int64_t xblocks)
+{
+    const int64_t bid = blockIdx.x;
+    const int64_t xb = bid % xblocks;
+    const int64_t row = (bid / xblocks) * kBY + threadIdx.y;
+    if (row >= g.ny * g.nz) return;
+    const int64_t j = 1 + row % g.ny;
+    const int64_t k = 1 + row / g.ny;
+    const int64_t i = 1 + xb * kBX + threadIdx.x;
+    if (i > g.nx) return;
+    const int64_t q = (DIM == 3 ? k * g.sz : 0) + j * g.sy + i;
+    const int64_t sy = g.sy, sz = g.sz;
+    auto ld = [&](int ox, int oy, int oz) { return u[q + oz * sz + oy * sy + ox]; };
+    y[q] = ordered_sum<T, DIM, ST, true>(ld) / h2;
+}
+
+// The d-linear operator applied element by element ("cell-wise, accumulating
+// into vertices"): every cell with lower corner (i, j, k), 0 <= i <= nx etc.,
+// adds K_ref u_e into its 2^d vertices, K_ref the assembled d-linear element
+// stiffness (entries by the number of coordinates in which two vertices
+// differ: 2D 2/3, -1/6, -1/3; 3D 1/3, 0, -1/12, -1/12).  Cells are taken in
+// 2^d colour passes, colour = parities of the lower corner; cells of one
+// colour share no vertex, so each pass scatters without conflicts and every
+// vertex receives its contributions in colour order.  One thread per cell.
+template <typename T, int DIM>
+__device__ __forceinline__ T kref(int ndiff)
+{
+    if (DIM == 2) return ndiff == 0 ? T(2) / T(3) : (ndiff == 1 ? T(-1) / T(6) : T(-1) / T(3));
+    return ndiff == 0 ? T(1) / T(3) : (ndiff == 1 ? T(0) : T(-1) / T(12));
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256)
+k_cell_pass(const T* __restrict__ u, T* __restrict__ y, Geo g, int colour, int64_t cx, int64_t cy,
+            int64_t cz)
+{
+    constexpr int NV = 1 << DIM;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cx * cy * cz) return;
+    const int64_t i = (colour & 1) + 2 * (t % cx);
+    const int64_t j = ((colour >> 1) & 1) + 2 * ((t / cx) % cy);
+    const int64_t k = DIM == 3 ? ((colour >> 2) & 1) + 2 * (t / (cx * cy)) : 0;
+    const int64_t base = (DIM == 3 ? k * g.sz : 0) + j * g.sy + i;
+    int64_t off[NV];
+    T ue[NV];
+#pragma unroll
+    for (int a = 0; a < NV; ++a) {
+        off[a] = base + (a & 1) + ((a >> 1) & 1) * g.sy + (DIM == 3 ? ((a >> 2) & 1) * g.sz : 0);
+        ue[a] = u[off[a]];
+    }
+#pragma unroll
+    for (int a = 0; a < NV; ++a) {
+        T acc = T(0);
+#pragma unroll
+        for (int bb = 0; bb < NV; ++bb) {
+            const int x = a ^ bb;
+            const T kab = kref<T, DIM>((x & 1) + ((x >> 1) & 1) + ((x >> 2) & 1));
+            if (kab == T(0)) continue;
+            acc = acc + kab * ue[bb];
+        }
+        y[off[a]] = y[off[a]] + acc;
+    }
+}
+
+// y over the whole halo'd extent (the cell passes write partial sums into
+// the halo vertices too) set to zero, or the interior divided by h^2.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256)
+k_fill_or_scale(T* __restrict__ y, Geo g, T h2, int scale)
+{
+    const int64_t wx = g.nx + 2, wy = g.ny + 2;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= wx * wy * (DIM == 3 ? g.nz + 2 : 1)) return;
+    const int64_t i = t % wx, j = (t / wx) % wy, k = DIM == 3 ? t / (wx * wy) : 0;
+    const int64_t q = (DIM == 3 ? k * g.sz : 0) + j * g.sy + i;
+    if (!scale) {
+        y[q] = T(0);
+        return;
+    }
+    const bool inner = i >= 1 && i <= g.nx && j >= 1 && j <= g.ny && (DIM == 2 || (k >= 1 && k <= g.nz));
+    if (inner) y[q] = y[q] / h2;
+}
+
 // Halo points enumerated as: (3D) planes k = 0 and k = nz+1 in full, then for
 // each interior plane the rows j = 0, j = ny+1 and the columns i = 0, i = nx+1.
 template <typename T, int DIM>
@@ -492,10 +580,46 @@ cs_status launch_colour_pass(int dtype, int dim, int stencil, const Geo& g, void
     CS_DISPATCH(colour_pass_t, dtype, dim, stencil, g, u, b, h2, colour, cost, s);
 }
 
+template <typename T, int DIM, int ST>
+cs_status apply_t(const Geo& g, const void* u, void* y, double h2, int cellwise, hipStream_t s)
+{
+    if (!cellwise) {
+        const int64_t xblocks = (g.nx + kBX - 1) / kBX;
+        const int64_t blocks = xblocks * ((g.ny * g.nz + kBY - 1) / kBY);
+        if (blocks > 0x7fffffff) { set_error("apply: grid too large"); return CS_EUNSUPPORTED; }
+        hipLaunchKernelGGL((k_apply<T, DIM, ST>), dim3((unsigned)blocks), dim3(kBX, kBY), 0, s,
+                           (const T*)u, (T*)y, g, (T)h2, xblocks);
+        return check_launch("apply (stencil form)");
+    }
+    const int64_t all = (g.nx + 2) * (g.ny + 2) * (DIM == 3 ? g.nz + 2 : 1);
+    const int64_t fblocks = (all + 255) / 256;
+    if (fblocks > 0x7fffffff) { set_error("apply: grid too large"); return CS_EUNSUPPORTED; }
+    hipLaunchKernelGGL((k_fill_or_scale<T, DIM>), dim3((unsigned)fblocks), dim3(256), 0, s, (T*)y, g,
+                       (T)h2, 0);
+    for (int c = 0; c < (1 << DIM); ++c) {
+        // lower corners i = bx, bx + 2, ... <= nx (the cell's far vertex i + 1 <= nx + 1)
+        const int64_t cx = (g.nx - (c & 1)) / 2 + 1;
+        const int64_t cy = (g.ny - ((c >> 1) & 1)) / 2 + 1;
+        const int64_t cz = DIM == 3 ? (g.nz - ((c >> 2) & 1)) / 2 + 1 : 1;
+        const int64_t blocks = (cx * cy * cz + 255) / 256;
+        hipLaunchKernelGGL((k_cell_pass<T, DIM>), dim3((unsigned)blocks), dim3(256), 0, s,
+                           (const T*)u, (T*)y, g, c, cx, cy, cz);
+    }
+    hipLaunchKernelGGL((k_fill_or_scale<T, DIM>), dim3((unsigned)fblocks), dim3(256), 0, s, (T*)y, g,
+                       (T)h2, 1);
+    return check_launch("apply (cell-wise)");
+}
+
 cs_status launch_lex_sweep(int dtype, int dim, int stencil, const Geo& g, void* u, const void* b,
                            double h2, hipStream_t s)
 {
     CS_DISPATCH(lex_sweep_t, dtype, dim, stencil, g, u, b, h2, s);
+}
+
+cs_status launch_apply(int dtype, int dim, int stencil, const Geo& g, const void* u, void* y,
+                       double h2, int cellwise, hipStream_t s)
+{
+    CS_DISPATCH(apply_t, dtype, dim, stencil, g, u, y, h2, cellwise, s);
 }
 
 cs_status launch_jacobi(int dtype, int dim, int stencil, const Geo& g, const void* src,

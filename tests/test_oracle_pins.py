@@ -136,6 +136,24 @@ def test_cellwise_q1_equals_stencil_form(dim, shape):
     c = O.q1_apply_cellwise(u, dim=dim)
     ai, ci = O.interior(a), O.interior(c)
     assert _relmax(ci, ai) <= 1e-15
+    # the same accumulation in 2^d cell-colour passes (different summation order)
+    cc = O.interior(O.q1_apply_cellwise_coloured(u, dim=dim))
+    assert _relmax(cc, ai) <= 1e-15
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (6, 7)), (3, (4, 5, 6))])
+def test_cell_colours_share_no_vertex(dim, shape):
+    # cells whose lower corners have the same parities are at least two apart
+    # along some axis, so their vertex sets are disjoint
+    import itertools
+    rng = [range(0, n + 1) for n in shape]
+    seen = {}
+    for corner in itertools.product(*rng):
+        col = sum((c & 1) << m for m, c in enumerate(corner))
+        for off in itertools.product((0, 1), repeat=dim):
+            v = tuple(c + o for c, o in zip(corner, off))
+            assert (col, v) not in seen, (corner, seen.get((col, v)))
+            seen[(col, v)] = corner
 
 
 # --------------------------------------------------------------------------
