@@ -135,6 +135,15 @@ cs_status cs_gs_sweeps_lex(cs_grid g, int32_t nsweeps, void* stream);
 cs_status cs_gs_sweeps_cost(cs_grid g, int32_t nsweeps, int32_t kmax, int32_t hetero,
                             void* stream);
 
+/* Seeded input on the device: the interior of a (layout desc, device array)
+ * receives i.i.d. uniform[-1, 1) values from SplitMix64 in counter form,
+ * value(seed, l) = mix64(seed + (l + 1) * 0x9E3779B97F4A7C15) at lexicographic
+ * interior index l (x fastest), as (v >> 11) * 2^-52 - 1 (exact in FP64,
+ * rounded for FP32): the same values as the host-side input generator, so a
+ * right-hand side can be made where it is used.  The halo is untouched.
+ * Errors: CS_EINVAL for a bad descriptor or pointer. */
+cs_status cs_fill_uniform(const cs_grid_desc* desc, void* a, uint64_t seed, void* stream);
+
 /* Operator application y = A u = (S u) / h^2 at the interior points (the
  * separate-output-array mat-vec of Sec. 2).  cellwise == 0: stencil form, the
  * ordered neighbour sum; y's halo is untouched.  cellwise == 1 (d-linear

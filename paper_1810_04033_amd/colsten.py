@@ -57,6 +57,8 @@ _SIGS = {
     "cs_jacobi_sweeps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32,
                                         ctypes.c_void_p, ctypes.c_void_p]),
     "cs_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cs_fill_uniform": (ctypes.c_int, [ctypes.POINTER(cs_grid_desc), ctypes.c_void_p, ctypes.c_uint64,
+                                       ctypes.c_void_p]),
     "cs_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "cs_gs_sweeps_lex": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "cs_gs_sweeps_cost": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -152,6 +154,14 @@ def cs_colour_pass(handle, colour, stream=None):
 def cs_gs_sweeps(handle, nsweeps, u_tmp_ptr=0, stream=None):
     _check(lib().cs_gs_sweeps(ctypes.c_void_p(handle), int(nsweeps), ctypes.c_void_p(u_tmp_ptr),
                               _stream(stream)))
+
+
+def fill_uniform(t, seed, *, dim, stream=None):
+    """Fill the interior of the halo'd device tensor t with the seeded
+    uniform[-1, 1) field (on the GPU; same values as inputs.uniform_field)."""
+    d = describe(t, dim=dim, stencil=CS_FD, h=1.0)
+    _check(lib().cs_fill_uniform(ctypes.byref(d), ctypes.c_void_p(t.data_ptr()), ctypes.c_uint64(int(seed)),
+                                 _stream(stream)))
 
 
 def cs_apply(handle, y_ptr, cellwise=0, stream=None):

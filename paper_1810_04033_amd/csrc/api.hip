@@ -249,6 +249,23 @@ cs_status cs_gs_sweeps(cs_grid g, int32_t nsweeps, void* u_tmp, void* stream)
     return CS_OK;
 }
 
+cs_status cs_fill_uniform(const cs_grid_desc* desc, void* a, uint64_t seed, void* stream)
+{
+    g_err[0] = 0;
+    cs_status st = validate_desc(desc);
+    if (st != CS_OK) return st;
+    const size_t elem = desc->dtype == CS_F64 ? 8 : 4;
+    if ((st = check_device_range(a, (size_t)span_of(*desc) * elem, elem, "a")) != CS_OK) return st;
+    Geo geo;
+    geo.nx = desc->n[0];
+    geo.ny = desc->n[1];
+    geo.nz = desc->dim == 3 ? desc->n[2] : 1;
+    geo.sy = desc->stride[1];
+    geo.sz = desc->dim == 3 ? desc->stride[2] : 0;
+    geo.parity = desc->parity;
+    return launch_fill_uniform(desc->dtype, desc->dim, geo, a, seed, (hipStream_t)stream);
+}
+
 cs_status cs_apply(cs_grid g, void* y, int32_t cellwise, void* stream)
 {
     cs_status st = check_grid(g);

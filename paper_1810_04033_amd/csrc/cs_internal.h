@@ -46,6 +46,7 @@ cs_status check_launch(const char* what);
 cs_status launch_colour_pass(int dtype, int dim, int stencil, const Geo& g, void* u,
                              const void* b, double h2, int colour, hipStream_t s,
                              const StencilCost* cost = nullptr);
+cs_status launch_fill_uniform(int dtype, int dim, const Geo& g, void* a, uint64_t seed, hipStream_t s);
 cs_status launch_apply(int dtype, int dim, int stencil, const Geo& g, const void* u, void* y,
                        double h2, int cellwise, hipStream_t s);
 cs_status launch_lex_sweep(int dtype, int dim, int stencil, const Geo& g, void* u, const void* b,

@@ -9,6 +9,8 @@
 #include "cs_device.h"
 #include "cs_internal.h"
 
+#include <stdint.h>
+
 namespace cs {
 
 namespace {
@@ -143,6 +145,30 @@ k_jacobi(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict__ b
     const int64_t sy = g.sy, sz = g.sz;
     auto ld = [&](int ox, int oy, int oz) { return src[q + oz * sz + oy * sy + ox]; };
     dst[q] = jacobi_value<T, DIM, ST>(h2, omega, b[q], src[q], ld);
+}
+
+// Seeded uniform[-1, 1) field on the interior: SplitMix64 in counter form,
+// value(seed, l) = mix64(seed + (l + 1) * 0x9E3779B97F4A7C15) over the
+// lexicographic interior index l (x fastest), (v >> 11) * 2^-52 - 1 exact in
+// binary64 (rounded to T).  The same published generator as the host-side
+// input module, so device and host fields agree bit for bit.
+__device__ __forceinline__ uint64_t splitmix_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256)
+k_fill_uniform(T* __restrict__ a, Geo g, uint64_t seed)
+{
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= g.nx * g.ny * g.nz) return;
+    const int64_t i = 1 + l % g.nx, j = 1 + (l / g.nx) % g.ny, k = 1 + l / (g.nx * g.ny);
+    const uint64_t v = splitmix_mix(seed + ((uint64_t)l + 1) * 0x9E3779B97F4A7C15ull);
+    const double x = (double)(v >> 11) * 0x1p-52 - 1.0;
+    a[(DIM == 3 ? k * g.sz : 0) + j * g.sy + i] = (T)x;
 }
 
 // Operator application y = A u = (S u) / h^2 at interior points (the
@@ -614,6 +640,21 @@ cs_status launch_lex_sweep(int dtype, int dim, int stencil, const Geo& g, void* 
                            double h2, hipStream_t s)
 {
     CS_DISPATCH(lex_sweep_t, dtype, dim, stencil, g, u, b, h2, s);
+}
+
+cs_status launch_fill_uniform(int dtype, int dim, const Geo& g, void* a, uint64_t seed, hipStream_t s)
+{
+    const int64_t n = g.nx * g.ny * g.nz;
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffff) { set_error("fill: grid too large"); return CS_EUNSUPPORTED; }
+    if (dtype == 0) {
+        if (dim == 2) hipLaunchKernelGGL((k_fill_uniform<double, 2>), dim3((unsigned)blocks), dim3(256), 0, s, (double*)a, g, seed);
+        else hipLaunchKernelGGL((k_fill_uniform<double, 3>), dim3((unsigned)blocks), dim3(256), 0, s, (double*)a, g, seed);
+    } else {
+        if (dim == 2) hipLaunchKernelGGL((k_fill_uniform<float, 2>), dim3((unsigned)blocks), dim3(256), 0, s, (float*)a, g, seed);
+        else hipLaunchKernelGGL((k_fill_uniform<float, 3>), dim3((unsigned)blocks), dim3(256), 0, s, (float*)a, g, seed);
+    }
+    return check_launch("seeded fill");
 }
 
 cs_status launch_apply(int dtype, int dim, int stencil, const Geo& g, const void* u, void* y,
