@@ -110,7 +110,9 @@ cs_status cs_gs_sweeps(cs_grid g, int32_t nsweeps, void* u_tmp, void* stream);
 /* nsweeps weighted Jacobi sweeps (the separate-output-array form of Sec. 2):
  *   u'_q = u_q + omega * (h^2 b_q - sum_o S_o u_{q+o}) / S_0
  * reading only the previous iterate.  u_tmp (required) must have u's layout;
- * its halo is overwritten with u's halo.  The result ends in u.
+ * its halo is overwritten with u's halo.  The result ends in u.  On 3D grids
+ * the sweeps run two per pass over memory (the intermediate iterate stays on
+ * chip); the iterate is the same, rounded identically.
  * Errors: CS_EINVAL (u_tmp NULL, nsweeps < 0, omega not finite). */
 cs_status cs_jacobi_sweeps(cs_grid g, double omega, int32_t nsweeps, void* u_tmp, void* stream);
 

@@ -332,8 +332,15 @@ cs_status cs_jacobi_sweeps(cs_grid g, double omega, int32_t nsweeps, void* u_tmp
     if ((st = launch_halo_copy(dt, dim, g->geo, g->u, u_tmp, s)) != CS_OK) return st;
     const void* src = g->u;
     void* dst = u_tmp;
-    for (int32_t it = 0; it < nsweeps; ++it) {
-        st = launch_jacobi(dt, dim, sten, g->geo, src, dst, g->b, h2_of(g), omega, s);
+    const bool pairs = dim == 3 && jacobi3_two_supported(sten, g->geo);
+    for (int32_t it = 0; it < nsweeps;) {
+        if (pairs && nsweeps - it >= 2) {
+            st = launch_jacobi3_two(dt, sten, g->geo, src, dst, g->b, h2_of(g), omega, s);
+            it += 2;
+        } else {
+            st = launch_jacobi(dt, dim, sten, g->geo, src, dst, g->b, h2_of(g), omega, s);
+            it += 1;
+        }
         if (st != CS_OK) return st;
         void* nsrc = dst;
         dst = (void*)src;

@@ -81,6 +81,11 @@ cs_status launch_ir_update(int dim, const Geo& g, void* x, const Geo& g2, const 
 bool stream_supported(const Geo& g);
 cs_status launch_jacobi3_stream(int dtype, int stencil, const Geo& g, const void* src, void* dst,
                                 const void* b, double h2, double omega, hipStream_t s);
+// Two Jacobi sweeps in one pass over memory (3D): src -> dst holds the
+// iterate of two one-sweep passes bit for bit.
+bool jacobi3_two_supported(int stencil, const Geo& g);
+cs_status launch_jacobi3_two(int dtype, int stencil, const Geo& g, const void* src, void* dst,
+                             const void* b, double h2, double omega, hipStream_t s);
 cs_status launch_residual3_stream(int dtype, int stencil, const Geo& g, const void* u,
                                   const void* b, void* r, double h2, Partial* partials,
                                   double* norms, hipStream_t s);

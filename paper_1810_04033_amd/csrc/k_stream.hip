@@ -316,6 +316,404 @@ k_jacobi3_q1_pairs(const S* __restrict__ src, S* __restrict__ dst, const S* __re
     }
 }
 
+// Two weighted Jacobi sweeps with the 7-point stencil in one pass over memory.
+// The first sweep's iterate u1 = J(u) is computed on the tile grown by one
+// point in x and y and kept in a three-plane LDS ring; the second sweep
+// u2 = J(u1) is computed on the tile from that ring and stored.  u1 never goes
+// to HBM, so the pass moves the bytes of one sweep for the updates of two.
+// Every value is the same expression as in the one-sweep kernel, so the pair
+// of sweeps gives the iterate of two one-sweep passes bit for bit.  Grown-tile
+// points on the boundary keep their Dirichlet value (the halo of the work array
+// holds the same values).
+//
+// A thread computes u1 and u2 at the same tile points, so b is loaded once per
+// point and kept in a three-plane register ring (the z loop is unrolled by
+// three, so the ring rotates without register moves); the ring of grown-tile
+// points around the tile is spread over all threads.  Step k of the z loop
+// computes u1 on plane k, then u2 on plane k - 1; a chunk of output planes
+// [z0, z1) reads u on planes z0 - 2 .. z1 + 1.  Two barriers per plane: after
+// the u plane is stored, and after the u1 plane is written.
+template <typename S, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT)
+k_jacobi3_fd_two(const S* __restrict__ src, S* __restrict__ dst, const S* __restrict__ b, Geo g,
+                 double h2d, double omegad, StreamWork wk)
+{
+    constexpr int W = TX + 4, HH = TY + 4, NCOL = W * HH;  // u on the tile + 2
+    constexpr int W1 = TX + 2, H1 = TY + 2, N1 = W1 * H1;  // u1 on the tile + 1
+    constexpr int NR = 2 * W1 + 2 * (H1 - 2);              // u1 points outside the tile
+    constexpr int M = (NCOL + NT - 1) / NT;
+    constexpr int P = (TX * TY + NT - 1) / NT;
+    constexpr int PR = (NR + NT - 1) / NT;
+    __shared__ S L[3][NCOL];
+    __shared__ S L1[3][N1];
+
+    const int64_t work = xcd_block(wk.nblocks);
+    const int64_t tiles = (int64_t)wk.tiles_x * wk.tiles_y;
+    const int64_t chunk = work / tiles;
+    const int64_t tile = work % tiles;
+    const int64_t x0 = 1 + (tile % wk.tiles_x) * TX;
+    const int64_t y0 = 1 + (tile / wk.tiles_x) * TY;
+    const int64_t z0 = 1 + (chunk * g.nz) / wk.chunks;
+    const int64_t z1 = 1 + ((chunk + 1) * g.nz) / wk.chunks;
+    const int tid = threadIdx.x;
+
+    int coff[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int c = tid + NT * m;
+        const int64_t x = x0 - 2 + c % W, y = y0 - 2 + c / W;
+        const bool ok = c < NCOL && x >= 0 && x <= g.nx + 1 && y >= 0 && y <= g.ny + 1;
+        coff[m] = ok ? (int)(y * g.sy + x) : -1;
+    }
+    // kind of a u1 point: 2 interior (computed), 1 boundary (keeps u), 0 outside
+    auto kind_of = [&](int64_t x, int64_t y) {
+        if (x > g.nx + 1 || y > g.ny + 1) return 0;
+        return (x >= 1 && x <= g.nx && y >= 1 && y <= g.ny) ? 2 : 1;
+    };
+    // tile points (u1 and u2)
+    int tk[P], tu[P], t1[P], toff[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const int t = tid + NT * i;
+        const int tx = t % TX, ty = t / TX;
+        const int64_t x = x0 + tx, y = y0 + ty;
+        tk[i] = t < TX * TY ? kind_of(x, y) : 0;
+        tu[i] = (ty + 2) * W + (tx + 2);
+        t1[i] = (ty + 1) * W1 + (tx + 1);
+        toff[i] = tk[i] == 2 ? (int)(y * g.sy + x) : 0;
+    }
+    // ring points (u1 only): top row, bottom row, left column, right column
+    int rk[PR], ru[PR], r1[PR], roff[PR];
+#pragma unroll
+    for (int j = 0; j < PR; ++j) {
+        const int r = tid + NT * j;
+        int lx, ly;
+        if (r < W1) {
+            lx = r; ly = 0;
+        } else if (r < 2 * W1) {
+            lx = r - W1; ly = H1 - 1;
+        } else {
+            const int q = r - 2 * W1;
+            lx = q < H1 - 2 ? 0 : W1 - 1;
+            ly = 1 + q % (H1 - 2);
+        }
+        const int64_t x = x0 - 1 + lx, y = y0 - 1 + ly;
+        rk[j] = r < NR ? kind_of(x, y) : 0;
+        ru[j] = (ly + 1) * W + (lx + 1);
+        r1[j] = ly * W1 + lx;
+        roff[j] = rk[j] == 2 ? (int)(y * g.sy + x) : 0;
+    }
+
+    auto load_plane = [&](int64_t k, S* v) {
+        const bool kin = k >= 0 && k <= g.nz + 1;
+        const S* sp = src + (kin ? k : 0) * g.sz;
+#pragma unroll
+        for (int m = 0; m < M; ++m) v[m] = (kin && coff[m] >= 0) ? sp[coff[m]] : S(0);
+    };
+    auto store_plane = [&](const S* v, S* lp) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int c = tid + NT * m;
+            if (c < NCOL) lp[c] = v[m];
+        }
+    };
+    auto load_b = [&](int64_t k, S* bt, S* br) {
+        const bool kin = k >= 1 && k <= g.nz;
+        const S* bp = b + (kin ? k : 0) * g.sz;
+#pragma unroll
+        for (int i = 0; i < P; ++i) bt[i] = (kin && tk[i] == 2) ? bp[toff[i]] : S(0);
+#pragma unroll
+        for (int j = 0; j < PR; ++j) br[j] = (kin && rk[j] == 2) ? bp[roff[j]] : S(0);
+    };
+    auto slot = [&](int64_t k) { return (int)((k - z0 + 6) % 3); };
+
+    const S h2 = (S)h2d, omega = (S)omegad;
+    auto u1_point = [&](bool kint, int kind, int cu, S bq, const S* lm, const S* l0,
+                        const S* lp) -> S {
+        if (!(kint && kind == 2)) return l0[cu];
+        auto ld = [&](int ox, int oy, int oz) -> S {
+            const S* pl = oz < 0 ? lm : (oz > 0 ? lp : l0);
+            return pl[cu + oy * W + ox];
+        };
+        return jacobi_value<S, 3, FD>(h2, omega, bq, l0[cu], ld);
+    };
+
+    S pre[M];
+    S B0[P], B1[P], B2[P], R0[PR], R1[PR], R2[PR];
+    {
+        S t[M];
+        load_plane(z0 - 2, t);
+        store_plane(t, L[slot(z0 - 2)]);
+        load_plane(z0 - 1, t);
+        store_plane(t, L[slot(z0 - 1)]);
+    }
+    load_plane(z0, pre);
+    load_b(z0 - 1, B0, R0);
+
+    // step k: u1 on plane k with b of plane k (bu, ru_), u2 on plane k - 1
+    // with b of plane k - 1 (bp2); b of plane k + 1 is loaded into (bn, rn)
+    auto step = [&](int64_t k, const S* bu, const S* bp2, S* bn, const S* rb, S* rn) {
+        store_plane(pre, L[slot(k + 1)]);
+        if (k + 2 <= z1 + 1) load_plane(k + 2, pre);
+        if (k + 1 <= z1) load_b(k + 1, bn, rn);
+        __syncthreads();
+        {
+            const S* lm = L[slot(k - 1)];
+            const S* l0 = L[slot(k)];
+            const S* lp = L[slot(k + 1)];
+            S* o = L1[slot(k)];
+            const bool kint = k >= 1 && k <= g.nz;
+#pragma unroll
+            for (int i = 0; i < P; ++i)
+                if (tk[i] != 0) o[t1[i]] = u1_point(kint, tk[i], tu[i], bu[i], lm, l0, lp);
+#pragma unroll
+            for (int j = 0; j < PR; ++j)
+                if (rk[j] != 0) o[r1[j]] = u1_point(kint, rk[j], ru[j], rb[j], lm, l0, lp);
+        }
+        __syncthreads();
+        if (k - 1 >= z0) {
+            const S* lm = L1[slot(k - 2)];
+            const S* l0 = L1[slot(k - 1)];
+            const S* lp = L1[slot(k)];
+            S* dp = dst + (k - 1) * g.sz;
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                if (tk[i] != 2) continue;
+                const int c = t1[i];
+                auto ld = [&](int ox, int oy, int oz) -> S {
+                    const S* pl = oz < 0 ? lm : (oz > 0 ? lp : l0);
+                    return pl[c + oy * W1 + ox];
+                };
+                st_stream(dp + toff[i], jacobi_value<S, 3, FD>(h2, omega, bp2[i], l0[c], ld));
+            }
+        }
+    };
+    for (int64_t k = z0 - 1; k <= z1; k += 3) {
+        step(k, B0, B2, B1, R0, R1);
+        if (k + 1 > z1) break;
+        step(k + 1, B1, B0, B2, R1, R2);
+        if (k + 2 > z1) break;
+        step(k + 2, B2, B1, B0, R2, R0);
+    }
+}
+
+// The 27-point pair update of k_jacobi3_q1_pairs on LDS plane data: the pair
+// whose row starts (column x-1) at index cl of planes pl[0..2] (row stride RW).
+template <typename S, int RW, typename V2>
+__device__ __forceinline__ V2 q1_jacobi_pair(const S* const* pls, int cl, V2 bq, V2 h2v, V2 omv)
+{
+    V2 lo[3][3], hi[3][3];
+#pragma unroll
+    for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy) {
+            const V2* row = reinterpret_cast<const V2*>(pls[oz] + cl + (oy - 1) * RW);
+            lo[oz][oy] = row[0];
+            hi[oz][oy] = row[1];
+        }
+    V2 acc = {S(0), S(0)};
+#pragma unroll
+    for (int oz = -1; oz <= 1; ++oz)
+#pragma unroll
+        for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+            for (int ox = -1; ox <= 1; ++ox) {
+                const S w = weight<S, 3, Q1>(ox, oy, oz);
+                if (w == S(0)) continue;
+                const V2 a = lo[oz + 1][oy + 1], c2 = hi[oz + 1][oy + 1];
+                const V2 val = ox < 0 ? a : (ox > 0 ? c2 : (V2){a.y, c2.x});
+                const V2 wv = {w, w};
+                acc = __builtin_elementwise_fma(wv, val, acc);
+            }
+    const V2 ctr = {lo[1][1].y, hi[1][1].x};
+    const V2 q = h2v * bq - acc;
+    const V2 sc = {over_centre<S, 3, Q1>(q.x), over_centre<S, 3, Q1>(q.y)};
+    return __builtin_elementwise_fma(omv, sc, ctr);
+}
+
+// Two weighted Jacobi sweeps with the 27-point stencil in one pass over memory:
+// the structure of k_jacobi3_fd_two (u1 on the tile grown by one, b loaded once
+// per point into a register ring) with the pair update of k_jacobi3_q1_pairs
+// at the tile points of both sweeps.  A thread's u1 pairs are its u2 pairs
+// (x, x+1), x - x0 even; the u plane region starts at x0 - 3 and the u1 region
+// at x0 - 1, so the 16-byte loads of both updates are aligned (the region rows
+// have even lengths).  The grown-tile points around the tile take the
+// single-point form, which rounds identically.
+template <typename S, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT)
+k_jacobi3_q1_two(const S* __restrict__ src, S* __restrict__ dst, const S* __restrict__ b, Geo g,
+                 double h2d, double omegad, StreamWork wk)
+{
+    typedef S v2 __attribute__((ext_vector_type(2)));
+    static_assert(TX % 2 == 0, "pairs");
+    constexpr int W = TX + 6, HH = TY + 4, NCOL = W * HH;  // u: x0-3 .., y0-2 ..
+    constexpr int W1 = TX + 2, H1 = TY + 2, N1 = W1 * H1;  // u1: x0-1 .., y0-1 ..
+    constexpr int NR = 2 * W1 + 2 * (H1 - 2);
+    constexpr int NPT = TX / 2 * TY;
+    constexpr int M = (NCOL + NT - 1) / NT;
+    constexpr int P = (NPT + NT - 1) / NT;
+    constexpr int PR = (NR + NT - 1) / NT;
+    __shared__ __attribute__((aligned(16))) S L[3][NCOL];
+    __shared__ __attribute__((aligned(16))) S L1[3][N1];
+
+    const int64_t work = xcd_block(wk.nblocks);
+    const int64_t tiles = (int64_t)wk.tiles_x * wk.tiles_y;
+    const int64_t chunk = work / tiles;
+    const int64_t tile = work % tiles;
+    const int64_t x0 = 1 + (tile % wk.tiles_x) * TX;
+    const int64_t y0 = 1 + (tile / wk.tiles_x) * TY;
+    const int64_t z0 = 1 + (chunk * g.nz) / wk.chunks;
+    const int64_t z1 = 1 + ((chunk + 1) * g.nz) / wk.chunks;
+    const int tid = threadIdx.x;
+
+    int coff[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int c = tid + NT * m;
+        const int64_t x = x0 - 3 + c % W, y = y0 - 2 + c / W;
+        const bool ok = c < NCOL && x >= 0 && x <= g.nx + 1 && y >= 0 && y <= g.ny + 1;
+        coff[m] = ok ? (int)(y * g.sy + x) : -1;
+    }
+    auto kind_of = [&](int64_t x, int64_t y) {
+        if (x > g.nx + 1 || y > g.ny + 1) return 0;
+        return (x >= 1 && x <= g.nx && y >= 1 && y <= g.ny) ? 2 : 1;
+    };
+    // tile pairs: kinds of both points, u row index of column x-1 (centre
+    // row), u1 index of column x-1 (centre row), global offset of x
+    int ka[P], kb[P], cu[P], c1[P], toff[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const int t = tid + NT * i;
+        const int tx = 2 * (t % (TX / 2)), ty = t / (TX / 2);
+        const int64_t x = x0 + tx, y = y0 + ty;
+        ka[i] = t < NPT ? kind_of(x, y) : 0;
+        kb[i] = t < NPT ? kind_of(x + 1, y) : 0;
+        cu[i] = (ty + 2) * W + tx + 2;
+        c1[i] = (ty + 1) * W1 + tx;
+        toff[i] = ka[i] == 2 ? (int)(y * g.sy + x) : 0;
+    }
+    int rk[PR], ru[PR], r1[PR], roff[PR];
+#pragma unroll
+    for (int j = 0; j < PR; ++j) {
+        const int r = tid + NT * j;
+        int lx, ly;
+        if (r < W1) {
+            lx = r; ly = 0;
+        } else if (r < 2 * W1) {
+            lx = r - W1; ly = H1 - 1;
+        } else {
+            const int q = r - 2 * W1;
+            lx = q < H1 - 2 ? 0 : W1 - 1;
+            ly = 1 + q % (H1 - 2);
+        }
+        const int64_t x = x0 - 1 + lx, y = y0 - 1 + ly;
+        rk[j] = r < NR ? kind_of(x, y) : 0;
+        ru[j] = (ly + 1) * W + (lx + 2);
+        r1[j] = ly * W1 + lx;
+        roff[j] = rk[j] == 2 ? (int)(y * g.sy + x) : 0;
+    }
+
+    auto load_plane = [&](int64_t k, S* v) {
+        const bool kin = k >= 0 && k <= g.nz + 1;
+        const S* sp = src + (kin ? k : 0) * g.sz;
+#pragma unroll
+        for (int m = 0; m < M; ++m) v[m] = (kin && coff[m] >= 0) ? sp[coff[m]] : S(0);
+    };
+    auto store_plane = [&](const S* v, S* lp) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int c = tid + NT * m;
+            if (c < NCOL) lp[c] = v[m];
+        }
+    };
+    auto load_b = [&](int64_t k, v2* bt, S* br) {
+        const bool kin = k >= 1 && k <= g.nz;
+        const S* bp = b + (kin ? k : 0) * g.sz;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            bt[i].x = (kin && ka[i] == 2) ? bp[toff[i]] : S(0);
+            bt[i].y = (kin && kb[i] == 2) ? bp[toff[i] + 1] : S(0);
+        }
+#pragma unroll
+        for (int j = 0; j < PR; ++j) br[j] = (kin && rk[j] == 2) ? bp[roff[j]] : S(0);
+    };
+    auto slot = [&](int64_t k) { return (int)((k - z0 + 6) % 3); };
+
+    const S h2 = (S)h2d, omega = (S)omegad;
+    const v2 h2v = {h2, h2}, omv = {omega, omega};
+
+    S pre[M];
+    v2 B0[P], B1[P], B2[P];
+    S R0[PR], R1[PR], R2[PR];
+    {
+        S t[M];
+        load_plane(z0 - 2, t);
+        store_plane(t, L[slot(z0 - 2)]);
+        load_plane(z0 - 1, t);
+        store_plane(t, L[slot(z0 - 1)]);
+    }
+    load_plane(z0, pre);
+    load_b(z0 - 1, B0, R0);
+
+    auto step = [&](int64_t k, const v2* bu, const v2* bp2, v2* bn, const S* rb, S* rn) {
+        store_plane(pre, L[slot(k + 1)]);
+        if (k + 2 <= z1 + 1) load_plane(k + 2, pre);
+        if (k + 1 <= z1) load_b(k + 1, bn, rn);
+        __syncthreads();
+        {
+            const S* pls[3] = {L[slot(k - 1)], L[slot(k)], L[slot(k + 1)]};
+            S* o = L1[slot(k)];
+            const bool kint = k >= 1 && k <= g.nz;
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                if (ka[i] == 0 && kb[i] == 0) continue;
+                const v2 out = q1_jacobi_pair<S, W>(pls, cu[i], bu[i], h2v, omv);
+                const S* l0 = pls[1];
+                o[c1[i] + 1] = (kint && ka[i] == 2) ? out.x : l0[cu[i] + 1];
+                if (kb[i] != 0) o[c1[i] + 2] = (kint && kb[i] == 2) ? out.y : l0[cu[i] + 2];
+            }
+#pragma unroll
+            for (int j = 0; j < PR; ++j) {
+                if (rk[j] == 0) continue;
+                const int c = ru[j];
+                const S* l0 = pls[1];
+                S v = l0[c];
+                if (kint && rk[j] == 2) {
+                    auto ld = [&](int ox, int oy, int oz) -> S {
+                        return pls[oz + 1][c + oy * W + ox];
+                    };
+                    v = jacobi_value<S, 3, Q1>(h2, omega, rb[j], l0[c], ld);
+                }
+                o[r1[j]] = v;
+            }
+        }
+        __syncthreads();
+        if (k - 1 >= z0) {
+            const S* pls[3] = {L1[slot(k - 2)], L1[slot(k - 1)], L1[slot(k)]};
+            S* dp = dst + (k - 1) * g.sz;
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                if (ka[i] != 2) continue;
+                const v2 out = q1_jacobi_pair<S, W1>(pls, c1[i], bp2[i], h2v, omv);
+                S* p = dp + toff[i];
+                if (kb[i] == 2 && (((uintptr_t)p & (2 * sizeof(S) - 1)) == 0)) {
+                    __builtin_nontemporal_store(out, reinterpret_cast<v2*>(p));
+                } else {
+                    st_stream(p, out.x);
+                    if (kb[i] == 2) st_stream(p + 1, out.y);
+                }
+            }
+        }
+    };
+    for (int64_t k = z0 - 1; k <= z1; k += 3) {
+        step(k, B0, B2, B1, R0, R1);
+        if (k + 1 > z1) break;
+        step(k + 1, B1, B0, B2, R1, R2);
+        if (k + 2 > z1) break;
+        step(k + 2, B2, B1, B0, R2, R0);
+    }
+}
+
 // Workgroups that fit the device at once for kernel kern (queried once per
 // kernel by the caller) and the z-chunking that fills them.
 template <typename K>
@@ -395,6 +793,44 @@ cs_status jacobi3_t(const Geo& g, const void* src, void* dst, const void* b, dou
     return check_launch("streaming jacobi");
 }
 
+// Two sweeps per launch (the caller pairs the sweeps).  Tile 64 x 16; FP64
+// runs best with 512 threads, FP32 with 256 (measured at 256^3).
+#ifndef CS_J2_TX
+#define CS_J2_TX 64
+#define CS_J2_TY 16
+#define CS_J2_NT64 512
+#define CS_J2_NT32 256
+#define CS_J2_FILL 1
+#endif
+#ifndef CS_J2Q_TX
+#define CS_J2Q_TX 64
+#define CS_J2Q_TY 16
+#define CS_J2Q_NT64 512
+#define CS_J2Q_NT32 256
+#endif
+template <typename S, int ST>
+cs_status jacobi3_two_t(const Geo& g, const void* src, void* dst, const void* b, double h2,
+                        double omega, hipStream_t s)
+{
+    constexpr bool f64 = sizeof(S) == 8;
+    if (ST == Q1) {
+        constexpr int TX = CS_J2Q_TX, TY = CS_J2Q_TY, NT = f64 ? CS_J2Q_NT64 : CS_J2Q_NT32;
+        auto kern = k_jacobi3_q1_two<S, TX, TY, NT>;
+        static const int64_t resident = resident_of(kern, NT);
+        const StreamWork wk = chunk_tiles(g, TX, TY, resident);
+        hipLaunchKernelGGL(kern, dim3((unsigned)wk.nblocks), dim3(NT), 0, s, (const S*)src,
+                           (S*)dst, (const S*)b, g, h2, omega, wk);
+        return check_launch("streaming jacobi (two sweeps, 27-point)");
+    }
+    constexpr int TX = CS_J2_TX, TY = CS_J2_TY, NT = f64 ? CS_J2_NT64 : CS_J2_NT32;
+    auto kern = k_jacobi3_fd_two<S, TX, TY, NT>;
+    static const int64_t resident = resident_of(kern, NT);
+    const StreamWork wk = chunk_tiles(g, TX, TY, resident * CS_J2_FILL);
+    hipLaunchKernelGGL(kern, dim3((unsigned)wk.nblocks), dim3(NT), 0, s, (const S*)src, (S*)dst,
+                       (const S*)b, g, h2, omega, wk);
+    return check_launch("streaming jacobi (two sweeps, 7-point)");
+}
+
 template <typename S, int ST>
 cs_status residual3_t(const Geo& g, const void* u, const void* b, void* r, double h2,
                       Partial* partials, double* norms, hipStream_t s)
@@ -456,6 +892,22 @@ cs_status launch_jacobi3_stream(int dtype, int stencil, const Geo& g, const void
                              : jacobi3_t<double, Q1>(g, src, dst, b, h2, omega, s);
     return stencil == FD ? jacobi3_t<float, FD>(g, src, dst, b, h2, omega, s)
                          : jacobi3_t<float, Q1>(g, src, dst, b, h2, omega, s);
+}
+
+bool jacobi3_two_supported(int stencil, const Geo& g)
+{
+    (void)stencil;
+    return stream_supported(g);
+}
+
+cs_status launch_jacobi3_two(int dtype, int stencil, const Geo& g, const void* src, void* dst,
+                             const void* b, double h2, double omega, hipStream_t s)
+{
+    if (dtype == 0)
+        return stencil == FD ? jacobi3_two_t<double, FD>(g, src, dst, b, h2, omega, s)
+                             : jacobi3_two_t<double, Q1>(g, src, dst, b, h2, omega, s);
+    return stencil == FD ? jacobi3_two_t<float, FD>(g, src, dst, b, h2, omega, s)
+                         : jacobi3_two_t<float, Q1>(g, src, dst, b, h2, omega, s);
 }
 
 cs_status launch_residual3_stream(int dtype, int stencil, const Geo& g, const void* u,
