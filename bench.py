@@ -170,10 +170,12 @@ def run_poisson3d(a):
     pts = N ** 3
     updates_per_step = 4 * SWEEPS * pts
     value = updates_per_step / (ms_step * 1e-3) / 1e9
-    # sweeps per pass over memory: one for Gauss-Seidel (fused), two for Jacobi
-    # (the library pairs the sweeps and keeps the intermediate iterate on chip),
-    # so a Jacobi pass moves the 24 bytes per point of one sweep for two updates
-    per_pass = {"gs_fd7": 1, "gs_q1_27": 1, "jacobi_fd7": 2, "jacobi_q1_27": 2}
+    # sweeps per pass over memory: the library pairs the red-black and the
+    # Jacobi sweeps (the intermediate iterate stays on chip), so such a pass
+    # moves the 24 bytes per point of one sweep for two updates; the 8-colour
+    # sweep is one per pass
+    per_pass = {"gs_fd7": 2 if fused_rows["fd7"] else 1, "gs_q1_27": 1, "jacobi_fd7": 2,
+                "jacobi_q1_27": 2}
     rows = {}
     moved = 0.0
     for r in ROWS[:4]:
@@ -191,7 +193,11 @@ def run_poisson3d(a):
     if dom.startswith("gs"):
         st_name = "fd7" if dom == "gs_fd7" else "q1_27"
         fused = fused_rows[st_name]
-        if fused:
+        if fused and st_name == "fd7":
+            kernel = "fused_gs_two_sweeps_fd7"
+            launches = SWEEPS // 2
+            bytes_per_launch = BYTES_PER_UPDATE * pts
+        elif fused:
             kernel = "fused_gs_sweep_" + st_name
             launches = SWEEPS
             bytes_per_launch = BYTES_PER_UPDATE * pts

@@ -231,8 +231,15 @@ cs_status cs_gs_sweeps(cs_grid g, int32_t nsweeps, void* u_tmp, void* stream)
         if ((st = launch_halo_copy(dt, dim, g->geo, g->u, u_tmp, s)) != CS_OK) return st;
         const void* src = g->u;
         void* dst = u_tmp;
-        for (int32_t it = 0; it < nsweeps; ++it) {
-            st = launch_fused_sweep(dt, dim, sten, g->geo, src, dst, g->b, h2, s);
+        const bool pairs = fused_two_supported(dt, dim, sten, g->geo);
+        for (int32_t it = 0; it < nsweeps;) {
+            if (pairs && nsweeps - it >= 2) {
+                st = launch_fused_two(dt, dim, sten, g->geo, src, dst, g->b, h2, s);
+                it += 2;
+            } else {
+                st = launch_fused_sweep(dt, dim, sten, g->geo, src, dst, g->b, h2, s);
+                it += 1;
+            }
             if (st != CS_OK) return st;
             void* nsrc = dst;
             dst = (void*)src;

@@ -65,6 +65,11 @@ cs_status launch_residual(int dtype, int dim, int stencil, const Geo& g, const v
 cs_status launch_fused_sweep(int dtype, int dim, int stencil, const Geo& g, const void* src,
                              void* dst, const void* b, double h2, hipStream_t s);
 bool fused_supported(int dtype, int dim, int stencil, const Geo& g);
+// Two red-black sweeps (7-point, 3D) in one pass over memory, src -> dst: the
+// iterate of two fused sweeps bit for bit.
+bool fused_two_supported(int dtype, int dim, int stencil, const Geo& g);
+cs_status launch_fused_two(int dtype, int dim, int stencil, const Geo& g, const void* src,
+                           void* dst, const void* b, double h2, hipStream_t s);
 // Second (fixed-order) stage of the residual reduction over `count` partials.
 cs_status launch_residual_finish(const Partial* partials, int count, double* norms, hipStream_t s);
 // Mixed-precision refinement: FP64 residual with the scaled FP32 copy and

@@ -229,6 +229,177 @@ __device__ __forceinline__ void fd3_tile(const T* __restrict__ src, T* __restric
 }
 
 // ---------------------------------------------------------------------------
+// Two red-black sweeps of the 7-point stencil in one pass over memory.
+//
+// The second sweep trails the first by two planes.  At plane step k: the red
+// points of plane k take their first-sweep values (from the previous
+// iterate), the black points of plane k-1 theirs (from those reds), the red
+// points of plane k-2 their second-sweep values (from the first-sweep
+// blacks), and the black points of plane k-3 theirs; plane k-3 is then final.
+// Every value is computed from the same neighbour values as in the four colour
+// passes, so the result equals them bit for bit.  A tile recomputes the rings
+// it needs -- first-sweep red on T+3, black on T+2, second-sweep red on T+1,
+// black on T -- from the previous iterate on T+4.  A column (x, y) takes part
+// in all four updates of a step or in none: (x, y, k) red means (x, y, k-1)
+// black, (x, y, k-2) red, (x, y, k-3) black.
+//
+// Each thread owns columns of T+4 and keeps planes k-4 .. k+1+D of them, and
+// their b values, in a register ring; the loop is unrolled over the ring, so
+// no value is moved.  The in-plane neighbours come from LDS snapshots of planes
+// k, k-1, k-2 and k-3 taken at the top of the step, when each holds what its
+// update reads.  NB = 2 alternates two snapshot sets (one barrier per step),
+// NB = 1 reuses one (two barriers).  The finished plane goes to an LDS row
+// buffer and is stored by whole rows one step later.  A chunk of output planes
+// [z0, z1) runs steps z0-3 .. z1+2 and reads u on planes z0-4 .. z1+3.
+// ---------------------------------------------------------------------------
+template <typename T, int TX, int TY, int NT, int D, int NB>
+__device__ __forceinline__ void fd3_tile_two(const T* __restrict__ src, T* __restrict__ dst,
+                                             const T* __restrict__ b, const Geo& g, T h2,
+                                             const TileBox& tb)
+{
+    constexpr int W = TX + 8, HH = TY + 8, NCOL = W * HH;
+    constexpr int M = (NCOL + NT - 1) / NT;
+    constexpr int R = 6 + D;
+    __shared__ T lds[NB][4][NCOL];
+    __shared__ T lout[2][TX * TY];
+    const int64_t x0 = tb.x0, y0 = tb.y0, z0 = tb.z0, z1 = tb.z1;
+    const int tid = threadIdx.x;
+
+    constexpr int PO = (TX * TY + NT - 1) / NT;
+    static_assert(PO <= 32, "output mask is 32 bits");
+    int oglb[PO];
+    unsigned omask = 0;
+#pragma unroll
+    for (int i = 0; i < PO; ++i) {
+        const int p = tid + NT * i;
+        const int ty = p / TX, tx = p % TX;
+        const bool ok = p < TX * TY && x0 + tx <= g.nx && y0 + ty <= g.ny;
+        oglb[i] = ok ? (int)((y0 + ty) * g.sy + x0 + tx) : 0;
+        omask |= ok ? 1u << i : 0u;
+    }
+    auto write_rows = [&](const T* lo, T* dp) {
+#pragma unroll
+        for (int i = 0; i < PO; ++i)
+            if ((omask >> i) & 1u) st_stream(dp + oglb[i], lo[tid + NT * i]);
+    };
+
+    // flags: bit0 valid; bits 1..4 interior and inside T+3, T+2, T+1, T;
+    // bit5 colour parity of (x, y)
+    int off[M], flags[M], oidx[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int c = tid + NT * m;
+        const int ly = c / W, lx = c % W;
+        const int64_t x = x0 - 4 + lx, y = y0 - 4 + ly;
+        const bool valid = c < NCOL && x >= 0 && x <= g.nx + 1 && y >= 0 && y <= g.ny + 1;
+        const bool interior = valid && x >= 1 && x <= g.nx && y >= 1 && y <= g.ny;
+        int f = valid ? 1 : 0;
+#pragma unroll
+        for (int r = 1; r <= 4; ++r) {
+            const bool in = interior && lx >= r && lx <= W - 1 - r && ly >= r && ly <= HH - 1 - r;
+            f |= in ? 1 << r : 0;
+        }
+        const int par = (int)(((x - 1) + (y - 1) + g.parity) & 1);
+        flags[m] = f | (par << 5);
+        off[m] = valid ? (int)(y * g.sy + x) : 0;
+        oidx[m] = (ly - 4) * TX + (lx - 4);
+    }
+
+    T U[R][M];
+    T B[R][M];
+    auto load_u = [&](int64_t k, T* v) {
+        const bool kin = k >= 0 && k <= g.nz + 1;
+        const T* sp = src + (kin ? k : 0) * g.sz;
+#pragma unroll
+        for (int m = 0; m < M; ++m) v[m] = (kin && (flags[m] & 1)) ? sp[off[m]] : T(0);
+    };
+    auto load_b = [&](int64_t k, T* v) {
+        const bool kin = k >= 1 && k <= g.nz;
+        const T* bp = b + (kin ? k : 0) * g.sz;
+#pragma unroll
+        for (int m = 0; m < M; ++m) v[m] = (kin && (flags[m] & 2)) ? bp[off[m]] : T(0);
+    };
+    // plane p lives in ring slot (p - k0 + 4) mod R
+    const int64_t k0 = z0 - 3, klast = z1 + 2;
+#pragma unroll
+    for (int s = 0; s < R; ++s)
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            U[s][m] = T(0);
+            B[s][m] = T(0);
+        }
+#pragma unroll
+    for (int d = 0; d < D + 2; ++d) load_u(k0 - 1 + d, U[3 + d]);  // planes k0-1 .. k0+D
+#pragma unroll
+    for (int d = 0; d < D; ++d) load_b(k0 + d, B[4 + d]);          // b of k0 .. k0+D-1
+
+    // planes each update runs on (besides being interior planes)
+    auto in_range = [&](int64_t p, int64_t lo, int64_t hi) { return p >= lo && p <= hi && p >= 1 && p <= g.nz; };
+    for (int64_t kb = k0; kb <= klast; kb += R) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t k = kb + r;
+            if (k > klast) break;
+            T* u4 = U[r % R];        // plane k-4
+            T* u3 = U[(r + 1) % R];  // k-3
+            T* u2 = U[(r + 2) % R];  // k-2
+            T* u1 = U[(r + 3) % R];  // k-1
+            T* u0 = U[(r + 4) % R];  // k
+            T* up = U[(r + 5) % R];  // k+1
+            const T* b3 = B[(r + 1) % R];
+            const T* b2 = B[(r + 2) % R];
+            const T* b1 = B[(r + 3) % R];
+            const T* b0 = B[(r + 4) % R];
+            if (k + 1 + D <= z1 + 3) load_u(k + 1 + D, U[(r + 5 + D) % R]);
+            if (k + D <= klast) load_b(k + D, B[(r + 4 + D) % R]);
+            if (NB == 1) __syncthreads();
+            T (*snap)[NCOL] = lds[NB == 2 ? (int)(k & 1) : 0];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int c = tid + NT * m;
+                if (c < NCOL) {
+                    snap[0][c] = u0[m];
+                    snap[1][c] = u1[m];
+                    snap[2][c] = u2[m];
+                    snap[3][c] = u3[m];
+                }
+            }
+            __syncthreads();
+            // plane k-4, finished at step k-1
+            if (k - 4 >= z0 && k - 4 < z1) write_rows(lout[(k - 1) & 1], dst + (k - 4) * g.sz);
+            const bool r1 = in_range(k, z0 - 3, z1 + 2);
+            const bool k1 = in_range(k - 1, z0 - 2, z1 + 1);
+            const bool r2 = in_range(k - 2, z0 - 1, z1);
+            const bool k2 = in_range(k - 3, z0, z1 - 1);
+            const int kc = (int)((k - 1) & 1);
+            T* lo = lout[k & 1];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int c = tid + NT * m;
+                const int f = flags[m];
+                const bool sel = (((f >> 5) + kc) & 1) == 0;  // (x, y, k) red
+                if (sel) {
+                    auto upd = [&](const T* pl, T zm, T zp, T bq) -> T {
+                        auto ld = [&](int ox, int oy, int oz) -> T {
+                            return oz < 0 ? zm : oz > 0 ? zp : pl[c + oy * W + ox];
+                        };
+                        return gs_value<T, 3, FD>(h2, bq, ld);
+                    };
+                    if (r1 && (f & 2)) u0[m] = upd(snap[0], u1[m], up[m], b0[m]);
+                    if (k1 && (f & 4)) u1[m] = upd(snap[1], u2[m], u0[m], b1[m]);
+                    if (r2 && (f & 8)) u2[m] = upd(snap[2], u3[m], u1[m], b2[m]);
+                    if (k2 && (f & 16)) u3[m] = upd(snap[3], u4[m], u2[m], b3[m]);
+                }
+                if (k2 && (f & 16)) lo[oidx[m]] = u3[m];
+            }
+        }
+    }
+    // the last plane, z1 - 1, was finished at step z1 + 2
+    __syncthreads();
+    if (z1 - 1 >= z0) write_rows(lout[klast & 1], dst + (z1 - 1) * g.sz);
+}
+
+// ---------------------------------------------------------------------------
 // 8-colour sweep of the 27-point trilinear stencil.
 //
 // Colour = px + 2 py + 4 pz (parities of x, y, z).  The face weights of this

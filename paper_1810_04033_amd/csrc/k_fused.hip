@@ -41,6 +41,16 @@ k_fused_fd3(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict_
     fd3_tile<T, TX, TY, NT, D>(src, dst, b, g, h2, tb);
 }
 
+template <typename T, int TX, int TY, int NT, int D, int NB>
+__global__ void __launch_bounds__(NT)
+k_fused_fd3_two(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict__ b, Geo g,
+                T h2, FusedWork wk)
+{
+    const TileBox tb = tile_box<TX, TY>(g, wk.tiles_x, wk.tiles_y, wk.chunks,
+                                        xcd_ordered_block(wk.nblocks));
+    fd3_tile_two<T, TX, TY, NT, D, NB>(src, dst, b, g, h2, tb);
+}
+
 template <typename T, int TX, int TY, int NT, int WPE, bool PAIRS>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_fused_q1_3(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict__ b, Geo g,
@@ -54,13 +64,13 @@ k_fused_q1_3(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict
         q1_3_tile<T, TX, TY, NT>(src, dst, b, g, h2, tb);
 }
 
-// Resident workgroups of a kernel on the current device (queried once per
-// kernel; the library runs on devices of one kind).
+// Resident workgroups of a kernel on the current device.  Callers keep the
+// result in a static of their own template instantiation, so it is queried once
+// per kernel (the library runs on devices of one kind); a cache here would be
+// shared by every kernel of the same signature.
 template <typename K>
 int64_t resident_blocks(K kern, int nt)
 {
-    static int64_t cached = 0;
-    if (cached > 0) return cached;
     int per_cu = 0, dev = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, 0) != hipSuccess ||
         hipGetDevice(&dev) != hipSuccess ||
@@ -68,23 +78,20 @@ int64_t resident_blocks(K kern, int nt)
         (void)hipGetLastError();
         return 256;
     }
-    cached = (int64_t)(per_cu > 0 ? per_cu : 1) * cus;
-    return cached;
+    return (int64_t)(per_cu > 0 ? per_cu : 1) * cus;
 }
 
 // Chunks so that the grid is one full wave of resident workgroups, each chunk
-// at least 8 planes deep.
-template <typename K>
-FusedWork plan_work(K kern, int nt, const Geo& g, int tx, int ty)
+// at least min_depth planes deep.
+FusedWork plan_work(int64_t resident, const Geo& g, int tx, int ty, int min_depth = 8)
 {
     FusedWork wk;
     wk.tiles_x = (int)((g.nx + tx - 1) / tx);
     wk.tiles_y = (int)((g.ny + ty - 1) / ty);
     const int64_t tiles = (int64_t)wk.tiles_x * wk.tiles_y;
-    const int64_t resident = resident_blocks(kern, nt);
     int64_t chunks = resident / tiles;
     if (chunks < 1) chunks = 1;
-    if (chunks > g.nz / 8) chunks = g.nz / 8 > 0 ? g.nz / 8 : 1;
+    if (chunks > g.nz / min_depth) chunks = g.nz / min_depth > 0 ? g.nz / min_depth : 1;
     wk.chunks = (int)chunks;
     wk.nblocks = tiles * chunks;
     return wk;
@@ -95,10 +102,25 @@ cs_status fused_fd3_t(const Geo& g, const void* src, void* dst, const void* b, d
                       hipStream_t s)
 {
     auto kern = k_fused_fd3<T, TX, TY, NT, D>;
-    const FusedWork wk = plan_work(kern, NT, g, TX, TY);
+    static const int64_t resident = resident_blocks(kern, NT);
+    const FusedWork wk = plan_work(resident, g, TX, TY);
     hipLaunchKernelGGL(kern, dim3((unsigned)wk.nblocks), dim3(NT), 0, s, (const T*)src, (T*)dst,
                        (const T*)b, g, (T)h2, wk);
     return check_launch("fused 7-point sweep");
+}
+
+// Two sweeps per launch: the chunks carry 3 extra planes of work on each side,
+// so they are kept at least 16 planes deep.
+template <typename T, int TX, int TY, int NT, int D, int NB>
+cs_status fused_fd3_two_t(const Geo& g, const void* src, void* dst, const void* b, double h2,
+                          hipStream_t s)
+{
+    auto kern = k_fused_fd3_two<T, TX, TY, NT, D, NB>;
+    static const int64_t resident = resident_blocks(kern, NT);
+    const FusedWork wk = plan_work(resident, g, TX, TY, 16);
+    hipLaunchKernelGGL(kern, dim3((unsigned)wk.nblocks), dim3(NT), 0, s, (const T*)src, (T*)dst,
+                       (const T*)b, g, (T)h2, wk);
+    return check_launch("fused 7-point double sweep");
 }
 
 template <typename T, int TX, int TY, int NT, int WPE, bool PAIRS>
@@ -106,7 +128,8 @@ cs_status fused_q1_3_t(const Geo& g, const void* src, void* dst, const void* b, 
                        hipStream_t s)
 {
     auto kern = k_fused_q1_3<T, TX, TY, NT, WPE, PAIRS>;
-    const FusedWork wk = plan_work(kern, NT, g, TX, TY);
+    static const int64_t resident = resident_blocks(kern, NT);
+    const FusedWork wk = plan_work(resident, g, TX, TY);
     hipLaunchKernelGGL(kern, dim3((unsigned)wk.nblocks), dim3(NT), 0, s, (const T*)src, (T*)dst,
                        (const T*)b, g, (T)h2, wk);
     return check_launch("fused 27-point sweep");
@@ -141,6 +164,40 @@ bool fused_supported(int dtype, int dim, int stencil, const Geo& g)
     // column offsets y*sy + x are 32-bit inside the kernels
     const bool small = (g.ny + 2) * g.sy < ((int64_t)1 << 31);
     return dim == 3 && small;
+}
+
+bool fused_two_supported(int dtype, int dim, int stencil, const Geo& g)
+{
+    return stencil == FD && fused_supported(dtype, dim, stencil, g);
+}
+
+// Tile, threads, prefetch depth and snapshot sets of the double sweep per
+// precision (measured at 256^3): FP64 64 x 16 with two snapshot sets, FP32
+// 64 x 32 with one.
+#ifndef CS_F2_TX
+#define CS_F2_TX 64
+#define CS_F2_TY 16
+#define CS_F2_NT 1024
+#define CS_F2_D 2
+#define CS_F2_NB 2
+#define CS_F2_TX32 64
+#define CS_F2_TY32 32
+#define CS_F2_NT32 1024
+#define CS_F2_D32 2
+#define CS_F2_NB32 1
+#endif
+cs_status launch_fused_two(int dtype, int dim, int stencil, const Geo& g, const void* src,
+                           void* dst, const void* b, double h2, hipStream_t s)
+{
+    if (!fused_two_supported(dtype, dim, stencil, g)) {
+        set_error("fused double sweep not available for this grid");
+        return CS_EUNSUPPORTED;
+    }
+    return dtype == 0
+               ? fused_fd3_two_t<double, CS_F2_TX, CS_F2_TY, CS_F2_NT, CS_F2_D, CS_F2_NB>(
+                     g, src, dst, b, h2, s)
+               : fused_fd3_two_t<float, CS_F2_TX32, CS_F2_TY32, CS_F2_NT32, CS_F2_D32, CS_F2_NB32>(
+                     g, src, dst, b, h2, s);
 }
 
 cs_status launch_fused_sweep(int dtype, int dim, int stencil, const Geo& g, const void* src,
