@@ -174,8 +174,8 @@ def run_poisson3d(a):
     # Jacobi sweeps (the intermediate iterate stays on chip), so such a pass
     # moves the 24 bytes per point of one sweep for two updates; the 8-colour
     # sweep is one per pass
-    per_pass = {"gs_fd7": 2 if fused_rows["fd7"] else 1, "gs_q1_27": 1, "jacobi_fd7": 2,
-                "jacobi_q1_27": 2}
+    per_pass = {"gs_" + k: (grids[k][0].sweeps_per_pass() if fused_rows[k] else 1) for k in grids}
+    per_pass.update({"jacobi_" + k: grids[k][1].sweeps_per_pass(jacobi=True) for k in grids})
     rows = {}
     moved = 0.0
     for r in ROWS[:4]:
@@ -193,8 +193,8 @@ def run_poisson3d(a):
     if dom.startswith("gs"):
         st_name = "fd7" if dom == "gs_fd7" else "q1_27"
         fused = fused_rows[st_name]
-        if fused and st_name == "fd7":
-            kernel = "fused_gs_two_sweeps_fd7"
+        if fused and per_pass[dom] == 2:
+            kernel = "fused_gs_two_sweeps_" + st_name
             launches = SWEEPS // 2
             bytes_per_launch = BYTES_PER_UPDATE * pts
         elif fused:
@@ -206,9 +206,13 @@ def run_poisson3d(a):
             nc = 2 if st_name == "fd7" else 8
             launches = SWEEPS * nc
             bytes_per_launch = BYTES_PER_UPDATE * pts / nc
-    else:
+    elif per_pass[dom] == 2:
         kernel = "jacobi_two_sweeps_" + dom.split("_", 1)[1]
         launches = SWEEPS // 2
+        bytes_per_launch = BYTES_PER_UPDATE * pts
+    else:
+        kernel = "jacobi_" + dom.split("_", 1)[1]
+        launches = SWEEPS
         bytes_per_launch = BYTES_PER_UPDATE * pts
     # the row also holds the halo copy (and the copy back for odd counts); the
     # mean launch duration below charges that to the kernel (conservative)

@@ -240,8 +240,31 @@ cs_status cs_graph_launch(cs_graph gr, void* stream);
 cs_status cs_graph_destroy(cs_graph gr);
 
 /* *out = 1 if cs_gs_sweeps with a work array runs this grid's sweeps as fused
- * single passes, 0 if it falls back to one launch per colour. */
+ * passes over memory, 0 if it falls back to one launch per colour. */
 cs_status cs_gs_fused(cs_grid g, int32_t* out);
+
+/* Sweeps per pass over memory.  Two sweeps in one pass keep the intermediate
+ * iterate on chip, so they move the bytes of one sweep; the iterate is the
+ * same in every mode, rounded identically (not from the paper, which times
+ * single sweeps: a schedule of the same computation).
+ *   CS_PASS_AUTO (default): two per pass for 3D Jacobi sweeps and, where the
+ *     grid is large enough for it to be faster, for fused 3D red-black sweeps;
+ *     one otherwise.
+ *   CS_PASS_ONE: one sweep per pass.
+ *   CS_PASS_TWO: two per pass wherever a kernel for it exists (3D Jacobi, fused
+ *     3D red-black), whatever the grid size.
+ * An odd remainder of sweeps runs as one single pass.  The 8-colour sweeps are
+ * always one per pass. */
+typedef enum { CS_PASS_AUTO = 0, CS_PASS_ONE = 1, CS_PASS_TWO = 2 } cs_pass_mode;
+
+/* Set the grid's pass mode (a cs_pass_mode).  Errors: CS_EINVAL (bad grid or
+ * mode). */
+cs_status cs_grid_set_pass_mode(cs_grid g, int32_t mode);
+
+/* *out = sweeps per pass (1 or 2) that cs_gs_sweeps with a work array
+ * (jacobi == 0) or cs_jacobi_sweeps (jacobi == 1) uses on this grid under its
+ * pass mode.  Errors: CS_EINVAL (bad grid, out NULL, jacobi not 0/1). */
+cs_status cs_sweeps_per_pass(cs_grid g, int32_t jacobi, int32_t* out);
 
 /* Description of the last failure on the calling thread ("" if none). */
 const char* cs_last_error(void);

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libcolsten.so")
 CS_OK, CS_EINVAL, CS_ENOMEM, CS_EHIP, CS_EUNSUPPORTED = 0, 1, 2, 3, 4
 CS_F64, CS_F32 = 0, 1
 CS_FD, CS_Q1 = 0, 1
+CS_PASS_AUTO, CS_PASS_ONE, CS_PASS_TWO = 0, 1, 2
 
 _STATUS = {0: "CS_OK", 1: "CS_EINVAL", 2: "CS_ENOMEM", 3: "CS_EHIP", 4: "CS_EUNSUPPORTED"}
 
@@ -52,6 +53,8 @@ _SIGS = {
     "cs_grid_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "cs_num_colours": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "cs_gs_fused": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "cs_grid_set_pass_mode": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "cs_sweeps_per_pass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "cs_colour_pass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "cs_gs_sweeps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "cs_jacobi_sweeps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32,
@@ -145,6 +148,17 @@ def cs_gs_fused(handle):
     out = ctypes.c_int32()
     _check(lib().cs_gs_fused(ctypes.c_void_p(handle), ctypes.byref(out)))
     return bool(out.value)
+
+
+def cs_grid_set_pass_mode(handle, mode):
+    _check(lib().cs_grid_set_pass_mode(ctypes.c_void_p(handle), ctypes.c_int32(mode)))
+
+
+def cs_sweeps_per_pass(handle, jacobi):
+    out = ctypes.c_int32()
+    _check(lib().cs_sweeps_per_pass(ctypes.c_void_p(handle), ctypes.c_int32(1 if jacobi else 0),
+                                    ctypes.byref(out)))
+    return out.value
 
 
 def cs_colour_pass(handle, colour, stream=None):
@@ -313,6 +327,13 @@ class Grid:
     @property
     def fused(self):
         return cs_gs_fused(self.handle)
+
+    def set_pass_mode(self, mode):
+        """CS_PASS_AUTO, CS_PASS_ONE or CS_PASS_TWO: sweeps per pass over memory."""
+        cs_grid_set_pass_mode(self.handle, mode)
+
+    def sweeps_per_pass(self, jacobi=False):
+        return cs_sweeps_per_pass(self.handle, jacobi)
 
     def colour_pass(self, colour, stream=None):
         cs_colour_pass(self.handle, colour, stream)

@@ -198,6 +198,44 @@ cs_status cs_num_colours(cs_grid g, int32_t* out)
     return CS_OK;
 }
 
+// Whether cs_gs_sweeps (with a work array) and cs_jacobi_sweeps run two
+// sweeps per pass on this grid, under its pass mode.
+static bool gs_pairs(cs_grid g)
+{
+    const int dt = g->d.dtype, dim = g->d.dim, sten = g->d.stencil;
+    if (g->pass_mode == CS_PASS_ONE) return false;
+    if (g->pass_mode == CS_PASS_TWO) return fused_two_available(dt, dim, sten, g->geo);
+    return fused_two_preferred(dt, dim, sten, g->geo);
+}
+
+static bool jacobi_pairs(cs_grid g)
+{
+    return g->pass_mode != CS_PASS_ONE && g->d.dim == 3 &&
+           jacobi3_two_supported(g->d.stencil, g->geo);
+}
+
+cs_status cs_grid_set_pass_mode(cs_grid g, int32_t mode)
+{
+    cs_status st = check_grid(g);
+    if (st != CS_OK) return st;
+    if (mode != CS_PASS_AUTO && mode != CS_PASS_ONE && mode != CS_PASS_TWO) {
+        set_error("pass mode must be CS_PASS_AUTO, CS_PASS_ONE or CS_PASS_TWO");
+        return CS_EINVAL;
+    }
+    g->pass_mode = mode;
+    return CS_OK;
+}
+
+cs_status cs_sweeps_per_pass(cs_grid g, int32_t jacobi, int32_t* out)
+{
+    cs_status st = check_grid(g);
+    if (st != CS_OK) return st;
+    if (!out) { set_error("out is NULL"); return CS_EINVAL; }
+    if (jacobi != 0 && jacobi != 1) { set_error("jacobi must be 0 or 1"); return CS_EINVAL; }
+    *out = (jacobi ? jacobi_pairs(g) : gs_pairs(g)) ? 2 : 1;
+    return CS_OK;
+}
+
 cs_status cs_gs_fused(cs_grid g, int32_t* out)
 {
     if (!g || !out) { set_error("NULL argument"); return CS_EINVAL; }
@@ -231,7 +269,7 @@ cs_status cs_gs_sweeps(cs_grid g, int32_t nsweeps, void* u_tmp, void* stream)
         if ((st = launch_halo_copy(dt, dim, g->geo, g->u, u_tmp, s)) != CS_OK) return st;
         const void* src = g->u;
         void* dst = u_tmp;
-        const bool pairs = fused_two_supported(dt, dim, sten, g->geo);
+        const bool pairs = gs_pairs(g);
         for (int32_t it = 0; it < nsweeps;) {
             if (pairs && nsweeps - it >= 2) {
                 st = launch_fused_two(dt, dim, sten, g->geo, src, dst, g->b, h2, s);
@@ -339,7 +377,7 @@ cs_status cs_jacobi_sweeps(cs_grid g, double omega, int32_t nsweeps, void* u_tmp
     if ((st = launch_halo_copy(dt, dim, g->geo, g->u, u_tmp, s)) != CS_OK) return st;
     const void* src = g->u;
     void* dst = u_tmp;
-    const bool pairs = dim == 3 && jacobi3_two_supported(sten, g->geo);
+    const bool pairs = jacobi_pairs(g);
     for (int32_t it = 0; it < nsweeps;) {
         if (pairs && nsweeps - it >= 2) {
             st = launch_jacobi3_two(dt, sten, g->geo, src, dst, g->b, h2_of(g), omega, s);

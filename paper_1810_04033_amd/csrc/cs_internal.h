@@ -66,8 +66,11 @@ cs_status launch_fused_sweep(int dtype, int dim, int stencil, const Geo& g, cons
                              void* dst, const void* b, double h2, hipStream_t s);
 bool fused_supported(int dtype, int dim, int stencil, const Geo& g);
 // Two red-black sweeps (7-point, 3D) in one pass over memory, src -> dst: the
-// iterate of two fused sweeps bit for bit.
-bool fused_two_supported(int dtype, int dim, int stencil, const Geo& g);
+// iterate of two fused sweeps bit for bit.  Available on every 7-point grid
+// the fused sweep supports; preferred where the grid is also large enough for
+// the double sweep to be the faster choice.
+bool fused_two_available(int dtype, int dim, int stencil, const Geo& g);
+bool fused_two_preferred(int dtype, int dim, int stencil, const Geo& g);
 cs_status launch_fused_two(int dtype, int dim, int stencil, const Geo& g, const void* src,
                            void* dst, const void* b, double h2, hipStream_t s);
 // Second (fixed-order) stage of the residual reduction over `count` partials.
@@ -106,4 +109,5 @@ struct cs_grid_s {
     size_t elem;          // bytes per element
     int64_t span;         // elements from the first to one past the last halo'd element
     cs::Partial* partials;  // kMaxResidualBlocks entries of device scratch
+    int pass_mode;        // cs_pass_mode: sweeps per pass over memory
 };

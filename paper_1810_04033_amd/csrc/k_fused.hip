@@ -112,12 +112,29 @@ cs_status fused_fd3_t(const Geo& g, const void* src, void* dst, const void* b, d
 // Two sweeps per launch: the chunks carry 3 extra planes of work on each side,
 // so they are kept at least 16 planes deep.
 template <typename T, int TX, int TY, int NT, int D, int NB>
+int64_t fused_two_resident()
+{
+    static const int64_t resident = resident_blocks(k_fused_fd3_two<T, TX, TY, NT, D, NB>, NT);
+    return resident;
+}
+
+// Whether the double sweep's grid fills at least 3/4 of the device: with one
+// workgroup per CU and chunks of 16 or more planes it leaves CUs idle on small
+// grids, where two single sweeps are faster (measured: FP64 from 160^3, FP32
+// from 192^3 the double sweep wins).
+template <typename T, int TX, int TY, int NT, int D, int NB>
+bool fused_two_fills(const Geo& g)
+{
+    const int64_t tiles = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
+    return 4 * tiles * (g.nz / 16) >= 3 * fused_two_resident<T, TX, TY, NT, D, NB>();
+}
+
+template <typename T, int TX, int TY, int NT, int D, int NB>
 cs_status fused_fd3_two_t(const Geo& g, const void* src, void* dst, const void* b, double h2,
                           hipStream_t s)
 {
     auto kern = k_fused_fd3_two<T, TX, TY, NT, D, NB>;
-    static const int64_t resident = resident_blocks(kern, NT);
-    const FusedWork wk = plan_work(resident, g, TX, TY, 16);
+    const FusedWork wk = plan_work(fused_two_resident<T, TX, TY, NT, D, NB>(), g, TX, TY, 16);
     hipLaunchKernelGGL(kern, dim3((unsigned)wk.nblocks), dim3(NT), 0, s, (const T*)src, (T*)dst,
                        (const T*)b, g, (T)h2, wk);
     return check_launch("fused 7-point double sweep");
@@ -166,11 +183,6 @@ bool fused_supported(int dtype, int dim, int stencil, const Geo& g)
     return dim == 3 && small;
 }
 
-bool fused_two_supported(int dtype, int dim, int stencil, const Geo& g)
-{
-    return stencil == FD && fused_supported(dtype, dim, stencil, g);
-}
-
 // Tile, threads, prefetch depth and snapshot sets of the double sweep per
 // precision (measured at 256^3): FP64 64 x 16 with two snapshot sets, FP32
 // 64 x 32 with one.
@@ -186,10 +198,23 @@ bool fused_two_supported(int dtype, int dim, int stencil, const Geo& g)
 #define CS_F2_D32 2
 #define CS_F2_NB32 1
 #endif
+bool fused_two_available(int dtype, int dim, int stencil, const Geo& g)
+{
+    return stencil == FD && fused_supported(dtype, dim, stencil, g);
+}
+
+bool fused_two_preferred(int dtype, int dim, int stencil, const Geo& g)
+{
+    if (!fused_two_available(dtype, dim, stencil, g)) return false;
+    return dtype == 0
+               ? fused_two_fills<double, CS_F2_TX, CS_F2_TY, CS_F2_NT, CS_F2_D, CS_F2_NB>(g)
+               : fused_two_fills<float, CS_F2_TX32, CS_F2_TY32, CS_F2_NT32, CS_F2_D32, CS_F2_NB32>(g);
+}
+
 cs_status launch_fused_two(int dtype, int dim, int stencil, const Geo& g, const void* src,
                            void* dst, const void* b, double h2, hipStream_t s)
 {
-    if (!fused_two_supported(dtype, dim, stencil, g)) {
+    if (!fused_two_available(dtype, dim, stencil, g)) {
         set_error("fused double sweep not available for this grid");
         return CS_EUNSUPPORTED;
     }

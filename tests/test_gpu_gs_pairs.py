@@ -22,17 +22,49 @@ SHAPES = [(1, 1, 1), (2, 3, 4), (5, 7, 3), (33, 9, 20), (65, 34, 7), (130, 20, 1
 
 @pytest.mark.parametrize("n", SHAPES, ids=lambda p: "x".join(map(str, p)))
 @pytest.mark.parametrize("nsw", [1, 2, 4, 5])
+@pytest.mark.parametrize("mode", [C.CS_PASS_TWO, C.CS_PASS_ONE], ids=["two", "one"])
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
 @pytest.mark.parametrize("layout", ["aligned", "compact", "odd"])
 @pytest.mark.parametrize("parity", [0, 1])
-def test_paired_fused_gs_bitwise(n, nsw, dt, layout, parity):
+def test_paired_fused_gs_bitwise(n, nsw, mode, dt, layout, parity):
     u, b = G.case(3, n, seed=1600 + nsw + 10 * parity)
     h = 1.0 / (max(n) + 1)
     uo, bo = u.astype(NP[dt]), b.astype(NP[dt])
     O.gs_sweeps(uo, bo, nsw, dim=3, stencil=O.FD, h=h, parity=parity)
     ug, bg = G.upload(u, dt, layout=layout), G.upload(b, dt, layout=layout)
     g = C.Grid(ug, bg, dim=3, stencil=C.CS_FD, h=h, parity=parity)
+    g.set_pass_mode(mode)
     g.gs(nsw, tmp=C.grid_like(ug))
     torch.cuda.synchronize()
     got = ug.detach().cpu().numpy()
     assert np.array_equal(got, uo), "max diff %g" % np.max(np.abs(got.astype(np.float64) - uo))
+
+
+def test_pass_mode_choice_and_errors():
+    """The automatic choice pairs the red-black sweeps on a grid that fills the
+    device and not on a small one; Jacobi sweeps are paired in 3D; the 8-colour
+    and 2D sweeps run one per pass; bad modes are rejected."""
+    def grid(n, st=C.CS_FD, dim=3):
+        u = C.empty_grid(n)
+        return C.Grid(u, C.grid_like(u), dim=dim, stencil=st, h=0.1)
+
+    big, small = grid((256, 256, 256)), grid((64, 64, 64))
+    assert big.sweeps_per_pass() == 2 and small.sweeps_per_pass() == 1
+    assert big.sweeps_per_pass(jacobi=True) == 2 and small.sweeps_per_pass(jacobi=True) == 2
+    small.set_pass_mode(C.CS_PASS_TWO)
+    assert small.sweeps_per_pass() == 2
+    big.set_pass_mode(C.CS_PASS_ONE)
+    assert big.sweeps_per_pass() == 1 and big.sweeps_per_pass(jacobi=True) == 1
+    q1 = grid((256, 256, 256), st=C.CS_Q1)
+    q1.set_pass_mode(C.CS_PASS_TWO)
+    assert q1.sweeps_per_pass() == 1 and q1.sweeps_per_pass(jacobi=True) == 2
+    two_d = grid((256, 256), dim=2)
+    two_d.set_pass_mode(C.CS_PASS_TWO)
+    assert two_d.sweeps_per_pass() == 1 and two_d.sweeps_per_pass(jacobi=True) == 1
+    for bad in (-1, 3):
+        with pytest.raises(C.ColstenError) as e:
+            big.set_pass_mode(bad)
+        assert e.value.status == C.CS_EINVAL
+    with pytest.raises(C.ColstenError) as e:
+        C.cs_sweeps_per_pass(None, False)
+    assert e.value.status == C.CS_EINVAL

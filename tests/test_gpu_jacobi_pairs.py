@@ -20,10 +20,11 @@ SHAPES = [(1, 1, 1), (2, 3, 4), (5, 7, 3), (33, 9, 20), (65, 34, 7), (130, 20, 1
 
 @pytest.mark.parametrize("n", SHAPES, ids=lambda p: "x".join(map(str, p)))
 @pytest.mark.parametrize("nsw", [1, 2, 4, 5])
+@pytest.mark.parametrize("mode", [C.CS_PASS_TWO, C.CS_PASS_ONE], ids=["two", "one"])
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
 @pytest.mark.parametrize("layout", ["aligned", "compact", "odd"])
 @pytest.mark.parametrize("st", [C.CS_FD, C.CS_Q1], ids=["fd", "q1"])
-def test_paired_jacobi_bitwise(n, nsw, dt, layout, st):
+def test_paired_jacobi_bitwise(n, nsw, mode, dt, layout, st):
     u, b = G.case(3, n, seed=1500 + nsw)
     h = 1.0 / (max(n) + 1)
     omega = 0.8
@@ -31,6 +32,7 @@ def test_paired_jacobi_bitwise(n, nsw, dt, layout, st):
     O.jacobi_sweeps(uo, bo, nsw, omega, dim=3, stencil=st, h=h)
     ug, bg = G.upload(u, dt, layout=layout), G.upload(b, dt, layout=layout)
     g = C.Grid(ug, bg, dim=3, stencil=st, h=h)
+    g.set_pass_mode(mode)
     g.jacobi(omega, nsw, C.grid_like(ug))
     torch.cuda.synchronize()
     got = ug.detach().cpu().numpy()
