@@ -198,8 +198,16 @@ cs_status cs_batch_destroy(cs_batch bt);
 
 /* nsweeps Gauss-Seidel sweeps of every patch (colours in canonical order),
  * each patch reading its u / tmp alternately; the result ends in u (one copy
- * back for odd counts).  The halo of every tmp is overwritten with u's. */
+ * back where a patch's last pass wrote tmp).  Patches of the large 7-point
+ * tile class run two red-black sweeps per pass (an odd last sweep alone); the
+ * iterate is the same, rounded identically.  The halo of every tmp is
+ * overwritten with u's. */
 cs_status cs_batch_gs_sweeps(cs_batch bt, int32_t nsweeps, void* stream);
+
+/* *out = sweeps per pass over memory (1 or 2) of patch index (the caller's
+ * order) in cs_batch_gs_sweeps.  Errors: CS_EINVAL (NULL, index out of
+ * range). */
+cs_status cs_batch_sweeps_per_pass(cs_batch bt, int32_t index, int32_t* out);
 
 /* Per-patch residual norms: norms (device, count x 3 doubles) receives, for
  * patch i at 3*i, ||r||_2, max |r| and ||b||_2 of r = b - A u (FP64

@@ -75,6 +75,7 @@ _SIGS = {
     "cs_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "cs_batch_gs_sweeps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "cs_batch_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cs_batch_sweeps_per_pass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "cs_batch_tile_policy": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "cs_graph_gs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_void_p)]),
@@ -229,6 +230,12 @@ def cs_batch_gs_sweeps(handle, nsweeps, stream=None):
 
 def cs_batch_residual(handle, norms_ptr, stream=None):
     _check(lib().cs_batch_residual(ctypes.c_void_p(handle), ctypes.c_void_p(norms_ptr), _stream(stream)))
+
+
+def cs_batch_sweeps_per_pass(handle, index):
+    out = ctypes.c_int32()
+    _check(lib().cs_batch_sweeps_per_pass(ctypes.c_void_p(handle), ctypes.c_int32(index), ctypes.byref(out)))
+    return out.value
 
 
 def cs_batch_tile_policy(stencil, dtype, small_max, mid_max):
@@ -428,6 +435,9 @@ class Batch:
 
     def gs(self, nsweeps, stream=None):
         cs_batch_gs_sweeps(self.handle, nsweeps, stream)
+
+    def sweeps_per_pass(self, index):
+        return cs_batch_sweeps_per_pass(self.handle, index)
 
     def residual(self, stream=None):
         cs_batch_residual(self.handle, self.norms.data_ptr(), stream)

@@ -45,6 +45,7 @@ struct cs_batch_s {
     int count = 0;
     int device = 0;
     std::vector<Group> groups;
+    std::vector<int> per_pass;  // sweeps per launch of each patch (caller's order)
     Partial* partials = nullptr;
 };
 
@@ -141,17 +142,21 @@ cs_status cs_batch_create(const cs_grid_desc* descs, void* const* u, const void*
             k = (int)bt->groups.size() - 1;
         }
         bt->groups[k].host.push_back(p);
+        bt->per_pass.push_back(batch_variant_pairs(d.stencil, variant) ? 2 : 1);
     }
     // z chunks: enough work items to fill the GPU (about 2048) when the batch
-    // holds few patches, never chunks thinner than 8 planes.  The split does
-    // not change any value: every point is computed the same way in any tile.
+    // holds few patches, never chunks thinner than 8 planes (16 for the tile
+    // class that also runs double sweeps).  The split does not change any
+    // value: every point is computed the same way in any tile.
     int64_t total_tiles = 0;
     for (auto& gr : bt->groups)
         for (auto& p : gr.host) total_tiles += (int64_t)p.tiles_x * p.tiles_y;
     const int64_t want = (2048 + total_tiles - 1) / total_tiles;
-    for (auto& gr : bt->groups)
+    for (auto& gr : bt->groups) {
+        const int depth = batch_variant_min_depth(gr.stencil, gr.variant);
         for (auto& p : gr.host)
-            p.chunks = (int)std::max<int64_t>(1, std::min<int64_t>(want, p.g.nz / 8));
+            p.chunks = (int)std::max<int64_t>(1, std::min<int64_t>(want, p.g.nz / depth));
+    }
     int64_t partial_total = 0;
     for (auto& gr : bt->groups) {
         std::stable_sort(gr.host.begin(), gr.host.end(), [](const BatchPatch& a, const BatchPatch& c) {
@@ -195,15 +200,53 @@ cs_status cs_batch_gs_sweeps(cs_batch bt, int32_t nsweeps, void* stream)
     cs_status st;
     for (auto& gr : bt->groups)
         if ((st = launch_batch_halo(gr.dtype, gr.dev, (int)gr.host.size(), s)) != CS_OK) return st;
-    for (int32_t it = 0; it < nsweeps; ++it)
-        for (auto& gr : bt->groups)
-            if ((st = launch_batch_sweep(gr.dtype, gr.stencil, gr.variant, gr.dev,
-                                         (int)gr.host.size(), gr.items, it & 1, s)) != CS_OK)
-                return st;
-    if (nsweeps & 1)
-        for (auto& gr : bt->groups)
-            if ((st = launch_batch_copyback(gr.dtype, gr.dev, (int)gr.host.size(), gr.res_items, s)) != CS_OK)
-                return st;
+    // Each launch reads u (phase 0) or tmp (phase 1) and writes the other; a
+    // group whose sweeps run two per launch flips less often, so the copy back
+    // into u is decided per group.
+    std::vector<int> phase(bt->groups.size(), 0);
+    for (int32_t it = 0; it < nsweeps;) {
+        const bool pair = nsweeps - it >= 2;
+        for (size_t gi = 0; gi < bt->groups.size(); ++gi) {
+            Group& gr = bt->groups[gi];
+            const bool two = batch_variant_pairs(gr.stencil, gr.variant);
+            if (two && !pair) continue;
+            const int runs = (two || !pair) ? 1 : 2;
+            for (int r = 0; r < runs; ++r) {
+                if ((st = launch_batch_sweep(gr.dtype, gr.stencil, gr.variant, gr.dev,
+                                             (int)gr.host.size(), gr.items, phase[gi], two, s)) !=
+                    CS_OK)
+                    return st;
+                phase[gi] ^= 1;
+            }
+        }
+        if (!pair) {
+            // the last, odd sweep: the paired groups take it as a single sweep
+            for (size_t gi = 0; gi < bt->groups.size(); ++gi) {
+                Group& gr = bt->groups[gi];
+                if (!batch_variant_pairs(gr.stencil, gr.variant)) continue;
+                if ((st = launch_batch_sweep(gr.dtype, gr.stencil, gr.variant, gr.dev,
+                                             (int)gr.host.size(), gr.items, phase[gi], false, s)) !=
+                    CS_OK)
+                    return st;
+                phase[gi] ^= 1;
+            }
+        }
+        it += pair ? 2 : 1;
+    }
+    for (size_t gi = 0; gi < bt->groups.size(); ++gi) {
+        Group& gr = bt->groups[gi];
+        if (phase[gi] &&
+            (st = launch_batch_copyback(gr.dtype, gr.dev, (int)gr.host.size(), gr.res_items, s)) != CS_OK)
+            return st;
+    }
+    return CS_OK;
+}
+
+cs_status cs_batch_sweeps_per_pass(cs_batch bt, int32_t index, int32_t* out)
+{
+    if (!bt || !out) { set_error("NULL argument"); return CS_EINVAL; }
+    if (index < 0 || index >= bt->count) { set_error("patch index out of range"); return CS_EINVAL; }
+    *out = bt->per_pass[(size_t)index];
     return CS_OK;
 }
 

@@ -50,6 +50,20 @@ k_batch_fd3(const BatchPatch* __restrict__ tab, int count, int phase)
     fd3_tile<T, TX, TY, NT, D>(src, dst, (const T*)P.b, P.g, (T)P.h2, tb);
 }
 
+// Two red-black sweeps per launch (the large 7-point tile class).
+template <typename T, int TX, int TY, int NT, int D, int NB>
+__global__ void __launch_bounds__(NT)
+k_batch_fd3_two(const BatchPatch* __restrict__ tab, int count, int phase)
+{
+    const int64_t w = blockIdx.x;
+    const int p = find_patch(tab, count, w, false);
+    const BatchPatch P = tab[p];
+    const TileBox tb = tile_box<TX, TY>(P.g, P.tiles_x, P.tiles_y, P.chunks, w - P.item_begin);
+    const T* src = (const T*)(phase ? P.tmp : P.u);
+    T* dst = (T*)(phase ? P.u : P.tmp);
+    fd3_tile_two<T, TX, TY, NT, D, NB>(src, dst, (const T*)P.b, P.g, (T)P.h2, tb);
+}
+
 template <typename T, int TX, int TY, int NT, int WPE>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_batch_q1_3(const BatchPatch* __restrict__ tab, int count, int phase)
@@ -211,11 +225,34 @@ void batch_variant_tile(int stencil, int variant, int* tx, int* ty)
     *ty = stencil == FD ? fd[v][1] : q1[v][1];
 }
 
+bool batch_variant_pairs(int stencil, int variant)
+{
+    return stencil == FD && variant >= 2;
+}
+
+int batch_variant_min_depth(int stencil, int variant)
+{
+    return batch_variant_pairs(stencil, variant) ? 16 : 8;
+}
+
 cs_status launch_batch_sweep(int dtype, int stencil, int variant, const BatchPatch* tab, int count,
-                             int64_t items, int phase, hipStream_t s)
+                             int64_t items, int phase, bool two, hipStream_t s)
 {
     if (items <= 0) return CS_OK;
     const dim3 grid((unsigned)items);
+    if (two) {
+        if (!batch_variant_pairs(stencil, variant)) {
+            set_error("no double sweep for this tile variant");
+            return CS_EUNSUPPORTED;
+        }
+        if (dtype == 0)
+            hipLaunchKernelGGL((k_batch_fd3_two<double, 64, 16, 1024, 2, 2>), grid, dim3(1024), 0,
+                               s, tab, count, phase);
+        else
+            hipLaunchKernelGGL((k_batch_fd3_two<float, 64, 16, 1024, 2, 2>), grid, dim3(1024), 0,
+                               s, tab, count, phase);
+        return check_launch("batched double sweep");
+    }
 #define CS_BFD(T, TX, TY, NT, D) \
     hipLaunchKernelGGL((k_batch_fd3<T, TX, TY, NT, D>), grid, dim3(NT), 0, s, tab, count, phase)
 #define CS_BQ1(T, TX, TY, NT, WPE) \

@@ -37,7 +37,7 @@ SHAPES = [(1, 1, 1), (2, 3, 4), (5, 7, 3), (8, 8, 8), (16, 16, 16), (17, 9, 12),
           (33, 20, 18), (48, 48, 48), (64, 64, 64), (70, 13, 65), (40, 66, 9)]
 
 
-@pytest.mark.parametrize("nsw", [3, 4])
+@pytest.mark.parametrize("nsw", [1, 2, 3, 4, 5])
 def test_mixed_batch_matches_oracle(nsw):
     ps = []
     for i, n in enumerate(SHAPES):
@@ -131,3 +131,18 @@ def test_patch_workload_4096_sampled():
         assert G.relmax(G.download(ps[i][0]), uo) <= 1e-13
         np.testing.assert_allclose(n1[i], O.residual(uo, bh, dim=3, stencil=O.FD, h=1.0 / (e + 1)),
                                    rtol=1e-11)
+
+
+def test_sweeps_per_pass_by_tile_class():
+    """Patches of the large 7-point tile class run two sweeps per pass, the
+    others (small and middle classes, 27-point) one; bad queries are rejected."""
+    ps = [_patch(n, st, torch.float64, 0, seed=1700 + i)
+          for i, (n, st) in enumerate([((8, 8, 8), C.CS_FD), ((64, 64, 64), C.CS_FD),
+                                       ((64, 64, 64), C.CS_Q1), ((30, 30, 30), C.CS_FD)])]
+    bt = _batch(ps)
+    assert [bt.sweeps_per_pass(i) for i in range(4)] == [1, 2, 1, 1]
+    for bad in (-1, 4):
+        with pytest.raises(C.ColstenError) as e:
+            bt.sweeps_per_pass(bad)
+        assert e.value.status == C.CS_EINVAL
+    bt.close()
