@@ -185,7 +185,8 @@ def run_poisson3d(a):
         moved += bpu * SWEEPS * pts
         rows[r] = {"ms_per_sweep": round(per_sweep_ms, 5), "GLUP/s": round(glups, 2),
                    "sweeps_per_pass": per_pass[r], "bytes_per_update": bpu,
-                   "hbm_frac": round(glups * bpu / HBM_PEAK_GBS, 4)}
+                   "hbm_frac": round(glups * bpu / HBM_PEAK_GBS, 4),
+                   "effective_frac_per_sweep": round(glups * BYTES_PER_UPDATE / HBM_PEAK_GBS, 4)}
     rows["residuals"] = {"ms": round(row_ms["residuals"], 5)}
 
     # dominant kernel: the sweep row with the largest time
@@ -244,7 +245,12 @@ def run_poisson3d(a):
                    "grid": [N, N, N], "sweeps_per_row": SWEEPS,
                    "gs_mode": {k: ("fused single pass" if v else "one launch per colour")
                                for k, v in fused_rows.items()}},
+        # hbm_frac: bytes the passes move over the step time (the real share of
+        # HBM bandwidth); effective_frac_per_sweep: 24 bytes per update of a
+        # single sweep over the time per sweep, which exceeds what HBM could
+        # move where sweeps run two per pass
         "hbm_frac": round(moved / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "effective_frac_per_sweep": round(value * BYTES_PER_UPDATE / HBM_PEAK_GBS, 4),
         "rows": rows,
         "roofline": roofline,
         "final_rel_residual": [float(x) for x in (norms[:, 0] / norms[:, 2]).cpu().numpy()],
