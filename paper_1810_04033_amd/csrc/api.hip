@@ -198,14 +198,17 @@ cs_status cs_num_colours(cs_grid g, int32_t* out)
     return CS_OK;
 }
 
-// Whether cs_gs_sweeps (with a work array) and cs_jacobi_sweeps run two
-// sweeps per pass on this grid, under its pass mode.
-static bool gs_pairs(cs_grid g)
+// Sweeps per pass of cs_gs_sweeps (with a work array) and whether
+// cs_jacobi_sweeps pairs its sweeps, on this grid under its pass mode.  2D
+// grids take up to fused2d_max_sweeps sweeps per launch (an LDS-resident
+// tile), 3D red-black grids two.
+static int gs_per_pass(cs_grid g)
 {
     const int dt = g->d.dtype, dim = g->d.dim, sten = g->d.stencil;
-    if (g->pass_mode == CS_PASS_ONE) return false;
-    if (g->pass_mode == CS_PASS_TWO) return fused_two_available(dt, dim, sten, g->geo);
-    return fused_two_preferred(dt, dim, sten, g->geo);
+    if (g->pass_mode == CS_PASS_ONE || !fused_supported(dt, dim, sten, g->geo)) return 1;
+    if (dim == 2) return fused2d_max_sweeps(sten);
+    if (g->pass_mode == CS_PASS_TWO) return fused_two_available(dt, dim, sten, g->geo) ? 2 : 1;
+    return fused_two_preferred(dt, dim, sten, g->geo) ? 2 : 1;
 }
 
 static bool jacobi_pairs(cs_grid g)
@@ -232,7 +235,7 @@ cs_status cs_sweeps_per_pass(cs_grid g, int32_t jacobi, int32_t* out)
     if (st != CS_OK) return st;
     if (!out) { set_error("out is NULL"); return CS_EINVAL; }
     if (jacobi != 0 && jacobi != 1) { set_error("jacobi must be 0 or 1"); return CS_EINVAL; }
-    *out = (jacobi ? jacobi_pairs(g) : gs_pairs(g)) ? 2 : 1;
+    *out = jacobi ? (jacobi_pairs(g) ? 2 : 1) : gs_per_pass(g);
     return CS_OK;
 }
 
@@ -269,9 +272,14 @@ cs_status cs_gs_sweeps(cs_grid g, int32_t nsweeps, void* u_tmp, void* stream)
         if ((st = launch_halo_copy(dt, dim, g->geo, g->u, u_tmp, s)) != CS_OK) return st;
         const void* src = g->u;
         void* dst = u_tmp;
-        const bool pairs = gs_pairs(g);
+        const int per = gs_per_pass(g);
         for (int32_t it = 0; it < nsweeps;) {
-            if (pairs && nsweeps - it >= 2) {
+            if (dim == 2) {
+                int sw = per;
+                while (sw > nsweeps - it) sw >>= 1;  // 8, 4, 2, 1
+                st = launch_fused2d(dt, sten, sw, g->geo, src, dst, g->b, h2, s);
+                it += sw;
+            } else if (per == 2 && nsweeps - it >= 2) {
                 st = launch_fused_two(dt, dim, sten, g->geo, src, dst, g->b, h2, s);
                 it += 2;
             } else {

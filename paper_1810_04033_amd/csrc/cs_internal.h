@@ -70,6 +70,11 @@ bool fused_supported(int dtype, int dim, int stencil, const Geo& g);
 // the fused sweep supports; preferred where the grid is also large enough for
 // the double sweep to be the faster choice.
 bool fused_two_available(int dtype, int dim, int stencil, const Geo& g);
+// Fused sweeps of 2D grids (k_fused2d.hip): sweeps (1 or 2, or 4 for the
+// 5-point stencil) whole sweeps per launch, src -> dst.
+int fused2d_max_sweeps(int stencil);
+cs_status launch_fused2d(int dtype, int stencil, int sweeps, const Geo& g, const void* src,
+                         void* dst, const void* b, double h2, hipStream_t s);
 bool fused_two_preferred(int dtype, int dim, int stencil, const Geo& g);
 cs_status launch_fused_two(int dtype, int dim, int stencil, const Geo& g, const void* src,
                            void* dst, const void* b, double h2, hipStream_t s);

@@ -178,7 +178,8 @@ bool fused_supported(int dtype, int dim, int stencil, const Geo& g)
 {
     (void)dtype;
     (void)stencil;
-    // column offsets y*sy + x are 32-bit inside the kernels
+    if (dim == 2) return true;  // k_fused2d.hip, 64-bit offsets
+    // column offsets y*sy + x are 32-bit inside the 3D kernels
     const bool small = (g.ny + 2) * g.sy < ((int64_t)1 << 31);
     return dim == 3 && small;
 }
@@ -200,7 +201,7 @@ bool fused_supported(int dtype, int dim, int stencil, const Geo& g)
 #endif
 bool fused_two_available(int dtype, int dim, int stencil, const Geo& g)
 {
-    return stencil == FD && fused_supported(dtype, dim, stencil, g);
+    return dim == 3 && stencil == FD && fused_supported(dtype, dim, stencil, g);
 }
 
 bool fused_two_preferred(int dtype, int dim, int stencil, const Geo& g)
@@ -228,7 +229,7 @@ cs_status launch_fused_two(int dtype, int dim, int stencil, const Geo& g, const 
 cs_status launch_fused_sweep(int dtype, int dim, int stencil, const Geo& g, const void* src,
                              void* dst, const void* b, double h2, hipStream_t s)
 {
-    if (!fused_supported(dtype, dim, stencil, g)) {
+    if (dim != 3 || !fused_supported(dtype, dim, stencil, g)) {
         set_error("fused sweep not available for this grid");
         return CS_EUNSUPPORTED;
     }

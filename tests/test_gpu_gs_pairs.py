@@ -43,7 +43,7 @@ def test_paired_fused_gs_bitwise(n, nsw, mode, dt, layout, parity):
 def test_pass_mode_choice_and_errors():
     """The automatic choice pairs the red-black sweeps on a grid that fills the
     device and not on a small one; Jacobi sweeps are paired in 3D; the 8-colour
-    and 2D sweeps run one per pass; bad modes are rejected."""
+    sweeps run one per pass, 2D Jacobi one per pass; bad modes are rejected."""
     def grid(n, st=C.CS_FD, dim=3):
         u = C.empty_grid(n)
         return C.Grid(u, C.grid_like(u), dim=dim, stencil=st, h=0.1)
@@ -59,7 +59,7 @@ def test_pass_mode_choice_and_errors():
     q1.set_pass_mode(C.CS_PASS_TWO)
     assert q1.sweeps_per_pass() == 1 and q1.sweeps_per_pass(jacobi=True) == 2
     two_d = grid((256, 256), dim=2)
-    two_d.set_pass_mode(C.CS_PASS_TWO)
+    two_d.set_pass_mode(C.CS_PASS_ONE)
     assert two_d.sweeps_per_pass() == 1 and two_d.sweeps_per_pass(jacobi=True) == 1
     for bad in (-1, 3):
         with pytest.raises(C.ColstenError) as e:
