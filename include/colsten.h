@@ -257,11 +257,12 @@ cs_status cs_gs_fused(cs_grid g, int32_t* out);
  * single sweeps: a schedule of the same computation).
  *   CS_PASS_AUTO (default): two per pass for 3D Jacobi sweeps and, where the
  *     grid is large enough for it to be faster, for fused 3D red-black sweeps;
- *     one otherwise.
+ *     one otherwise.  Fused 2D sweeps run up to 4 (red-black) or 2 (four
+ *     colours) per pass.
  *   CS_PASS_ONE: one sweep per pass.
- *   CS_PASS_TWO: two per pass wherever a kernel for it exists (3D Jacobi, fused
- *     3D red-black), whatever the grid size.
- * An odd remainder of sweeps runs as one single pass.  The 8-colour sweeps are
+ *   CS_PASS_TWO: as CS_PASS_AUTO, but two 3D sweeps per pass wherever a kernel
+ *     for it exists (3D Jacobi, fused 3D red-black), whatever the grid size.
+ * A remainder of sweeps runs in smaller passes.  The 8-colour sweeps are
  * always one per pass. */
 typedef enum { CS_PASS_AUTO = 0, CS_PASS_ONE = 1, CS_PASS_TWO = 2 } cs_pass_mode;
 
@@ -269,7 +270,7 @@ typedef enum { CS_PASS_AUTO = 0, CS_PASS_ONE = 1, CS_PASS_TWO = 2 } cs_pass_mode
  * mode). */
 cs_status cs_grid_set_pass_mode(cs_grid g, int32_t mode);
 
-/* *out = sweeps per pass (1 or 2) that cs_gs_sweeps with a work array
+/* *out = sweeps per pass (1, 2, or 4 for 2D red-black) that cs_gs_sweeps with a work array
  * (jacobi == 0) or cs_jacobi_sweeps (jacobi == 1) uses on this grid under its
  * pass mode.  Errors: CS_EINVAL (bad grid, out NULL, jacobi not 0/1). */
 cs_status cs_sweeps_per_pass(cs_grid g, int32_t jacobi, int32_t* out);
