@@ -100,11 +100,13 @@ cs_status cs_colour_pass(cs_grid g, int32_t colour, void* stream);
 
 /* nsweeps full Gauss-Seidel sweeps, each the colours 0..c-1 in order.
  * u_tmp: NULL, or a caller-owned device array with exactly u's layout.  With
- * u_tmp the library runs each sweep as one fused pass over memory that reads
- * u (or u_tmp) and writes the other array (the same iterate as the colour
- * passes, rounded identically); red-black sweeps on 3D grids run two per pass.
- * The halo of u_tmp is overwritten with u's halo, and the result ends in u.  Without u_tmp, each sweep is c in-place colour
- * passes.  nsweeps == 0 is a no-op.  Errors: CS_EINVAL (nsweeps < 0). */
+ * u_tmp the library runs the sweeps as fused passes over memory, each reading
+ * u (or u_tmp) and writing the other array (the same iterate as the colour
+ * passes, rounded identically): one or two sweeps per pass on 3D grids, up to
+ * four on 2D grids (see cs_grid_set_pass_mode).  The halo of u_tmp is
+ * overwritten with u's halo, and the result ends in u.  Without u_tmp, each
+ * sweep is c in-place colour passes.  nsweeps == 0 is a no-op.
+ * Errors: CS_EINVAL (nsweeps < 0). */
 cs_status cs_gs_sweeps(cs_grid g, int32_t nsweeps, void* u_tmp, void* stream);
 
 /* nsweeps weighted Jacobi sweeps (the separate-output-array form of Sec. 2):
