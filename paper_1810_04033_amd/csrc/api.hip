@@ -211,10 +211,11 @@ static int gs_per_pass(cs_grid g)
     return fused_two_preferred(dt, dim, sten, g->geo) ? 2 : 1;
 }
 
-static bool jacobi_pairs(cs_grid g)
+static int jacobi_per_pass(cs_grid g)
 {
-    return g->pass_mode != CS_PASS_ONE && g->d.dim == 3 &&
-           jacobi3_two_supported(g->d.stencil, g->geo);
+    if (g->pass_mode == CS_PASS_ONE) return 1;
+    if (g->d.dim == 2) return jacobi2d_max_sweeps(g->geo);
+    return jacobi3_two_supported(g->d.stencil, g->geo) ? 2 : 1;
 }
 
 cs_status cs_grid_set_pass_mode(cs_grid g, int32_t mode)
@@ -235,7 +236,7 @@ cs_status cs_sweeps_per_pass(cs_grid g, int32_t jacobi, int32_t* out)
     if (st != CS_OK) return st;
     if (!out) { set_error("out is NULL"); return CS_EINVAL; }
     if (jacobi != 0 && jacobi != 1) { set_error("jacobi must be 0 or 1"); return CS_EINVAL; }
-    *out = jacobi ? (jacobi_pairs(g) ? 2 : 1) : gs_per_pass(g);
+    *out = jacobi ? jacobi_per_pass(g) : gs_per_pass(g);
     return CS_OK;
 }
 
@@ -385,9 +386,14 @@ cs_status cs_jacobi_sweeps(cs_grid g, double omega, int32_t nsweeps, void* u_tmp
     if ((st = launch_halo_copy(dt, dim, g->geo, g->u, u_tmp, s)) != CS_OK) return st;
     const void* src = g->u;
     void* dst = u_tmp;
-    const bool pairs = jacobi_pairs(g);
+    const int per = jacobi_per_pass(g);
     for (int32_t it = 0; it < nsweeps;) {
-        if (pairs && nsweeps - it >= 2) {
+        if (dim == 2 && per > 1) {
+            int sw = per;
+            while (sw > nsweeps - it) sw >>= 1;  // 8, 4, 2, 1
+            st = launch_jacobi2d(dt, sten, sw, g->geo, src, dst, g->b, h2_of(g), omega, s);
+            it += sw;
+        } else if (per == 2 && nsweeps - it >= 2) {
             st = launch_jacobi3_two(dt, sten, g->geo, src, dst, g->b, h2_of(g), omega, s);
             it += 2;
         } else {

@@ -73,6 +73,11 @@ bool fused_two_available(int dtype, int dim, int stencil, const Geo& g);
 // Fused sweeps of 2D grids (k_fused2d.hip): sweeps (1 or 2, or 4 for the
 // 5-point stencil) whole sweeps per launch, src -> dst.
 int fused2d_max_sweeps(int stencil);
+// Weighted Jacobi sweeps of 2D grids, sweeps (1, 2, 4 or 8) per launch on an
+// LDS-resident tile, src -> dst; the most this grid is run with.
+int jacobi2d_max_sweeps(const Geo& g);
+cs_status launch_jacobi2d(int dtype, int stencil, int sweeps, const Geo& g, const void* src,
+                          void* dst, const void* b, double h2, double omega, hipStream_t s);
 cs_status launch_fused2d(int dtype, int stencil, int sweeps, const Geo& g, const void* src,
                          void* dst, const void* b, double h2, hipStream_t s);
 bool fused_two_preferred(int dtype, int dim, int stencil, const Geo& g);
