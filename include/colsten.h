@@ -112,9 +112,10 @@ cs_status cs_gs_sweeps(cs_grid g, int32_t nsweeps, void* u_tmp, void* stream);
 /* nsweeps weighted Jacobi sweeps (the separate-output-array form of Sec. 2):
  *   u'_q = u_q + omega * (h^2 b_q - sum_o S_o u_{q+o}) / S_0
  * reading only the previous iterate.  u_tmp (required) must have u's layout;
- * its halo is overwritten with u's halo.  The result ends in u.  On 3D grids
- * the sweeps run two per pass over memory (the intermediate iterate stays on
- * chip); the iterate is the same, rounded identically.
+ * its halo is overwritten with u's halo.  The result ends in u.  The sweeps
+ * run two per pass over memory on 3D grids and up to eight per launch on 2D
+ * grids (the intermediate iterates stay on chip; see cs_grid_set_pass_mode);
+ * the iterate is the same, rounded identically.
  * Errors: CS_EINVAL (u_tmp NULL, nsweeps < 0, omega not finite). */
 cs_status cs_jacobi_sweeps(cs_grid g, double omega, int32_t nsweeps, void* u_tmp, void* stream);
 
@@ -272,7 +273,7 @@ typedef enum { CS_PASS_AUTO = 0, CS_PASS_ONE = 1, CS_PASS_TWO = 2 } cs_pass_mode
  * mode). */
 cs_status cs_grid_set_pass_mode(cs_grid g, int32_t mode);
 
-/* *out = sweeps per pass (1, 2, or 4 for 2D red-black) that cs_gs_sweeps with a work array
+/* *out = sweeps per pass (1, 2, 4 or 8; more than 2 only on 2D grids) that cs_gs_sweeps with a work array
  * (jacobi == 0) or cs_jacobi_sweeps (jacobi == 1) uses on this grid under its
  * pass mode.  Errors: CS_EINVAL (bad grid, out NULL, jacobi not 0/1). */
 cs_status cs_sweeps_per_pass(cs_grid g, int32_t jacobi, int32_t* out);
