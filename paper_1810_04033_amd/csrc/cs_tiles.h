@@ -662,7 +662,7 @@ __device__ __forceinline__ void q1_load_b_pairs(const T* __restrict__ b, const G
     }
 }
 
-template <typename T, int W, int P>
+template <typename T, int W, int P, bool ROWWISE>
 __device__ __forceinline__ void q1_phase_pairs(bool active, const int* pc, const T* bv,
                                                const T* lm, T* lk, const T* lp, const int* pfl,
                                                T h2)
@@ -671,13 +671,36 @@ __device__ __forceinline__ void q1_phase_pairs(bool active, const int* pc, const
     // ox = -1 and ox = +1 are the aligned column pairs (x-1, x) and (x+1, x+2)
     // as loaded, the ox = 0 term is (x, x+1).  Each lane runs the ordered
     // fused multiply-add chain of gs_value (same offsets, same weights), so
-    // both points round exactly as the single-point form.
+    // both points round exactly as the single-point form.  ROWWISE adds each
+    // row's terms as soon as the row is loaded (the same order), which needs
+    // far fewer registers than loading all eight rows first.
     typedef T v2 __attribute__((ext_vector_type(2)));
     if (!active) return;
 #pragma unroll
     for (int i = 0; i < P; ++i) {
         const int c = pc[i];
         if (c < 0) continue;
+        v2 acc = {T(0), T(0)};
+        if (ROWWISE) {
+#pragma unroll
+            for (int oz = -1; oz <= 1; ++oz) {
+                const T* pl = oz < 0 ? lm : (oz > 0 ? lp : lk);
+#pragma unroll
+                for (int oy = -1; oy <= 1; ++oy) {
+                    if (oz == 0 && oy == 0) continue;  // faces zero, centre excluded
+                    const v2* row = reinterpret_cast<const v2*>(pl + (c - 1 + oy * W));
+                    const v2 a = row[0], bb = row[1];
+#pragma unroll
+                    for (int ox = -1; ox <= 1; ++ox) {
+                        const T w = weight<T, 3, Q1>(ox, oy, oz);
+                        if (w == T(0)) continue;
+                        const v2 val = ox < 0 ? a : (ox > 0 ? bb : (v2){a.y, bb.x});
+                        const v2 wv = {w, w};
+                        acc = __builtin_elementwise_fma(wv, val, acc);
+                    }
+                }
+            }
+        } else {
         v2 lo[3][3], hi[3][3];  // columns (x-1, x) and (x+1, x+2) of each row
 #pragma unroll
         for (int oz = -1; oz <= 1; ++oz) {
@@ -691,7 +714,6 @@ __device__ __forceinline__ void q1_phase_pairs(bool active, const int* pc, const
                 hi[oz + 1][oy + 1] = row[1];
             }
         }
-        v2 acc = {T(0), T(0)};
 #pragma unroll
         for (int oz = -1; oz <= 1; ++oz)
 #pragma unroll
@@ -706,6 +728,7 @@ __device__ __forceinline__ void q1_phase_pairs(bool active, const int* pc, const
                     const v2 wv = {w, w};
                     acc = __builtin_elementwise_fma(wv, val, acc);
                 }
+        }
         const v2 bq = {bv[2 * i], bv[2 * i + 1]};
         const v2 h2v = {h2, h2};
         const v2 x = h2v * bq - acc;
@@ -717,7 +740,7 @@ __device__ __forceinline__ void q1_phase_pairs(bool active, const int* pc, const
     }
 }
 
-template <typename T, int TX, int TY, int NT>
+template <typename T, int TX, int TY, int NT, bool ROWWISE = false>
 __device__ __forceinline__ void q1_3_tile_pairs(const T* __restrict__ src, T* __restrict__ dst,
                                                 const T* __restrict__ b, const Geo& g, T h2,
                                                 const TileBox& tb)
@@ -839,15 +862,15 @@ __device__ __forceinline__ void q1_3_tile_pairs(const T* __restrict__ src, T* __
         if (pend_e >= 0) write_plane(slot(pend_e), dst + pend_e * g.sz);
         if (pend_o >= 0) write_plane(slot(pend_o), dst + pend_o * g.sz);
         const bool ab = e >= 1 && e <= g.nz;
-        q1_phase_pairs<T, W, PA::P>(ab, ca, cba, lm1, l0, lp1, fa, h2);
+        q1_phase_pairs<T, W, PA::P, ROWWISE>(ab, ca, cba, lm1, l0, lp1, fa, h2);
         __syncthreads();
-        q1_phase_pairs<T, W, PB::P>(ab, cb, cbb, lm1, l0, lp1, fb, h2);
+        q1_phase_pairs<T, W, PB::P, ROWWISE>(ab, cb, cbb, lm1, l0, lp1, fb, h2);
         __syncthreads();
         const int64_t o = e - 1;
         const bool cdo = o >= z0 && o < z1 && o >= 1 && o <= g.nz;
-        q1_phase_pairs<T, W, PC::P>(cdo, cc, cbc, lm2, lm1, l0, fc, h2);
+        q1_phase_pairs<T, W, PC::P, ROWWISE>(cdo, cc, cbc, lm2, lm1, l0, fc, h2);
         __syncthreads();
-        q1_phase_pairs<T, W, PD::P>(cdo, cd, cbd, lm2, lm1, l0, fd, h2);
+        q1_phase_pairs<T, W, PD::P, ROWWISE>(cdo, cd, cbd, lm2, lm1, l0, fd, h2);
         __syncthreads();
         // planes e (rows A, B) and e-1 (rows C, D) are final; their slots are
         // not refilled before the top of double step e+4

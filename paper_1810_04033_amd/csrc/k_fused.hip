@@ -51,7 +51,7 @@ k_fused_fd3_two(const T* __restrict__ src, T* __restrict__ dst, const T* __restr
     fd3_tile_two<T, TX, TY, NT, D, NB>(src, dst, b, g, h2, tb);
 }
 
-template <typename T, int TX, int TY, int NT, int WPE, bool PAIRS>
+template <typename T, int TX, int TY, int NT, int WPE, bool PAIRS, bool ROWWISE = false>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_fused_q1_3(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict__ b, Geo g,
              T h2, FusedWork wk)
@@ -59,7 +59,7 @@ k_fused_q1_3(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict
     const TileBox tb = tile_box<TX, TY>(g, wk.tiles_x, wk.tiles_y, wk.chunks,
                                         xcd_ordered_block(wk.nblocks));
     if (PAIRS)
-        q1_3_tile_pairs<T, TX, TY, NT>(src, dst, b, g, h2, tb);
+        q1_3_tile_pairs<T, TX, TY, NT, ROWWISE>(src, dst, b, g, h2, tb);
     else
         q1_3_tile<T, TX, TY, NT>(src, dst, b, g, h2, tb);
 }
@@ -140,11 +140,11 @@ cs_status fused_fd3_two_t(const Geo& g, const void* src, void* dst, const void* 
     return check_launch("fused 7-point double sweep");
 }
 
-template <typename T, int TX, int TY, int NT, int WPE, bool PAIRS>
+template <typename T, int TX, int TY, int NT, int WPE, bool PAIRS, bool ROWWISE = false>
 cs_status fused_q1_3_t(const Geo& g, const void* src, void* dst, const void* b, double h2,
                        hipStream_t s)
 {
-    auto kern = k_fused_q1_3<T, TX, TY, NT, WPE, PAIRS>;
+    auto kern = k_fused_q1_3<T, TX, TY, NT, WPE, PAIRS, ROWWISE>;
     static const int64_t resident = resident_blocks(kern, NT);
     const FusedWork wk = plan_work(resident, g, TX, TY);
     hipLaunchKernelGGL(kern, dim3((unsigned)wk.nblocks), dim3(NT), 0, s, (const T*)src, (T*)dst,
@@ -247,7 +247,14 @@ cs_status launch_fused_sweep(int dtype, int dim, int stencil, const Geo& g, cons
         case 4: CS_Q13(64, 8, 128, 4, true);
         case 5: CS_Q13(128, 8, 256, 2, true);
         case 6: CS_Q13(32, 32, 256, 3, true);
-        default: CS_Q13(64, 16, 256, 2, true);
+        case 7: CS_Q13(64, 16, 256, 2, true);
+        default:
+            // the pair update row by row: FP64 with 512 threads (two
+            // workgroups of 8 waves per CU, 107 VGPRs), FP32 with 256
+            // (measured at 256^3 and 512^3)
+            return dtype == 0
+                       ? fused_q1_3_t<double, 64, 16, 512, 4, true, true>(g, src, dst, b, h2, s)
+                       : fused_q1_3_t<float, 64, 16, 256, 2, true, true>(g, src, dst, b, h2, s);
         }
     }
     switch (fused_variant()) {
