@@ -64,7 +64,7 @@ k_batch_fd3_two(const BatchPatch* __restrict__ tab, int count, int phase)
     fd3_tile_two<T, TX, TY, NT, D, NB>(src, dst, (const T*)P.b, P.g, (T)P.h2, tb);
 }
 
-template <typename T, int TX, int TY, int NT, int WPE>
+template <typename T, int TX, int TY, int NT, int WPE, bool ROWWISE>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_batch_q1_3(const BatchPatch* __restrict__ tab, int count, int phase)
 {
@@ -74,7 +74,7 @@ k_batch_q1_3(const BatchPatch* __restrict__ tab, int count, int phase)
     const TileBox tb = tile_box<TX, TY>(P.g, P.tiles_x, P.tiles_y, P.chunks, w - P.item_begin);
     const T* src = (const T*)(phase ? P.tmp : P.u);
     T* dst = (T*)(phase ? P.u : P.tmp);
-    q1_3_tile_pairs<T, TX, TY, NT>(src, dst, (const T*)P.b, P.g, (T)P.h2, tb);
+    q1_3_tile_pairs<T, TX, TY, NT, ROWWISE>(src, dst, (const T*)P.b, P.g, (T)P.h2, tb);
 }
 
 // Halo copy u -> tmp, one workgroup per patch.
@@ -255,8 +255,8 @@ cs_status launch_batch_sweep(int dtype, int stencil, int variant, const BatchPat
     }
 #define CS_BFD(T, TX, TY, NT, D) \
     hipLaunchKernelGGL((k_batch_fd3<T, TX, TY, NT, D>), grid, dim3(NT), 0, s, tab, count, phase)
-#define CS_BQ1(T, TX, TY, NT, WPE) \
-    hipLaunchKernelGGL((k_batch_q1_3<T, TX, TY, NT, WPE>), grid, dim3(NT), 0, s, tab, count, phase)
+#define CS_BQ1(T, TX, TY, NT, WPE, RW) \
+    hipLaunchKernelGGL((k_batch_q1_3<T, TX, TY, NT, WPE, RW>), grid, dim3(NT), 0, s, tab, count, phase)
     if (stencil == FD) {
         if (dtype == 0) {
             if (variant == 0) CS_BFD(double, 16, 16, 256, 1);
@@ -268,14 +268,16 @@ cs_status launch_batch_sweep(int dtype, int stencil, int variant, const BatchPat
             else CS_BFD(float, 64, 16, 512, 1);
         }
     } else {
+        // the large FP64 tile and every FP32 tile take the row-wise pair
+        // update (as the single-grid 27-point sweep)
         if (dtype == 0) {
-            if (variant == 0) CS_BQ1(double, 16, 8, 128, 2);
-            else if (variant == 1) CS_BQ1(double, 32, 16, 256, 2);
-            else CS_BQ1(double, 64, 16, 256, 2);
+            if (variant == 0) CS_BQ1(double, 16, 8, 128, 2, false);
+            else if (variant == 1) CS_BQ1(double, 32, 16, 256, 2, false);
+            else CS_BQ1(double, 64, 16, 512, 4, true);
         } else {
-            if (variant == 0) CS_BQ1(float, 16, 8, 128, 2);
-            else if (variant == 1) CS_BQ1(float, 32, 16, 256, 2);
-            else CS_BQ1(float, 64, 16, 256, 2);
+            if (variant == 0) CS_BQ1(float, 16, 8, 128, 2, true);
+            else if (variant == 1) CS_BQ1(float, 32, 16, 256, 2, true);
+            else CS_BQ1(float, 64, 16, 256, 2, true);
         }
     }
 #undef CS_BFD

@@ -752,18 +752,7 @@ StreamWork plan(const Geo& g, int max_blocks)
     wk.tiles_x = (int)((g.nx + TX - 1) / TX);
     wk.tiles_y = (int)((g.ny + TY - 1) / TY);
     const int64_t tiles = (int64_t)wk.tiles_x * wk.tiles_y;
-    static int64_t resident = 0;  // queried once per kernel
-    if (resident == 0) {
-        int per_cu = 0, dev = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, 0) != hipSuccess ||
-            hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-            (void)hipGetLastError();
-            per_cu = 2;
-            cus = 256;
-        }
-        resident = (int64_t)(per_cu > 0 ? per_cu : 1) * cus;
-    }
+    static const int64_t resident = resident_of(kern, NT);  // once per kernel
     int64_t chunks = resident / tiles;
     if (chunks < 1) chunks = 1;
     if (chunks > g.nz / 4) chunks = g.nz / 4 > 0 ? g.nz / 4 : 1;
