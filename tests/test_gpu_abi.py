@@ -1,4 +1,4 @@
-"""Argument validation and ownership through the C ABI (GPU machine).
+"""Argument validation and ownership through the C ABI (on a GPU).
 
 Every bad call must come back with a status and a message before anything is
 launched; none of these tests launches a kernel on invalid memory."""

@@ -2,7 +2,7 @@
 
 Parity: a fixed number of refinement steps on the GPU and in the oracle (same
 scale rule, same inner sweep count) give the same iterate to 1e-13.
-Convergence: the GPU reaches 1e-10 relative residual, judged by the oracle's
+Convergence: the GPU reaches 1e-10 relative residual, measured by the oracle's
 own FP64 residual of the GPU's final iterate.
 """
 import numpy as np
