@@ -225,6 +225,13 @@ cs_status cs_batch_residual(cs_batch bt, double* norms, void* stream);
  * for a bad stencil or dtype, or small_max > mid_max. */
 cs_status cs_batch_tile_policy(int32_t stencil, int32_t dtype, int32_t small_max, int32_t mid_max);
 
+/* Colour schedule for batches created afterwards (process-wide, per stencil
+ * and dtype): pair_large = 1 (default) runs the sweeps of the large 7-point
+ * tile class two per pass over memory, 0 one per pass; the iterate is the same
+ * either way.  Set by the autotuner.  Errors: CS_EINVAL for a bad stencil or
+ * dtype, or pair_large not 0/1. */
+cs_status cs_batch_pass_policy(int32_t stencil, int32_t dtype, int32_t pair_large);
+
 /* ---- Captured sweep sequences (HIP graphs) -------------------------------
  * A fixed number of sweeps recorded once into a HIP graph and replayed with
  * one launch call, for callers that repeat the same sweeps many times on small

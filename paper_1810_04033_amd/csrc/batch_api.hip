@@ -18,6 +18,7 @@ namespace {
 
 struct Group {
     int dtype = 0, stencil = 0, variant = 0;
+    bool pairs = false;  // two sweeps per launch
     std::vector<BatchPatch> host;
     BatchPatch* dev = nullptr;
     int64_t items = 0, res_items = 0, partial_base = 0;
@@ -26,6 +27,7 @@ struct Group {
 // [stencil][dtype]
 int g_small_max[2][2] = {{16, 16}, {16, 16}};
 int g_mid_max[2][2] = {{40, 40}, {40, 40}};
+int g_pair_large[2][2] = {{1, 1}, {1, 1}};  // pair the sweeps of the large tile class
 
 int pick_variant(int stencil, int dtype, int64_t nx)
 {
@@ -69,6 +71,17 @@ cs_status cs_batch_tile_policy(int32_t stencil, int32_t dtype, int32_t small_max
     }
     g_small_max[stencil][dtype] = small_max;
     g_mid_max[stencil][dtype] = mid_max;
+    return CS_OK;
+}
+
+cs_status cs_batch_pass_policy(int32_t stencil, int32_t dtype, int32_t pair_large)
+{
+    if ((stencil != CS_FD && stencil != CS_Q1) || (dtype != CS_F64 && dtype != CS_F32) ||
+        (pair_large != 0 && pair_large != 1)) {
+        set_error("bad pass policy");
+        return CS_EINVAL;
+    }
+    g_pair_large[stencil][dtype] = pair_large;
     return CS_OK;
 }
 
@@ -121,6 +134,7 @@ cs_status cs_batch_create(const cs_grid_desc* descs, void* const* u, const void*
         p.h2 = d.dtype == CS_F32 ? (double)(float)p.hh : p.hh;
         p.index = i;
         const int variant = pick_variant(d.stencil, d.dtype, d.n[0]);
+        const bool pairs = batch_variant_pairs(d.stencil, variant) && g_pair_large[d.stencil][d.dtype];
         int tx = 0, ty = 0;
         batch_variant_tile(d.stencil, variant, &tx, &ty);
         p.tiles_x = (int)((d.n[0] + tx - 1) / tx);
@@ -131,18 +145,19 @@ cs_status cs_batch_create(const cs_grid_desc* descs, void* const* u, const void*
         int k = -1;
         for (size_t j = 0; j < bt->groups.size(); ++j)
             if (bt->groups[j].dtype == d.dtype && bt->groups[j].stencil == d.stencil &&
-                bt->groups[j].variant == variant)
+                bt->groups[j].variant == variant && bt->groups[j].pairs == pairs)
                 k = (int)j;
         if (k < 0) {
             Group gr;
             gr.dtype = d.dtype;
             gr.stencil = d.stencil;
             gr.variant = variant;
+            gr.pairs = pairs;
             bt->groups.push_back(gr);
             k = (int)bt->groups.size() - 1;
         }
         bt->groups[k].host.push_back(p);
-        bt->per_pass.push_back(batch_variant_pairs(d.stencil, variant) ? 2 : 1);
+        bt->per_pass.push_back(pairs ? 2 : 1);
     }
     // z chunks: enough work items to fill the GPU (about 2048) when the batch
     // holds few patches, never chunks thinner than 8 planes (16 for the tile
@@ -153,7 +168,7 @@ cs_status cs_batch_create(const cs_grid_desc* descs, void* const* u, const void*
         for (auto& p : gr.host) total_tiles += (int64_t)p.tiles_x * p.tiles_y;
     const int64_t want = (2048 + total_tiles - 1) / total_tiles;
     for (auto& gr : bt->groups) {
-        const int depth = batch_variant_min_depth(gr.stencil, gr.variant);
+        const int depth = gr.pairs ? 16 : 8;
         for (auto& p : gr.host)
             p.chunks = (int)std::max<int64_t>(1, std::min<int64_t>(want, p.g.nz / depth));
     }
@@ -208,7 +223,7 @@ cs_status cs_batch_gs_sweeps(cs_batch bt, int32_t nsweeps, void* stream)
         const bool pair = nsweeps - it >= 2;
         for (size_t gi = 0; gi < bt->groups.size(); ++gi) {
             Group& gr = bt->groups[gi];
-            const bool two = batch_variant_pairs(gr.stencil, gr.variant);
+            const bool two = gr.pairs;
             if (two && !pair) continue;
             const int runs = (two || !pair) ? 1 : 2;
             for (int r = 0; r < runs; ++r) {
@@ -223,7 +238,7 @@ cs_status cs_batch_gs_sweeps(cs_batch bt, int32_t nsweeps, void* stream)
             // the last, odd sweep: the paired groups take it as a single sweep
             for (size_t gi = 0; gi < bt->groups.size(); ++gi) {
                 Group& gr = bt->groups[gi];
-                if (!batch_variant_pairs(gr.stencil, gr.variant)) continue;
+                if (!gr.pairs) continue;
                 if ((st = launch_batch_sweep(gr.dtype, gr.stencil, gr.variant, gr.dev,
                                              (int)gr.host.size(), gr.items, phase[gi], false, s)) !=
                     CS_OK)

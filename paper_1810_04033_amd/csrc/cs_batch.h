@@ -22,11 +22,10 @@ struct BatchPatch {
 
 int64_t batch_residual_items(const Geo& g);
 void batch_variant_tile(int stencil, int variant, int* tx, int* ty);
-// Whether a tile variant also runs two sweeps per launch (the large 7-point
-// class: 64 x 16 tiles, the same work items for the single and the double
-// sweep) and the least chunk depth its items are planned with.
+// Whether a tile variant can also run two sweeps per launch (the large
+// 7-point class: 64 x 16 tiles, the same work items for the single and the
+// double sweep); its items are then planned at least 16 planes deep.
 bool batch_variant_pairs(int stencil, int variant);
-int batch_variant_min_depth(int stencil, int variant);
 cs_status launch_batch_sweep(int dtype, int stencil, int variant, const BatchPatch* tab, int count,
                              int64_t items, int phase, bool two, hipStream_t s);
 cs_status launch_batch_halo(int dtype, const BatchPatch* tab, int count, hipStream_t s);

@@ -230,11 +230,6 @@ bool batch_variant_pairs(int stencil, int variant)
     return stencil == FD && variant >= 2;
 }
 
-int batch_variant_min_depth(int stencil, int variant)
-{
-    return batch_variant_pairs(stencil, variant) ? 16 : 8;
-}
-
 cs_status launch_batch_sweep(int dtype, int stencil, int variant, const BatchPatch* tab, int count,
                              int64_t items, int phase, bool two, hipStream_t s)
 {

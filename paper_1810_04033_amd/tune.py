@@ -1,15 +1,21 @@
-"""Autotuner for the batched-patch tile shapes.
+"""Autotuner for the batched-patch tile shapes and colour schedule.
 
 For each patch edge class it times the batched Gauss-Seidel sweep with each
 tile variant (small, middle, large tiles) on a batch of equal patches large
 enough to fill the GPU, picks the fastest variant per edge, and turns the
-picks into the size thresholds of cs_batch_tile_policy.  Results are cached
+picks into the size thresholds of cs_batch_tile_policy.  For the 7-point
+stencil the large tiles are timed with two sweeps per pass and with one, per
+edge and on a batch mixing (in equal counts) the edges that pick them, and the
+schedule that is faster on the mix is set with cs_batch_pass_policy (both give
+the same iterate; batches of equal patches are chunked differently from mixed
+ones, so the mix decides).  Results are cached
 as JSON keyed by GPU architecture, stencil and dtype (COLSTEN_TUNE_CACHE,
 default ~/.cache/colsten_tune.json), so later processes apply them without
 re-timing.
 """
 import json
 import os
+import sys
 
 import torch
 
@@ -35,13 +41,23 @@ def _key(stencil, dtype):
                          "f64" if dtype == torch.float64 else "f32")
 
 
-def _time_batch(edge, stencil, dtype, variant, points_target, sweeps):
-    # force one variant for every edge
+def _time_batch(edge, stencil, dtype, variant, points_target, sweeps, pair=True):
+    # force one variant (and schedule) for every edge
     C.cs_batch_tile_policy(stencil, C._DT[dtype], 1 << 30 if variant == 0 else 0,
                            1 << 30 if variant <= 1 else 0)
-    count = max(1, points_target // edge ** 3)
+    return _time_edges([edge], stencil, dtype, points_target, sweeps, pair)
+
+
+def _time_edges(edges, stencil, dtype, points_target, sweeps, pair):
+    """GLUP/s of a batch of cubic patches cycling through edges (equal counts)
+    up to about points_target points, under the current tile policy."""
+    C.cs_batch_pass_policy(stencil, C._DT[dtype], pair)
+    sizes, total = [], 0
+    while not sizes or total < points_target:
+        sizes.append(edges[len(sizes) % len(edges)])
+        total += sizes[-1] ** 3
     ps = []
-    for _ in range(count):
+    for edge in sizes:
         u = C.empty_grid((edge,) * 3, dtype=dtype)
         b = C.empty_grid((edge,) * 3, dtype=dtype)
         b.fill_(1.0)
@@ -57,23 +73,45 @@ def _time_batch(edge, stencil, dtype, variant, points_target, sweeps):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     bt.close()
-    return count * edge ** 3 * sweeps / (ms * 1e-3) / 1e9
+    return total * sweeps / (ms * 1e-3) / 1e9
 
 
 def tune(stencil, dtype=torch.float64, edges=(8, 16, 24, 32, 48, 64), points_target=1 << 24,
          sweeps=10, save=True):
     """Time every variant on every edge class; returns the record and applies
     the resulting policy."""
-    table = {}
+    table, single = {}, {}
     for e in edges:
         table[e] = [_time_batch(e, stencil, dtype, v, points_target, sweeps) for v in range(3)]
-    best = {e: max(range(3), key=lambda v: table[e][v]) for e in edges}
+        # the large tiles with one sweep per pass, where they can compete
+        if stencil == C.CS_FD and table[e][2] >= 0.75 * max(table[e][:2]):
+            single[e] = _time_batch(e, stencil, dtype, 2, points_target, sweeps, pair=False)
+        print("tune: edge %d: %s%s" % (e, [round(x, 1) for x in table[e]],
+                                       " one sweep per pass %.1f" % single[e] if e in single else ""),
+              file=sys.stderr, flush=True)
+    # the large tiles count with their faster schedule
+    rate = {e: table[e][:2] + [max(table[e][2], single.get(e, 0.0))] for e in edges}
+    best = {e: max(range(3), key=lambda v: rate[e][v]) for e in edges}
     # thresholds: the largest edge whose best variant is 0, then <= 1
     small_max = max([e for e in edges if best[e] == 0], default=0)
     mid_max = max([e for e in edges if best[e] <= 1] + [small_max])
+    large = [e for e in edges if best[e] == 2]
     C.cs_batch_tile_policy(stencil, C._DT[dtype], small_max, mid_max)
-    rec = {"small_max": small_max, "mid_max": mid_max,
+    # schedule of the large tiles, timed on a mix of the edges that use them,
+    # sized like a large batch (the z-chunking of a batch depends on its size)
+    mix = {}
+    if stencil == C.CS_FD and large:
+        for p in (True, False):
+            mix[p] = _time_edges(large, stencil, dtype, 8 * points_target, sweeps, p)
+            print("tune: mix of edges %s, %s per pass: %.1f GLUP/s"
+                  % (large, "two sweeps" if p else "one sweep", mix[p]), file=sys.stderr, flush=True)
+    pair = not mix or mix[True] >= mix[False]
+    C.cs_batch_pass_policy(stencil, C._DT[dtype], pair)
+    rec = {"small_max": small_max, "mid_max": mid_max, "pair_large": bool(pair),
            "glups": {str(e): [round(x, 2) for x in table[e]] for e in edges},
+           "glups_large_one_sweep_per_pass": {str(e): round(single[e], 2) for e in single},
+           "glups_large_mix": {("two_sweeps" if p else "one_sweep") + "_per_pass": round(v, 2)
+                               for p, v in mix.items()},
            "tiles": VARIANT_TILES[stencil]}
     if save:
         path = cache_path()
@@ -103,4 +141,5 @@ def apply_cached(stencil, dtype=torch.float64):
         return None
     if rec:
         C.cs_batch_tile_policy(stencil, C._DT[dtype], rec["small_max"], rec["mid_max"])
+        C.cs_batch_pass_policy(stencil, C._DT[dtype], rec.get("pair_large", True))
     return rec

@@ -146,3 +146,29 @@ def test_sweeps_per_pass_by_tile_class():
             bt.sweeps_per_pass(bad)
         assert e.value.status == C.CS_EINVAL
     bt.close()
+
+
+def test_pass_policy_one_sweep_per_pass_same_iterate():
+    """With the pass policy off, the large 7-point class runs one sweep per
+    pass and gives the same iterate bit for bit; bad policies are rejected."""
+    shapes = [(64, 64, 64), (48, 50, 40), (8, 8, 8)]
+    res = {}
+    for pair in (1, 0):
+        C.cs_batch_pass_policy(C.CS_FD, C.CS_F64, pair)
+        try:
+            ps = [_patch(n, C.CS_FD, torch.float64, i % 2, seed=1800 + i) for i, n in enumerate(shapes)]
+            bt = _batch(ps)
+            per = [bt.sweeps_per_pass(i) for i in range(len(ps))]
+            bt.gs(5)
+            torch.cuda.synchronize()
+            res[pair] = ([G.download(p["ug"]) for p in ps], per)
+            bt.close()
+        finally:
+            C.cs_batch_pass_policy(C.CS_FD, C.CS_F64, 1)
+    assert res[1][1] == [2, 2, 1] and res[0][1] == [1, 1, 1]
+    for a, b in zip(res[1][0], res[0][0]):
+        assert np.array_equal(a, b)
+    for bad in ((2, 0, 1), (0, 2, 1), (0, 0, 2)):
+        with pytest.raises(C.ColstenError) as e:
+            C.cs_batch_pass_policy(*bad)
+        assert e.value.status == C.CS_EINVAL
