@@ -618,6 +618,7 @@ def run_orderings(a):
                  "lexicographic_wavefront_graph": lambda k: [graphs["lexicographic_wavefront_graph"].launch()
                                                              for _ in range(k // sweeps)],
                  "coloured_per_colour": lambda k: g.gs(k),
+                 "coloured_persistent_barrier": lambda k: g.gs_sync(k),
                  "coloured_per_colour_graph": lambda k: [graphs["coloured_per_colour_graph"].launch()
                                                          for _ in range(k // sweeps)]}
         if g.fused:

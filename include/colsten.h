@@ -119,6 +119,22 @@ cs_status cs_gs_sweeps(cs_grid g, int32_t nsweeps, void* u_tmp, void* stream);
  * Errors: CS_EINVAL (u_tmp NULL, nsweeps < 0, omega not finite). */
 cs_status cs_jacobi_sweeps(cs_grid g, double omega, int32_t nsweeps, void* u_tmp, void* stream);
 
+/* nsweeps Gauss-Seidel sweeps (colours 0..c-1 in order, in place) in one
+ * persistent launch with a device-wide barrier after every colour: the
+ * Hyb-sync form of the colouring (Sec. 5, Algorithm 1), one parallel region
+ * instead of a launch per colour.  The iterate equals cs_gs_sweeps' bit for
+ * bit.  Every workgroup of the cooperative launch is resident and runs the
+ * same barriers; a barrier wait that polls too long (it never should) is
+ * counted, gives up and goes on instead of hanging -- see
+ * cs_gs_sync_failures.  Errors: CS_EINVAL (nsweeps < 0), CS_EHIP if the
+ * cooperative launch is refused. */
+cs_status cs_gs_sweeps_sync(cs_grid g, int32_t nsweeps, void* stream);
+
+/* *out = number of barrier waits of cs_gs_sweeps_sync on g that gave up since
+ * the grid was created (0 unless something went wrong).  Synchronises stream.
+ * Errors: CS_EINVAL (bad grid, out NULL), CS_EHIP. */
+cs_status cs_gs_sync_failures(cs_grid g, int32_t* out, void* stream);
+
 /* nsweeps lexicographic Gauss-Seidel sweeps: the iterate of the sequential
  * in-place loop in z-y-x order (x innermost), which the task graph of Sec. 3
  * preserves; no colouring, so a different iterate from cs_gs_sweeps.  Run as

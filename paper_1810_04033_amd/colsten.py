@@ -54,6 +54,8 @@ _SIGS = {
     "cs_num_colours": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "cs_gs_fused": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "cs_grid_set_pass_mode": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "cs_gs_sweeps_sync": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "cs_gs_sync_failures": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
     "cs_sweeps_per_pass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "cs_colour_pass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "cs_gs_sweeps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
@@ -150,6 +152,16 @@ def cs_gs_fused(handle):
     out = ctypes.c_int32()
     _check(lib().cs_gs_fused(ctypes.c_void_p(handle), ctypes.byref(out)))
     return bool(out.value)
+
+
+def cs_gs_sweeps_sync(handle, nsweeps, stream=None):
+    _check(lib().cs_gs_sweeps_sync(ctypes.c_void_p(handle), ctypes.c_int32(nsweeps), _stream(stream)))
+
+
+def cs_gs_sync_failures(handle, stream=None):
+    out = ctypes.c_int32()
+    _check(lib().cs_gs_sync_failures(ctypes.c_void_p(handle), ctypes.byref(out), _stream(stream)))
+    return out.value
 
 
 def cs_grid_set_pass_mode(handle, mode):
@@ -340,6 +352,13 @@ class Grid:
     @property
     def fused(self):
         return cs_gs_fused(self.handle)
+
+    def gs_sync(self, nsweeps, stream=None):
+        """Sweeps in one persistent launch with a device-wide barrier per colour."""
+        cs_gs_sweeps_sync(self.handle, nsweeps, stream)
+
+    def sync_failures(self, stream=None):
+        return cs_gs_sync_failures(self.handle, stream)
 
     def set_pass_mode(self, mode):
         """CS_PASS_AUTO, CS_PASS_ONE or CS_PASS_TWO: sweeps per pass over memory."""

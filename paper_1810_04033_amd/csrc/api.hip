@@ -178,6 +178,16 @@ cs_status cs_grid_create(const cs_grid_desc* desc, void* u, const void* b, cs_gr
         set_error("hipMalloc of the reduction scratch failed: %s", hipGetErrorString(e));
         return CS_ENOMEM;
     }
+    e = hipMalloc((void**)&g->bar, 4 * sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemset(g->bar, 0, 4 * sizeof(unsigned));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(g->partials);
+        if (g->bar) (void)hipFree(g->bar);
+        delete g;
+        set_error("allocation of the barrier words failed: %s", hipGetErrorString(e));
+        return CS_ENOMEM;
+    }
     *out = g;
     return CS_OK;
 }
@@ -186,6 +196,8 @@ cs_status cs_grid_destroy(cs_grid g)
 {
     if (!g) return CS_OK;
     hipError_t e = hipFree(g->partials);
+    const hipError_t e2 = hipFree(g->bar);
+    if (e == hipSuccess) e = e2;
     delete g;
     if (e != hipSuccess) return hip_fail(e, "hipFree");
     return CS_OK;
@@ -333,6 +345,30 @@ cs_status cs_apply(cs_grid g, void* y, int32_t cellwise, void* stream)
     }
     return launch_apply(g->d.dtype, g->d.dim, g->d.stencil, g->geo, g->u, y, h2_of(g), cellwise,
                         (hipStream_t)stream);
+}
+
+cs_status cs_gs_sweeps_sync(cs_grid g, int32_t nsweeps, void* stream)
+{
+    cs_status st = check_grid(g);
+    if (st != CS_OK) return st;
+    if (nsweeps < 0) { set_error("nsweeps must be >= 0"); return CS_EINVAL; }
+    if (nsweeps == 0) return CS_OK;
+    return launch_sync_sweeps(g->d.dtype, g->d.dim, g->d.stencil, g->geo, g->u, g->b, h2_of(g),
+                              nsweeps, g->bar, (hipStream_t)stream);
+}
+
+cs_status cs_gs_sync_failures(cs_grid g, int32_t* out, void* stream)
+{
+    cs_status st = check_grid(g);
+    if (st != CS_OK) return st;
+    if (!out) { set_error("out is NULL"); return CS_EINVAL; }
+    unsigned words[4] = {0, 0, 0, 0};
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(words, g->bar, sizeof(words), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "reading the barrier words");
+    *out = (int32_t)words[2];
+    return CS_OK;
 }
 
 cs_status cs_gs_sweeps_lex(cs_grid g, int32_t nsweeps, void* stream)

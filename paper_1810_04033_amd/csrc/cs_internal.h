@@ -95,6 +95,10 @@ cs_status launch_ir_residual3(int stencil, const Geo& g, const void* x, const vo
                               Partial* partials, double* norms, hipStream_t s);
 cs_status launch_ir_update(int dim, const Geo& g, void* x, const Geo& g2, const void* e32,
                            double scale, hipStream_t s);
+// Persistent colour sweeps with a device-wide barrier between colours
+// (k_sync.hip); bar: three zeroed words of device memory owned by the grid.
+cs_status launch_sync_sweeps(int dtype, int dim, int stencil, const Geo& g, void* u,
+                             const void* b, double h2, int nsweeps, unsigned* bar, hipStream_t s);
 // z-streaming Jacobi and residual for 3D grids (k_stream.hip).
 bool stream_supported(const Geo& g);
 cs_status launch_jacobi3_stream(int dtype, int stencil, const Geo& g, const void* src, void* dst,
@@ -120,4 +124,5 @@ struct cs_grid_s {
     int64_t span;         // elements from the first to one past the last halo'd element
     cs::Partial* partials;  // kMaxResidualBlocks entries of device scratch
     int pass_mode;        // cs_pass_mode: sweeps per pass over memory
+    unsigned* bar;        // device-wide barrier words of the persistent sweep
 };

@@ -1,0 +1,180 @@
+// Persistent colour sweeps with a device-wide barrier between colours: the
+// Hyb-sync form of the colouring (Sec. 5, Algorithm 1), one parallel region
+// for all sweeps with a barrier after each colour, instead of a fork and join
+// (a launch) per colour.
+//
+// One cooperative launch holds every workgroup resident.  For each sweep and
+// colour, the workgroups update that colour's points in a grid-stride loop --
+// the same point update, in place, as the one-launch-per-colour pass, so the
+// iterate is the same bit for bit -- and then meet at a device-wide barrier.
+// Every workgroup runs the same number of barriers, so all of them reach the
+// end of the kernel.
+#include "cs_device.h"
+#include "cs_internal.h"
+
+#include <stdint.h>
+
+namespace cs {
+
+namespace {
+
+// polls (each followed by a short sleep) before a barrier gives up waiting
+constexpr unsigned kSpinLimit = 1u << 24;
+
+// Device-wide barrier.  bar[0] counts arrivals, bar[1] is the generation,
+// bar[2] counts waits that gave up.  The last workgroup to arrive resets the
+// count and starts the next generation; the others poll the generation.  A
+// workgroup that polls kSpinLimit times without seeing it records a failure
+// and goes on, so a barrier cannot wait forever (the result is then not to be
+// trusted, and cs_gs_sync_failures reports it).  The workgroup barrier
+// completes every wave's stores into the XCD's L2; one device-scope fence by
+// the first thread then writes them back before it arrives, and one after the
+// wait invalidates the L2 and the CU's L1, so the next colour reads the values
+// the other workgroups, on any XCD, wrote.  (A fence in every wave costs a
+// write-back and invalidation of the L2 per wave: ~30 us per barrier.)
+__device__ void grid_barrier(unsigned* bar, unsigned nblocks)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived =
+            __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nblocks - 1) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                if (++spins == kSpinLimit) {
+                    __hip_atomic_fetch_add(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+// Number of points of colour c and the point of index w among them.
+struct ColourSet {
+    int64_t i0, j0, k0;  // first point (Q1) or row start data (FD)
+    int64_t cx, cy, cz;  // counts along x, y, z (FD: cx = slots per row)
+    int64_t total;
+};
+
+template <int DIM, int ST>
+__device__ inline ColourSet colour_set(const Geo& g, int c)
+{
+    ColourSet s;
+    if (ST == FD) {
+        s.i0 = s.j0 = s.k0 = 0;
+        s.cx = (g.nx + 1) / 2;  // slots per row; the row's first x depends on the row
+        s.cy = g.ny;
+        s.cz = DIM == 3 ? g.nz : 1;
+    } else {
+        const int px = c & 1, py = (c >> 1) & 1, pz = (c >> 2) & 1;
+        s.i0 = 1 + ((px + g.parity) & 1);
+        s.j0 = 1 + ((py + g.parity) & 1);
+        s.k0 = DIM == 3 ? 1 + ((pz + g.parity) & 1) : 1;
+        s.cx = s.i0 <= g.nx ? (g.nx - s.i0) / 2 + 1 : 0;
+        s.cy = s.j0 <= g.ny ? (g.ny - s.j0) / 2 + 1 : 0;
+        s.cz = DIM == 3 ? (s.k0 <= g.nz ? (g.nz - s.k0) / 2 + 1 : 0) : 1;
+    }
+    s.total = s.cx * s.cy * s.cz;
+    return s;
+}
+
+constexpr int kSyncThreads = 1024;
+
+template <typename T, int DIM, int ST>
+__global__ void __launch_bounds__(kSyncThreads)
+k_sync_sweeps(T* u, const T* __restrict__ b, Geo g, T h2, int nsweeps, unsigned* bar)
+{
+    constexpr int NC = num_colours<ST, DIM>();
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t sy = g.sy, sz = g.sz;
+    for (int sw = 0; sw < nsweeps; ++sw) {
+        for (int c = 0; c < NC; ++c) {
+            const ColourSet cs = colour_set<DIM, ST>(g, c);
+            for (int64_t w = tid; w < cs.total; w += nthreads) {
+                const int64_t m = w % cs.cx, n = (w / cs.cx) % cs.cy, l = w / (cs.cx * cs.cy);
+                int64_t i, j, k;
+                if (ST == FD) {
+                    j = 1 + n;
+                    k = 1 + l;
+                    const int64_t kk = DIM == 3 ? k - 1 : 0;
+                    i = 1 + ((c + (j - 1) + kk + g.parity) & 1) + 2 * m;
+                    if (i > g.nx) continue;
+                } else {
+                    i = cs.i0 + 2 * m;
+                    j = cs.j0 + 2 * n;
+                    k = cs.k0 + 2 * l;
+                }
+                const int64_t q = (DIM == 3 ? k * sz : 0) + j * sy + i;
+                auto ld = [&](int ox, int oy, int oz) { return u[q + oz * sz + oy * sy + ox]; };
+                u[q] = gs_value<T, DIM, ST>(h2, b[q], ld);
+            }
+            grid_barrier(bar, gridDim.x);
+        }
+    }
+}
+
+template <typename T, int DIM, int ST>
+cs_status sync_sweeps_t(const Geo& g, void* u, const void* b, double h2, int nsweeps,
+                        unsigned* bar, hipStream_t s)
+{
+    auto kern = k_sync_sweeps<T, DIM, ST>;
+    static const int64_t resident = [&] {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kSyncThreads, 0) != hipSuccess ||
+            hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            return (int64_t)0;
+        }
+        // one workgroup per CU: fewer workgroups, fewer fences per barrier
+        return (int64_t)(per_cu > 0 ? 1 : 0) * cus;
+    }();
+    if (resident <= 0) {
+        set_error("persistent sweep: no resident workgroups");
+        return CS_EHIP;
+    }
+    // enough workgroups for the largest colour, at most what fits at once
+    const int64_t pts = g.nx * g.ny * (DIM == 3 ? g.nz : 1);
+    int64_t blocks = (pts / 2 + kSyncThreads - 1) / kSyncThreads;
+    if (blocks > resident) blocks = resident;
+    if (blocks < 1) blocks = 1;
+    Geo gg = g;
+    T h2t = (T)h2;
+    int ns = nsweeps;
+    void* args[] = {&u, (void*)&b, &gg, &h2t, &ns, &bar};
+    hipError_t e = hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)blocks),
+                                              dim3(kSyncThreads), args, 0, s);
+    if (e != hipSuccess) return hip_fail(e, "hipLaunchCooperativeKernel");
+    return check_launch("persistent colour sweeps");
+}
+
+}  // namespace
+
+cs_status launch_sync_sweeps(int dtype, int dim, int stencil, const Geo& g, void* u,
+                             const void* b, double h2, int nsweeps, unsigned* bar, hipStream_t s)
+{
+    if (dtype == 0) {
+        if (dim == 2)
+            return stencil == FD ? sync_sweeps_t<double, 2, FD>(g, u, b, h2, nsweeps, bar, s)
+                                 : sync_sweeps_t<double, 2, Q1>(g, u, b, h2, nsweeps, bar, s);
+        return stencil == FD ? sync_sweeps_t<double, 3, FD>(g, u, b, h2, nsweeps, bar, s)
+                             : sync_sweeps_t<double, 3, Q1>(g, u, b, h2, nsweeps, bar, s);
+    }
+    if (dim == 2)
+        return stencil == FD ? sync_sweeps_t<float, 2, FD>(g, u, b, h2, nsweeps, bar, s)
+                             : sync_sweeps_t<float, 2, Q1>(g, u, b, h2, nsweeps, bar, s);
+    return stencil == FD ? sync_sweeps_t<float, 3, FD>(g, u, b, h2, nsweeps, bar, s)
+                         : sync_sweeps_t<float, 3, Q1>(g, u, b, h2, nsweeps, bar, s);
+}
+
+}  // namespace cs
