@@ -79,22 +79,43 @@ def _traffic(kernel_key, sha):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline():
+def _omp_threads():
+    """Threads of the OpenMP oracle: OMP_NUM_THREADS if set, else the cores
+    this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(openmp=False):
     """The oracle on the host: one sweep of each kind plus both residuals at
-    the full 256^3 size (single thread)."""
+    the full 256^3 size, single thread; with openmp, the four sweeps alone with
+    the same oracle source built with OpenMP (one parallel loop per colour, the
+    paper's BSP colouring of Sec. 3) on the host cores (the residual's
+    fixed-order sums are sequential, so they are left out of that sample)."""
     import numpy as np
     from oracle import oracle as O
     from paper_1810_04033_amd import inputs as I
 
+    O.set_openmp(openmp)
     b = I.halo_array(I.uniform_field(2, (N, N, N)))
     t0 = time.perf_counter()
     for st in (O.FD, O.Q1):
         u = I.halo_array(np.zeros((N, N, N)))
         O.gs_sweeps(u, b, 1, dim=3, stencil=st, h=H)
-        O.residual(u, b, dim=3, stencil=st, h=H)
+        if not openmp:
+            O.residual(u, b, dim=3, stencil=st, h=H)
         uj = I.halo_array(np.zeros((N, N, N)))
         O.jacobi_sweeps(uj, b, 1, OMEGA, dim=3, stencil=st, h=H)
     dt = time.perf_counter() - t0
+    O.set_openmp(False)
+    if openmp:
+        return {"value": 4 * N ** 3 / dt / 1e9, "unit": "GLUP/s", "cores": _omp_threads(),
+                "kind": "oracle, OpenMP build",
+                "sample": "one sweep of each of the four sweep kinds on the full 256^3 grid (no "
+                          "residuals), the oracle built with -fopenmp (a parallel loop per colour "
+                          "and per Jacobi sweep), %.1f s" % dt}
     return {"value": 4 * N ** 3 / dt / 1e9, "unit": "GLUP/s", "cores": 1, "kind": "oracle",
             "sample": "one sweep of each of the four sweep kinds plus both residual norms on the "
                       "full 256^3 grid, sequential C oracle, %.1f s" % dt}
@@ -257,6 +278,7 @@ def run_poisson3d(a):
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
+        out["cpu_openmp"] = cpu_baseline(openmp=True)
     print(json.dumps(out), flush=True)
 
 

@@ -21,21 +21,36 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "colsten_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")  # the same source with -fopenmp
 _lib = None
+_openmp = False
 
 FD, Q1 = 0, 1
 
 
-def build(force=True):
-    """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
-    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
-        return _LIB
-    tmp = _LIB + ".tmp%d" % os.getpid()
+def build(force=True, openmp=False):
+    """Compile the oracle with gcc (no FMA contraction, no fast-math); with
+    openmp, the same source with -fopenmp (the colour passes and Jacobi sweeps
+    then run one parallel loop per colour, Sec. 3)."""
+    out = _LIB_OMP if openmp else _LIB
+    if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(_SRC):
+        return out
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
            "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
+    cmd.insert(1, "-fopenmp" if openmp else "-Wno-unknown-pragmas")
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB)
-    return _LIB
+    os.replace(tmp, out)
+    return out
+
+
+def set_openmp(flag):
+    """Route the calls below to the OpenMP build (True) or the sequential one
+    (False, the default).  Both give the same results bit for bit."""
+    global _lib, _openmp
+    if bool(flag) != _openmp:
+        _openmp = bool(flag)
+        _lib = None
 
 
 def _load():
@@ -46,8 +61,7 @@ def _load():
     if alt:
         lib = ctypes.CDLL(alt)
     else:
-        build(force=False)
-        lib = ctypes.CDLL(_LIB)
+        lib = ctypes.CDLL(build(force=False, openmp=_openmp))
     i32, i64, f64, vp = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
     geo = [i32, i32, i32, i64, i64, i64, i64, i64, f64]
     lib.og_weight.restype = f64
