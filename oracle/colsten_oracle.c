@@ -651,3 +651,73 @@ void og_apply_stencil(int dim, int stencil, int64_t nx, int64_t ny, int64_t nz,
                 out[q] = og_fullsum(&g, u, q);
             }
 }
+
+/* ------------------------------------------------------------------ */
+/* Grid transfers of a geometric multigrid V-cycle                       */
+/* ------------------------------------------------------------------ */
+/* The paper names multigrid as the setting its smoothers serve (Sec. 1); a
+ * V-cycle here uses the coloured Gauss-Seidel sweep above as its smoother and
+ * the textbook vertex-centred transfers below.  A fine grid has n_f = 2 n_c + 1
+ * interior points per axis, and fine index i = 2 I lies on coarse index I, so
+ * the coarse halo (I = 0, n_c + 1) lies on the fine halo.
+ *
+ * Restriction by full weighting, at every coarse interior point:
+ *   bc_I = sum over o in {-1,0,1}^d of w(o_x) w(o_y) [w(o_z)] r_{2I+o},
+ *   w(0) = 1/2, w(+-1) = 1/4 (weights sum to 1; R = P^T / 2^d),
+ * terms in lexicographic (oz, oy, ox) order, each added with one fma; the
+ * coarse iterate uc is set to zero at the same points.
+ *
+ * Prolongation by d-linear interpolation, added to the fine iterate at every
+ * fine interior point:
+ *   uf_i <- uf_i + sum over coarse c with |2 c_m - i_m| <= 1 for every axis m
+ *           of prod_m (1 if 2 c_m = i_m, else 1/2) uc_c,
+ * coarse halo values included, terms in increasing (cz, cy, cx) order, each
+ * added with one fma, then one addition to uf.  All weights are powers of two,
+ * so their products are exact.                                              */
+static double og_fw(int o) { return o == 0 ? 0.5 : 0.25; }
+
+void og_restrict_f64(int dim, int64_t nxc, int64_t nyc, int64_t nzc, int64_t syc, int64_t szc,
+                     int64_t syf, int64_t szf, const double* r, double* bc, double* uc)
+{
+    int zr = dim == 3 ? 1 : 0;
+    int64_t nz = dim == 3 ? nzc : 1;
+    for (int64_t K = 1; K <= nz; ++K)
+        for (int64_t J = 1; J <= nyc; ++J)
+            for (int64_t I = 1; I <= nxc; ++I) {
+                int64_t qf = (dim == 3 ? 2 * K * szf : 0) + 2 * J * syf + 2 * I;
+                double acc = 0.0;
+                for (int oz = -zr; oz <= zr; ++oz)
+                    for (int oy = -1; oy <= 1; ++oy)
+                        for (int ox = -1; ox <= 1; ++ox) {
+                            double w = (dim == 3 ? og_fw(oz) : 1.0) * og_fw(oy) * og_fw(ox);
+                            acc = fma(w, r[qf + oz * szf + oy * syf + ox], acc);
+                        }
+                int64_t qc = (dim == 3 ? K * szc : 0) + J * syc + I;
+                bc[qc] = acc;
+                uc[qc] = 0.0;
+            }
+}
+
+void og_prolong_add_f64(int dim, int64_t nxf, int64_t nyf, int64_t nzf, int64_t syf, int64_t szf,
+                        int64_t syc, int64_t szc, const double* uc, double* uf)
+{
+    int64_t nz = dim == 3 ? nzf : 1;
+    for (int64_t k = 1; k <= nz; ++k)
+        for (int64_t j = 1; j <= nyf; ++j)
+            for (int64_t i = 1; i <= nxf; ++i) {
+                /* coarse neighbours along an axis: t/2, and t/2 + 1 when t is odd */
+                int nkz = dim == 3 ? 1 + (int)(k & 1) : 1;
+                int nky = 1 + (int)(j & 1), nkx = 1 + (int)(i & 1);
+                double wz = dim == 3 && (k & 1) ? 0.5 : 1.0;
+                double wy = (j & 1) ? 0.5 : 1.0, wx = (i & 1) ? 0.5 : 1.0;
+                double acc = 0.0;
+                for (int a = 0; a < nkz; ++a)
+                    for (int bb = 0; bb < nky; ++bb)
+                        for (int c = 0; c < nkx; ++c) {
+                            int64_t qc = (dim == 3 ? (k / 2 + a) * szc : 0) + (j / 2 + bb) * syc + i / 2 + c;
+                            acc = fma(wz * wy * wx, uc[qc], acc);
+                        }
+                int64_t q = (dim == 3 ? k * szf : 0) + j * syf + i;
+                uf[q] = uf[q] + acc;
+            }
+}

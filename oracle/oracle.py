@@ -100,6 +100,10 @@ def _load():
     lib.og_q1_apply_cellwise_coloured.argtypes = [i32, i64, i64, i64, i64, i64, vp, vp]
     lib.og_apply_stencil.restype = None
     lib.og_apply_stencil.argtypes = [i32, i32, i64, i64, i64, i64, i64, vp, vp]
+    lib.og_restrict_f64.restype = None
+    lib.og_restrict_f64.argtypes = [i32, i64, i64, i64, i64, i64, i64, i64, vp, vp, vp]
+    lib.og_prolong_add_f64.restype = None
+    lib.og_prolong_add_f64.argtypes = [i32, i64, i64, i64, i64, i64, i64, i64, vp, vp]
     _lib = lib
     return lib
 
@@ -310,3 +314,66 @@ def ir_solve(b, tol, *, dim, stencil, h, inner_sweeps, max_outer, x0=None):
         inner += s * interior(e).astype(np.float64)
         s = _pow2_at_least(norms[1])
     return x, hist, max_outer
+
+
+# ---------------------------------------------------------------------------
+# Geometric multigrid with the coloured sweep as smoother (the transfers are
+# defined in colsten_oracle.c).  FP64 only.
+# ---------------------------------------------------------------------------
+def _interior_n(a, dim):
+    nx, ny, nz, _, _ = _geometry(a, dim)
+    return (nx, ny) if dim == 2 else (nx, ny, nz)
+
+
+def _check_pair(fine, coarse, dim):
+    if fine.dtype != np.float64 or coarse.dtype != np.float64:
+        raise ValueError("multigrid transfers are float64")
+    nf, nc = _interior_n(fine, dim), _interior_n(coarse, dim)
+    if any(f != 2 * c + 1 for f, c in zip(nf, nc)):
+        raise ValueError("fine n %s is not 2 * coarse n + 1 (coarse %s)" % (nf, nc))
+
+
+def restrict(r, bc, uc, *, dim):
+    """bc <- full weighting of the fine residual r at the coarse interior;
+    uc <- 0 at the coarse interior (halos untouched)."""
+    _check_pair(r, bc, dim)
+    _check_same(bc, uc)
+    nxc, nyc, nzc, syc, szc = _geometry(bc, dim)
+    _, _, _, syf, szf = _geometry(r, dim)
+    _load().og_restrict_f64(dim, nxc, nyc, nzc, syc, szc, syf, szf, _ptr(r), _ptr(bc), _ptr(uc))
+
+
+def prolong_add(uc, uf, *, dim):
+    """uf <- uf + d-linear interpolation of uc (coarse halo included) at the
+    fine interior."""
+    _check_pair(uf, uc, dim)
+    nxf, nyf, nzf, syf, szf = _geometry(uf, dim)
+    _, _, _, syc, szc = _geometry(uc, dim)
+    _load().og_prolong_add_f64(dim, nxf, nyf, nzf, syf, szf, syc, szc, _ptr(uc), _ptr(uf))
+
+
+def mg_coarsens(n):
+    """Whether a grid of interior sizes n has a coarser level: every axis odd
+    and at least 3."""
+    return all(v % 2 == 1 and v >= 3 for v in n)
+
+
+def mg_vcycle(u, b, *, dim, stencil, h, nu1=2, nu2=2, coarse_sweeps=2, parity=0):
+    """One V(nu1, nu2)-cycle on A u = b in place: nu1 coloured Gauss-Seidel
+    sweeps, residual, restriction, the cycle on the coarse correction equation
+    (h doubled, zero initial guess and zero Dirichlet halo), prolongation added
+    to u, nu2 sweeps; on a grid that does not coarsen, coarse_sweeps sweeps."""
+    n = _interior_n(u, dim)
+    if not mg_coarsens(n):
+        gs_sweeps(u, b, coarse_sweeps, dim=dim, stencil=stencil, h=h, parity=parity)
+        return
+    gs_sweeps(u, b, nu1, dim=dim, stencil=stencil, h=h, parity=parity)
+    _, r = residual(u, b, dim=dim, stencil=stencil, h=h, want_r=True)
+    shape = tuple((v - 1) // 2 + 2 for v in reversed(n))
+    uc = np.zeros(shape, dtype=np.float64)
+    bc = np.zeros(shape, dtype=np.float64)
+    restrict(r, bc, uc, dim=dim)
+    mg_vcycle(uc, bc, dim=dim, stencil=stencil, h=2.0 * h, nu1=nu1, nu2=nu2,
+              coarse_sweeps=coarse_sweeps, parity=parity)
+    prolong_add(uc, u, dim=dim)
+    gs_sweeps(u, b, nu2, dim=dim, stencil=stencil, h=h, parity=parity)
