@@ -45,13 +45,18 @@ def _args():
     p.add_argument("--per-colour", action="store_true",
                    help="run the GS rows as one launch per colour pass (no work array)")
     p.add_argument("--workload", default="poisson3d",
-                   choices=["poisson3d", "patches", "refine", "serve", "expensive", "orderings"],
+                   choices=["poisson3d", "patches", "refine", "serve", "expensive", "orderings",
+                            "multigrid"],
                    help="poisson3d (default, the headline line); patches: 4096 batched patches; "
                         "refine: FP32 sweeps in FP64 refinement to 1e-10; serve: request stream; "
                         "expensive: sweeps with the S(k) stencil cost; orderings: lexicographic "
-                        "wavefront GS beside coloured GS")
+                        "wavefront GS beside coloured GS; multigrid: V-cycles with the coloured "
+                        "smoother to 1e-10")
     p.add_argument("--tune", action="store_true", help="patches: run the tile autotuner first")
     p.add_argument("--refine-n", type=int, default=512, help="refine: interior edge")
+    p.add_argument("--mg-n", type=int, default=255, help="multigrid: interior edge, 2^m - 1")
+    p.add_argument("--mg-gs-compare", type=int, default=1,
+                   help="multigrid: also solve with the coloured sweeps alone (1) or not (0)")
     return p.parse_args()
 
 
@@ -480,6 +485,111 @@ def run_refine(a):
     print(json.dumps(out), flush=True)
 
 
+def run_multigrid(a):
+    """3D Poisson, n^3 interior with n = 2^m - 1 (default 255), h = 1/(n+1),
+    uniform[-1,1) right-hand side (seed 2) made on the device, u0 = 0.
+    Multigrid V(2,2)-cycles whose smoother is the coloured Gauss-Seidel sweep
+    (red-black 7-point, 8-colour 27-point), full weighting and d-linear
+    interpolation down to one point, to 1e-10 relative residual; against the
+    coloured sweeps alone to the same tolerance.  The final residual of each
+    multigrid solve is recomputed by the oracle in FP64 on the host."""
+    import numpy as np
+    import torch
+
+    from paper_1810_04033_amd import colsten as C
+    from paper_1810_04033_amd import mg as MG
+    from paper_1810_04033_amd import solve as S
+
+    torch.cuda.set_device(0)
+
+    def say(msg):
+        print("[multigrid] " + msg, file=sys.stderr, flush=True)
+
+    last = [0.0]
+
+    def progress(sweeps, rel):
+        if time.perf_counter() - last[0] > 20.0:
+            last[0] = time.perf_counter()
+            say("%d sweeps, relative residual %.3e" % (sweeps, rel))
+
+    n = a.mg_n
+    if n < 3 or (n + 1) & n:
+        raise SystemExit("--mg-n must be 2^m - 1")
+    h = 1.0 / (n + 1)
+    tol = 1e-10
+    n3 = (n, n, n)
+    rows = {}
+    for name, st in (("fd7", C.CS_FD), ("q1_27", C.CS_Q1)):
+        b = C.empty_grid(n3)
+        C.fill_uniform(b, 2, dim=3)
+        u = C.empty_grid(n3)
+        g = C.Grid(u, b, dim=3, stencil=st, h=h)
+        mg = MG.Multigrid(g)
+        mg.cycle()  # warm-up (first launches), then start again from zero
+        torch.cuda.synchronize()
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = mg.solve(tol, max_cycles=100)
+        torch.cuda.synchronize()
+        mg_s = time.perf_counter() - t0
+        say("%s: %d cycles, %.3f s, relative residual %.3e" % (name, res.outer, mg_s, res.rel_residual))
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            mg.cycle()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        cycle_ms = e0.elapsed_time(e1) / 5
+        factors = [res.history[i + 1] / res.history[i] for i in range(1, len(res.history) - 1)]
+        row = {"cycles": res.outer, "seconds": round(mg_s, 4), "ms_per_cycle": round(cycle_ms, 3),
+               "levels": mg.depth, "rel_residual_gpu": res.rel_residual, "converged": res.converged,
+               "mean_factor_per_cycle": float(np.exp(np.mean(np.log(factors)))) if factors else None}
+        if not a.no_cpu_baseline:
+            from oracle import oracle as O
+            u.zero_()
+            res2 = mg.solve(tol, max_cycles=100)
+            torch.cuda.synchronize()
+            nr = O.residual(u.detach().cpu().numpy(), b.detach().cpu().numpy(), dim=3,
+                            stencil=O.FD if st == C.CS_FD else O.Q1, h=h)
+            row["rel_residual_oracle_fp64"] = float(nr[0] / nr[2])
+            row["oracle_cycles"] = res2.outer
+        mg.close()
+        if a.mg_gs_compare:
+            u2 = C.empty_grid(n3)
+            tmp = C.grid_like(u2)
+            g2 = C.Grid(u2, b, dim=3, stencil=st, h=h)
+            torch.cuda.synchronize()
+            say("%s: coloured sweeps alone to %.0e" % (name, tol))
+            t0 = time.perf_counter()
+            gs = S.gs_solve(g2, tol, check_every=1000, tmp=tmp, progress=progress)
+            torch.cuda.synchronize()
+            gs_s = time.perf_counter() - t0
+            row["gs_alone"] = {"seconds": round(gs_s, 3), "sweeps": gs.sweeps,
+                               "rel_residual_gpu": gs.rel_residual, "converged": gs.converged}
+            row["speedup_vs_gs"] = round(gs_s / mg_s, 1)
+            g2.close()
+            del u2, tmp
+        rows[name] = row
+        g.close()
+        del u, b
+        torch.cuda.empty_cache()
+    total = rows["fd7"]["seconds"] + rows["q1_27"]["seconds"]
+    out = {
+        "metric": "seconds to 1e-10 relative residual, multigrid V(2,2) with the coloured "
+                  "Gauss-Seidel smoother (7-point and 27-point solves)",
+        "value": round(total, 4), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(total * 1e3, 2), "higher_is_better": False, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "3D Poisson %d^3, h=1/%d, uniform[-1,1) RHS (seed 2), u0=0; V(2,2)-"
+                               "cycles, full weighting, d-linear interpolation, %d levels to one "
+                               "point, 2 sweeps on the coarsest; tol 1e-10" % (n, n + 1, rows["fd7"]["levels"])},
+        "rows": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 EXPENSIVE_CASES = (
     # name, dim, stencil, interior n (x first), kmax, hetero
     ("fd5_2d_k100", 2, 0, (2048, 2048), 100, 0),
@@ -712,6 +822,8 @@ def main():
         run_patches(a)
     elif a.workload == "refine":
         run_refine(a)
+    elif a.workload == "multigrid":
+        run_multigrid(a)
     elif a.workload == "serve":
         run_serve(a)
     elif a.workload == "expensive":

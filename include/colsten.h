@@ -183,6 +183,34 @@ cs_status cs_apply(cs_grid g, void* y, int32_t cellwise, void* stream);
  * same data give identical bits.  FP32 grids are evaluated in FP64. */
 cs_status cs_residual(cs_grid g, void* r, double* norms, void* stream);
 
+/* ---- Multigrid grid transfers -------------------------------------------
+ * A geometric multigrid V-cycle whose smoother is the coloured Gauss-Seidel
+ * sweep (the paper names multigrid as the setting its smoothers serve,
+ * Sec. 1).  fine and coarse are grids of the same dim, stencil and dtype with
+ * fine n = 2 * coarse n + 1 along every axis; fine index i = 2 I lies on
+ * coarse index I (vertex-centred), so the coarse halo lies on the fine halo.
+ * The coarse grid carries the correction equation A_2h e = R r: its h is
+ * expected to be twice the fine h (not checked; the transfers do not use h).
+ *
+ * cs_restrict: coarse.b <- R r by full weighting at every coarse interior
+ *   point, sum over o in {-1,0,1}^d of prod_m w(o_m) r(2I + o), w(0) = 1/2,
+ *   w(+-1) = 1/4, in lexicographic (oz, oy, ox) order with one fused
+ *   multiply-add per term; coarse.u <- 0 at the same points (halos
+ *   untouched).  r: device array with fine u's layout and dtype (e.g. the r
+ *   of cs_residual), read at fine interior points only; it must not be
+ *   fine.u or one of coarse's arrays.  coarse.b is written although the grid
+ *   otherwise only reads b.
+ * cs_prolong_add: fine.u <- fine.u + P coarse.u at every fine interior point,
+ *   P the d-linear interpolation: the 1, 2, 4 or 8 coarse values around i / 2
+ *   (coarse halo included, so the halo of a correction must hold zeros),
+ *   weighted 1 or 1/2 per axis, summed in increasing (cz, cy, cx) order with
+ *   one fused multiply-add per term, then one addition.
+ * Both are deterministic; both ask nothing of the grids' colouring parity.
+ * Errors: CS_EINVAL for mismatched grids or sizes, arrays shared between the
+ * two grids, or a bad r. */
+cs_status cs_restrict(cs_grid fine, const void* r, cs_grid coarse, void* stream);
+cs_status cs_prolong_add(cs_grid coarse, cs_grid fine, void* stream);
+
 /* ---- FP32 sweeps inside FP64 iterative refinement ----------------------
  * g64: an FP64 grid whose u holds the iterate x and whose b is the right-hand
  * side.  g32: an FP32 grid of the same dim, stencil, parity, n and h (its own

@@ -71,6 +71,8 @@ _SIGS = {
     "cs_ir_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
                                       ctypes.c_void_p]),
     "cs_ir_update": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]),
+    "cs_restrict": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cs_prolong_add": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "cs_batch_create": (ctypes.c_int, [ctypes.POINTER(cs_grid_desc), ctypes.POINTER(ctypes.c_void_p),
                                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
@@ -222,6 +224,26 @@ def cs_ir_residual(h64, h32, scale, norms_ptr, stream=None):
 
 def cs_ir_update(h64, h32, scale, stream=None):
     _check(lib().cs_ir_update(ctypes.c_void_p(h64), ctypes.c_void_p(h32), float(scale), _stream(stream)))
+
+
+def cs_restrict(h_fine, r_ptr, h_coarse, stream=None):
+    _check(lib().cs_restrict(ctypes.c_void_p(h_fine), ctypes.c_void_p(r_ptr), ctypes.c_void_p(h_coarse),
+                             _stream(stream)))
+
+
+def cs_prolong_add(h_coarse, h_fine, stream=None):
+    _check(lib().cs_prolong_add(ctypes.c_void_p(h_coarse), ctypes.c_void_p(h_fine), _stream(stream)))
+
+
+def restrict(fine, r, coarse, stream=None):
+    """coarse.b <- full weighting of r (fine layout) and coarse.u <- 0, at the
+    coarse interior."""
+    cs_restrict(fine.handle, r.data_ptr(), coarse.handle, stream)
+
+
+def prolong_add(coarse, fine, stream=None):
+    """fine.u <- fine.u + d-linear interpolation of coarse.u (halo included)."""
+    cs_prolong_add(coarse.handle, fine.handle, stream)
 
 
 def cs_batch_create(descs, u_ptrs, b_ptrs, tmp_ptrs):

@@ -459,6 +459,53 @@ cs_status cs_residual(cs_grid g, void* r, double* norms, void* stream)
                            g->d.h * g->d.h, g->partials, norms, (hipStream_t)stream);
 }
 
+// A fine and a coarse grid of one multigrid hierarchy: same dim, stencil and
+// dtype, fine n = 2 coarse n + 1 along every axis of the grid.
+static cs_status check_mg_pair(cs_grid fine, cs_grid coarse)
+{
+    cs_status st = check_grid(fine);
+    if (st != CS_OK) return st;
+    if ((st = check_grid(coarse)) != CS_OK) return st;
+    if (fine->d.dim != coarse->d.dim || fine->d.stencil != coarse->d.stencil ||
+        fine->d.dtype != coarse->d.dtype) {
+        set_error("multigrid grids differ in dim, stencil or dtype");
+        return CS_EINVAL;
+    }
+    for (int a = 0; a < fine->d.dim; ++a)
+        if (fine->d.n[a] != 2 * coarse->d.n[a] + 1) {
+            set_error("fine n[%d] = %lld is not 2 * coarse n + 1 (coarse n = %lld)", a,
+                      (long long)fine->d.n[a], (long long)coarse->d.n[a]);
+            return CS_EINVAL;
+        }
+    if (fine->u == coarse->u || fine->u == coarse->b || (const void*)coarse->u == fine->b) {
+        set_error("multigrid grids share an array");
+        return CS_EINVAL;
+    }
+    return CS_OK;
+}
+
+cs_status cs_restrict(cs_grid fine, const void* r, cs_grid coarse, void* stream)
+{
+    cs_status st = check_mg_pair(fine, coarse);
+    if (st != CS_OK) return st;
+    if (r == coarse->u || r == coarse->b || r == fine->u) {
+        set_error("r must be a separate array");
+        return CS_EINVAL;
+    }
+    if ((st = check_device_range(r, (size_t)fine->span * fine->elem, fine->elem, "r")) != CS_OK)
+        return st;
+    return launch_restrict(fine->d.dtype, fine->d.dim, fine->geo, r, coarse->geo,
+                           const_cast<void*>(coarse->b), coarse->u, (hipStream_t)stream);
+}
+
+cs_status cs_prolong_add(cs_grid coarse, cs_grid fine, void* stream)
+{
+    cs_status st = check_mg_pair(fine, coarse);
+    if (st != CS_OK) return st;
+    return launch_prolong_add(fine->d.dtype, fine->d.dim, coarse->geo, coarse->u, fine->geo,
+                              fine->u, (hipStream_t)stream);
+}
+
 static cs_status check_ir_pair(cs_grid g64, cs_grid g32, double scale)
 {
     cs_status st = check_grid(g64);

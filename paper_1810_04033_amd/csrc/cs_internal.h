@@ -114,6 +114,16 @@ cs_status launch_residual3_stream(int dtype, int stencil, const Geo& g, const vo
 
 }  // namespace cs
 
+namespace cs {
+// Multigrid transfers (k_mg.hip): full weighting of the fine residual r into
+// the coarse b (and zero into the coarse u), d-linear interpolation of the
+// coarse u added to the fine u.
+cs_status launch_restrict(int dtype, int dim, const Geo& gf, const void* r, const Geo& gc,
+                          void* bc, void* uc, hipStream_t s);
+cs_status launch_prolong_add(int dtype, int dim, const Geo& gc, const void* uc, const Geo& gf,
+                             void* uf, hipStream_t s);
+}  // namespace cs
+
 struct cs_grid_s {
     cs_grid_desc d;
     cs::Geo geo;

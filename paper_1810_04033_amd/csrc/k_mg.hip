@@ -1,0 +1,147 @@
+// Grid transfers of a geometric multigrid V-cycle whose smoother is the
+// coloured Gauss-Seidel sweep (the paper names multigrid as the setting its
+// smoothers serve, Sec. 1).  Vertex-centred grids: a fine grid has
+// n_f = 2 n_c + 1 interior points per axis and fine index i = 2 I lies on
+// coarse index I, so the coarse halo lies on the fine halo.
+//
+// Restriction by full weighting: at every coarse interior point the 3^d fine
+// residuals around 2I, weighted 1/2 on the axis and 1/4 off it per axis, are
+// summed in lexicographic (oz, oy, ox) order with one fused multiply-add each;
+// the coarse iterate is set to zero at the same point (zero initial guess of
+// the coarse correction).  Interpolation: at every fine interior point the
+// 1, 2, 4 or 8 coarse values around i/2 (coarse halo included), weighted 1 or
+// 1/2 per axis, summed in increasing (cz, cy, cx) order with one fused
+// multiply-add each, then added to the fine iterate.  All weights are powers
+// of two, so the weight products are exact; one thread per output point, rows
+// of 64 points per wavefront.  Each output is a plain function of its inputs,
+// so the transfers are deterministic.
+#include "cs_device.h"
+#include "cs_internal.h"
+
+namespace cs {
+
+namespace {
+
+constexpr int kMX = 64;  // points along x (one wavefront)
+constexpr int kMY = 4;   // rows per block
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kMX* kMY)
+k_restrict(const T* __restrict__ r, Geo gf, T* __restrict__ bc, T* __restrict__ uc, Geo gc,
+           int64_t xblocks)
+{
+    const int64_t bid = blockIdx.x;
+    const int64_t xb = bid % xblocks;
+    const int64_t row = (bid / xblocks) * kMY + threadIdx.y;
+    if (row >= gc.ny * gc.nz) return;
+    const int64_t J = 1 + row % gc.ny;
+    const int64_t K = 1 + row / gc.ny;
+    const int64_t I = 1 + xb * kMX + threadIdx.x;
+    if (I > gc.nx) return;
+    const int64_t qf = (DIM == 3 ? 2 * K * gf.sz : 0) + 2 * J * gf.sy + 2 * I;
+    constexpr int ZR = DIM == 3 ? 1 : 0;
+    T acc = T(0);
+#pragma unroll
+    for (int oz = -ZR; oz <= ZR; ++oz)
+#pragma unroll
+        for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+            for (int ox = -1; ox <= 1; ++ox) {
+                const T wz = DIM == 3 ? (oz == 0 ? T(0.5) : T(0.25)) : T(1);
+                const T w = wz * (oy == 0 ? T(0.5) : T(0.25)) * (ox == 0 ? T(0.5) : T(0.25));
+                acc = fma_t(w, r[qf + oz * gf.sz + oy * gf.sy + ox], acc);
+            }
+    const int64_t qc = (DIM == 3 ? K * gc.sz : 0) + J * gc.sy + I;
+    bc[qc] = acc;
+    uc[qc] = T(0);
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kMX* kMY)
+k_prolong_add(const T* __restrict__ uc, Geo gc, T* __restrict__ uf, Geo gf, int64_t xblocks)
+{
+    const int64_t bid = blockIdx.x;
+    const int64_t xb = bid % xblocks;
+    const int64_t row = (bid / xblocks) * kMY + threadIdx.y;
+    if (row >= gf.ny * gf.nz) return;
+    const int64_t j = 1 + row % gf.ny;
+    const int64_t k = 1 + row / gf.ny;
+    const int64_t i = 1 + xb * kMX + threadIdx.x;
+    if (i > gf.nx) return;
+    // coarse neighbours along an axis: t/2, and t/2 + 1 when t is odd
+    const int nkz = DIM == 3 ? 1 + (int)(k & 1) : 1;
+    const int nky = 1 + (int)(j & 1), nkx = 1 + (int)(i & 1);
+    const T wz = (DIM == 3 && (k & 1)) ? T(0.5) : T(1);
+    const T wy = (j & 1) ? T(0.5) : T(1), wx = (i & 1) ? T(0.5) : T(1);
+    const T w = wz * wy * wx;
+    const int64_t c0 = (DIM == 3 ? (k / 2) * gc.sz : 0) + (j / 2) * gc.sy + i / 2;
+    T acc = T(0);
+    for (int a = 0; a < nkz; ++a)
+        for (int bb = 0; bb < nky; ++bb)
+            for (int c = 0; c < nkx; ++c)
+                acc = fma_t(w, uc[c0 + a * gc.sz + bb * gc.sy + c], acc);
+    const int64_t q = (DIM == 3 ? k * gf.sz : 0) + j * gf.sy + i;
+    uf[q] = uf[q] + acc;
+}
+
+// blocks of kMX x kMY points over the interior rows of g
+bool row_blocks(const Geo& g, int64_t* xblocks, int64_t* blocks)
+{
+    *xblocks = (g.nx + kMX - 1) / kMX;
+    *blocks = *xblocks * ((g.ny * g.nz + kMY - 1) / kMY);
+    return *blocks <= 0x7fffffff;
+}
+
+}  // namespace
+
+cs_status launch_restrict(int dtype, int dim, const Geo& gf, const void* r, const Geo& gc,
+                          void* bc, void* uc, hipStream_t s)
+{
+    int64_t xblocks = 0, blocks = 0;
+    if (!row_blocks(gc, &xblocks, &blocks)) { set_error("restrict: grid too large"); return CS_EUNSUPPORTED; }
+    if (blocks == 0) return CS_OK;
+    const dim3 grid((unsigned)blocks), block(kMX, kMY);
+    if (dtype == 0) {
+        if (dim == 3)
+            hipLaunchKernelGGL((k_restrict<double, 3>), grid, block, 0, s, (const double*)r, gf,
+                               (double*)bc, (double*)uc, gc, xblocks);
+        else
+            hipLaunchKernelGGL((k_restrict<double, 2>), grid, block, 0, s, (const double*)r, gf,
+                               (double*)bc, (double*)uc, gc, xblocks);
+    } else {
+        if (dim == 3)
+            hipLaunchKernelGGL((k_restrict<float, 3>), grid, block, 0, s, (const float*)r, gf,
+                               (float*)bc, (float*)uc, gc, xblocks);
+        else
+            hipLaunchKernelGGL((k_restrict<float, 2>), grid, block, 0, s, (const float*)r, gf,
+                               (float*)bc, (float*)uc, gc, xblocks);
+    }
+    return check_launch("restriction");
+}
+
+cs_status launch_prolong_add(int dtype, int dim, const Geo& gc, const void* uc, const Geo& gf,
+                             void* uf, hipStream_t s)
+{
+    int64_t xblocks = 0, blocks = 0;
+    if (!row_blocks(gf, &xblocks, &blocks)) { set_error("interpolation: grid too large"); return CS_EUNSUPPORTED; }
+    if (blocks == 0) return CS_OK;
+    const dim3 grid((unsigned)blocks), block(kMX, kMY);
+    if (dtype == 0) {
+        if (dim == 3)
+            hipLaunchKernelGGL((k_prolong_add<double, 3>), grid, block, 0, s, (const double*)uc, gc,
+                               (double*)uf, gf, xblocks);
+        else
+            hipLaunchKernelGGL((k_prolong_add<double, 2>), grid, block, 0, s, (const double*)uc, gc,
+                               (double*)uf, gf, xblocks);
+    } else {
+        if (dim == 3)
+            hipLaunchKernelGGL((k_prolong_add<float, 3>), grid, block, 0, s, (const float*)uc, gc,
+                               (float*)uf, gf, xblocks);
+        else
+            hipLaunchKernelGGL((k_prolong_add<float, 2>), grid, block, 0, s, (const float*)uc, gc,
+                               (float*)uf, gf, xblocks);
+    }
+    return check_launch("interpolation");
+}
+
+}  // namespace cs
