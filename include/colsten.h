@@ -105,7 +105,12 @@ cs_status cs_colour_pass(cs_grid g, int32_t colour, void* stream);
  * passes, rounded identically): one or two sweeps per pass on 3D grids, up to
  * four on 2D grids (see cs_grid_set_pass_mode).  The halo of u_tmp is
  * overwritten with u's halo, and the result ends in u.  Without u_tmp, each
- * sweep is c in-place colour passes.  nsweeps == 0 is a no-op.
+ * sweep is c in-place colour passes.  In the automatic pass mode small 3D
+ * grids take faster schedules of the same iterate whatever u_tmp is: up to
+ * 4096 points every sweep runs in one workgroup with a workgroup barrier
+ * after each colour (one launch in all), and 7-point grids of up to 1.1 M
+ * points run the in-place colour passes (u_tmp unused in both cases).
+ * nsweeps == 0 is a no-op.
  * Errors: CS_EINVAL (nsweeps < 0). */
 cs_status cs_gs_sweeps(cs_grid g, int32_t nsweeps, void* u_tmp, void* stream);
 
@@ -311,8 +316,10 @@ cs_status cs_gs_fused(cs_grid g, int32_t* out);
  * single sweeps: a schedule of the same computation).
  *   CS_PASS_AUTO (default): two per pass for 3D Jacobi sweeps and, where the
  *     grid is large enough for it to be faster, for fused 3D red-black sweeps;
- *     one otherwise.  Fused 2D sweeps run up to 4 (red-black) or 2 (four
- *     colours) per pass.
+ *     one otherwise.  Where a red-black count would take an odd number of
+ *     passes, one double pass runs as two single ones, so that the iterate
+ *     ends in u without a copy (e.g. 2 sweeps: two single passes).  Fused 2D
+ *     sweeps run up to 4 (red-black) or 2 (four colours) per pass.
  *   CS_PASS_ONE: one sweep per pass.
  *   CS_PASS_TWO: as CS_PASS_AUTO, but two 3D sweeps per pass wherever a kernel
  *     for it exists (3D Jacobi, fused 3D red-black), whatever the grid size.

@@ -214,6 +214,25 @@ cs_status cs_num_colours(cs_grid g, int32_t* out)
 // cs_jacobi_sweeps pairs its sweeps, on this grid under its pass mode.  2D
 // grids take up to fused2d_max_sweeps sweeps per launch (an LDS-resident
 // tile), 3D red-black grids two.
+// Schedules of small 3D grids in the automatic mode, from sweep times on
+// MI355X (FP64, us per sweep, fused pass / one launch per colour / one
+// workgroup): 7^3 7-point 12.1 / 7.7 / 3.4, 15^3 22.0 / 7.6 / 5.3, 23^3 -- /
+// -- / 14.4, 63^3 17.4 / 7.6 / 273; 27-point 7^3 14.0 / 23.5 / 6.4, 15^3
+// 25.0 / 23.0 / 12.6, 63^3 21.4 / 23.0 / 514; at 127^3 the fused pass is
+// level with the colour launches (7-point) or ahead (27-point).  Up to 16^3
+// points every sweep runs in one workgroup; 7-point grids up to ~100^3 run one
+// launch per colour, in place.
+static bool block_sweeps_pay(cs_grid g)
+{
+    return g->d.dim == 3 && g->geo.nx * g->geo.ny * g->geo.nz <= 4096;
+}
+
+static bool colour_launches_pay(cs_grid g)
+{
+    return g->d.dim == 3 && g->d.stencil == CS_FD &&
+           g->geo.nx * g->geo.ny * g->geo.nz <= 1100000;
+}
+
 static int gs_per_pass(cs_grid g)
 {
     const int dt = g->d.dtype, dim = g->d.dim, sten = g->d.stencil;
@@ -281,18 +300,28 @@ cs_status cs_gs_sweeps(cs_grid g, int32_t nsweeps, void* u_tmp, void* stream)
     if (u_tmp) {
         if ((st = check_tmp(g, u_tmp)) != CS_OK) return st;
     }
-    if (u_tmp && fused_supported(dt, dim, sten, g->geo)) {
+    const bool automatic = g->pass_mode == CS_PASS_AUTO;
+    if (automatic && block_sweeps_pay(g))
+        return launch_block_sweeps(dt, dim, sten, g->geo, g->u, g->b, h2, nsweeps, s);
+    if (u_tmp && fused_supported(dt, dim, sten, g->geo) && !(automatic && colour_launches_pay(g))) {
         if ((st = launch_halo_copy(dt, dim, g->geo, g->u, u_tmp, s)) != CS_OK) return st;
         const void* src = g->u;
         void* dst = u_tmp;
         const int per = gs_per_pass(g);
+        // 3D: double sweeps first, then single ones.  An odd number of passes
+        // leaves the iterate in u_tmp and costs a copy back; in the automatic
+        // mode one double sweep then runs as two single passes instead, which
+        // is cheaper than the copy (at 256^3 FP64: 2 x 85 us against
+        // 131 + 56 us).
+        int32_t pairs = (dim == 3 && per == 2) ? nsweeps / 2 : 0;
+        if (g->pass_mode == CS_PASS_AUTO && pairs > 0 && ((pairs + (nsweeps - 2 * pairs)) & 1)) --pairs;
         for (int32_t it = 0; it < nsweeps;) {
             if (dim == 2) {
                 int sw = per;
                 while (sw > nsweeps - it) sw >>= 1;  // 8, 4, 2, 1
                 st = launch_fused2d(dt, sten, sw, g->geo, src, dst, g->b, h2, s);
                 it += sw;
-            } else if (per == 2 && nsweeps - it >= 2) {
+            } else if (it < 2 * pairs) {
                 st = launch_fused_two(dt, dim, sten, g->geo, src, dst, g->b, h2, s);
                 it += 2;
             } else {

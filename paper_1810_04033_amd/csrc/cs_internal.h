@@ -97,6 +97,10 @@ cs_status launch_ir_update(int dim, const Geo& g, void* x, const Geo& g2, const 
                            double scale, hipStream_t s);
 // Persistent colour sweeps with a device-wide barrier between colours
 // (k_sync.hip); bar: three zeroed words of device memory owned by the grid.
+// All sweeps of a small grid in one workgroup, a workgroup barrier per colour
+// (k_sync.hip); the iterate of the colour passes.
+cs_status launch_block_sweeps(int dtype, int dim, int stencil, const Geo& g, void* u,
+                              const void* b, double h2, int nsweeps, hipStream_t s);
 cs_status launch_sync_sweeps(int dtype, int dim, int stencil, const Geo& g, void* u,
                              const void* b, double h2, int nsweeps, unsigned* bar, hipStream_t s);
 // z-streaming Jacobi and residual for 3D grids (k_stream.hip).

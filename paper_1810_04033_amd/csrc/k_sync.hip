@@ -89,6 +89,35 @@ __device__ inline ColourSet colour_set(const Geo& g, int c)
 
 constexpr int kSyncThreads = 1024;
 
+// The points of colour c taken by thread tid of nthreads, each set to its
+// colour-pass value in place (the same update as the one-launch-per-colour
+// pass).
+template <typename T, int DIM, int ST>
+__device__ __forceinline__ void colour_points(T* u, const T* __restrict__ b, const Geo& g, T h2,
+                                              int c, int64_t tid, int64_t nthreads)
+{
+    const int64_t sy = g.sy, sz = g.sz;
+    const ColourSet cs = colour_set<DIM, ST>(g, c);
+    for (int64_t w = tid; w < cs.total; w += nthreads) {
+        const int64_t m = w % cs.cx, n = (w / cs.cx) % cs.cy, l = w / (cs.cx * cs.cy);
+        int64_t i, j, k;
+        if (ST == FD) {
+            j = 1 + n;
+            k = 1 + l;
+            const int64_t kk = DIM == 3 ? k - 1 : 0;
+            i = 1 + ((c + (j - 1) + kk + g.parity) & 1) + 2 * m;
+            if (i > g.nx) continue;
+        } else {
+            i = cs.i0 + 2 * m;
+            j = cs.j0 + 2 * n;
+            k = cs.k0 + 2 * l;
+        }
+        const int64_t q = (DIM == 3 ? k * sz : 0) + j * sy + i;
+        auto ld = [&](int ox, int oy, int oz) { return u[q + oz * sz + oy * sy + ox]; };
+        u[q] = gs_value<T, DIM, ST>(h2, b[q], ld);
+    }
+}
+
 template <typename T, int DIM, int ST>
 __global__ void __launch_bounds__(kSyncThreads)
 k_sync_sweeps(T* u, const T* __restrict__ b, Geo g, T h2, int nsweeps, unsigned* bar)
@@ -96,31 +125,43 @@ k_sync_sweeps(T* u, const T* __restrict__ b, Geo g, T h2, int nsweeps, unsigned*
     constexpr int NC = num_colours<ST, DIM>();
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t sy = g.sy, sz = g.sz;
     for (int sw = 0; sw < nsweeps; ++sw) {
         for (int c = 0; c < NC; ++c) {
-            const ColourSet cs = colour_set<DIM, ST>(g, c);
-            for (int64_t w = tid; w < cs.total; w += nthreads) {
-                const int64_t m = w % cs.cx, n = (w / cs.cx) % cs.cy, l = w / (cs.cx * cs.cy);
-                int64_t i, j, k;
-                if (ST == FD) {
-                    j = 1 + n;
-                    k = 1 + l;
-                    const int64_t kk = DIM == 3 ? k - 1 : 0;
-                    i = 1 + ((c + (j - 1) + kk + g.parity) & 1) + 2 * m;
-                    if (i > g.nx) continue;
-                } else {
-                    i = cs.i0 + 2 * m;
-                    j = cs.j0 + 2 * n;
-                    k = cs.k0 + 2 * l;
-                }
-                const int64_t q = (DIM == 3 ? k * sz : 0) + j * sy + i;
-                auto ld = [&](int ox, int oy, int oz) { return u[q + oz * sz + oy * sy + ox]; };
-                u[q] = gs_value<T, DIM, ST>(h2, b[q], ld);
-            }
+            colour_points<T, DIM, ST>(u, b, g, h2, c, tid, nthreads);
             grid_barrier(bar, gridDim.x);
         }
     }
+}
+
+// All sweeps of a small grid in one workgroup: the colours in order, a
+// workgroup barrier after each (the workgroup's global stores are visible to
+// its own threads after the barrier).  One launch instead of one per colour.
+constexpr int kBlockThreads = 1024;
+
+template <typename T, int DIM, int ST>
+__global__ void __launch_bounds__(kBlockThreads)
+k_block_sweeps(T* u, const T* __restrict__ b, Geo g, T h2, int nsweeps)
+{
+    constexpr int NC = num_colours<ST, DIM>();
+    for (int sw = 0; sw < nsweeps; ++sw)
+        for (int c = 0; c < NC; ++c) {
+            colour_points<T, DIM, ST>(u, b, g, h2, c, threadIdx.x, blockDim.x);
+            __syncthreads();
+        }
+}
+
+template <typename T, int DIM, int ST>
+cs_status block_sweeps_t(const Geo& g, void* u, const void* b, double h2, int nsweeps,
+                         hipStream_t s)
+{
+    // threads: about one per point of the largest colour, whole wavefronts
+    const int64_t pts = g.nx * g.ny * (DIM == 3 ? g.nz : 1);
+    int64_t nt = (pts / 2 + 63) / 64 * 64;
+    if (nt > kBlockThreads) nt = kBlockThreads;
+    if (nt < 64) nt = 64;
+    hipLaunchKernelGGL((k_block_sweeps<T, DIM, ST>), dim3(1), dim3((unsigned)nt), 0, s, (T*)u,
+                       (const T*)b, g, (T)h2, nsweeps);
+    return check_launch("one-workgroup sweeps");
 }
 
 template <typename T, int DIM, int ST>
@@ -159,6 +200,23 @@ cs_status sync_sweeps_t(const Geo& g, void* u, const void* b, double h2, int nsw
 }
 
 }  // namespace
+
+cs_status launch_block_sweeps(int dtype, int dim, int stencil, const Geo& g, void* u,
+                              const void* b, double h2, int nsweeps, hipStream_t s)
+{
+    if (dtype == 0) {
+        if (dim == 2)
+            return stencil == FD ? block_sweeps_t<double, 2, FD>(g, u, b, h2, nsweeps, s)
+                                 : block_sweeps_t<double, 2, Q1>(g, u, b, h2, nsweeps, s);
+        return stencil == FD ? block_sweeps_t<double, 3, FD>(g, u, b, h2, nsweeps, s)
+                             : block_sweeps_t<double, 3, Q1>(g, u, b, h2, nsweeps, s);
+    }
+    if (dim == 2)
+        return stencil == FD ? block_sweeps_t<float, 2, FD>(g, u, b, h2, nsweeps, s)
+                             : block_sweeps_t<float, 2, Q1>(g, u, b, h2, nsweeps, s);
+    return stencil == FD ? block_sweeps_t<float, 3, FD>(g, u, b, h2, nsweeps, s)
+                         : block_sweeps_t<float, 3, Q1>(g, u, b, h2, nsweeps, s);
+}
 
 cs_status launch_sync_sweeps(int dtype, int dim, int stencil, const Geo& g, void* u,
                              const void* b, double h2, int nsweeps, unsigned* bar, hipStream_t s)
