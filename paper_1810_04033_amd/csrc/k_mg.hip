@@ -27,17 +27,12 @@ constexpr int kMY = 4;   // rows per block
 
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kMX* kMY)
-k_restrict(const T* __restrict__ r, Geo gf, T* __restrict__ bc, T* __restrict__ uc, Geo gc,
-           int64_t xblocks)
+k_restrict(const T* __restrict__ r, Geo gf, T* __restrict__ bc, T* __restrict__ uc, Geo gc)
 {
-    const int64_t bid = blockIdx.x;
-    const int64_t xb = bid % xblocks;
-    const int64_t row = (bid / xblocks) * kMY + threadIdx.y;
-    if (row >= gc.ny * gc.nz) return;
-    const int64_t J = 1 + row % gc.ny;
-    const int64_t K = 1 + row / gc.ny;
-    const int64_t I = 1 + xb * kMX + threadIdx.x;
-    if (I > gc.nx) return;
+    const int64_t I = 1 + (int64_t)blockIdx.x * kMX + threadIdx.x;
+    const int64_t J = 1 + (int64_t)blockIdx.y * kMY + threadIdx.y;
+    const int64_t K = 1 + (int64_t)blockIdx.z;
+    if (I > gc.nx || J > gc.ny) return;
     const int64_t qf = (DIM == 3 ? 2 * K * gf.sz : 0) + 2 * J * gf.sy + 2 * I;
     constexpr int ZR = DIM == 3 ? 1 : 0;
     T acc = T(0);
@@ -58,16 +53,12 @@ k_restrict(const T* __restrict__ r, Geo gf, T* __restrict__ bc, T* __restrict__ 
 
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kMX* kMY)
-k_prolong_add(const T* __restrict__ uc, Geo gc, T* __restrict__ uf, Geo gf, int64_t xblocks)
+k_prolong_add(const T* __restrict__ uc, Geo gc, T* __restrict__ uf, Geo gf)
 {
-    const int64_t bid = blockIdx.x;
-    const int64_t xb = bid % xblocks;
-    const int64_t row = (bid / xblocks) * kMY + threadIdx.y;
-    if (row >= gf.ny * gf.nz) return;
-    const int64_t j = 1 + row % gf.ny;
-    const int64_t k = 1 + row / gf.ny;
-    const int64_t i = 1 + xb * kMX + threadIdx.x;
-    if (i > gf.nx) return;
+    const int64_t i = 1 + (int64_t)blockIdx.x * kMX + threadIdx.x;
+    const int64_t j = 1 + (int64_t)blockIdx.y * kMY + threadIdx.y;
+    const int64_t k = 1 + (int64_t)blockIdx.z;
+    if (i > gf.nx || j > gf.ny) return;
     // coarse neighbours along an axis: t/2, and t/2 + 1 when t is odd
     const int nkz = DIM == 3 ? 1 + (int)(k & 1) : 1;
     const int nky = 1 + (int)(j & 1), nkx = 1 + (int)(i & 1);
@@ -84,12 +75,13 @@ k_prolong_add(const T* __restrict__ uc, Geo gc, T* __restrict__ uf, Geo gf, int6
     uf[q] = uf[q] + acc;
 }
 
-// blocks of kMX x kMY points over the interior rows of g
-bool row_blocks(const Geo& g, int64_t* xblocks, int64_t* blocks)
+// blocks of kMX x kMY points of one plane, one grid layer per plane
+bool point_grid(const Geo& g, dim3* grid)
 {
-    *xblocks = (g.nx + kMX - 1) / kMX;
-    *blocks = *xblocks * ((g.ny * g.nz + kMY - 1) / kMY);
-    return *blocks <= 0x7fffffff;
+    const int64_t gx = (g.nx + kMX - 1) / kMX, gy = (g.ny + kMY - 1) / kMY, gz = g.nz;
+    if (gx > 0x7fffffff || gy > 65535 || gz > 65535) return false;
+    *grid = dim3((unsigned)gx, (unsigned)gy, (unsigned)gz);
+    return true;
 }
 
 }  // namespace
@@ -97,24 +89,23 @@ bool row_blocks(const Geo& g, int64_t* xblocks, int64_t* blocks)
 cs_status launch_restrict(int dtype, int dim, const Geo& gf, const void* r, const Geo& gc,
                           void* bc, void* uc, hipStream_t s)
 {
-    int64_t xblocks = 0, blocks = 0;
-    if (!row_blocks(gc, &xblocks, &blocks)) { set_error("restrict: grid too large"); return CS_EUNSUPPORTED; }
-    if (blocks == 0) return CS_OK;
-    const dim3 grid((unsigned)blocks), block(kMX, kMY);
+    dim3 grid;
+    if (!point_grid(gc, &grid)) { set_error("restrict: grid too large"); return CS_EUNSUPPORTED; }
+    const dim3 block(kMX, kMY);
     if (dtype == 0) {
         if (dim == 3)
             hipLaunchKernelGGL((k_restrict<double, 3>), grid, block, 0, s, (const double*)r, gf,
-                               (double*)bc, (double*)uc, gc, xblocks);
+                               (double*)bc, (double*)uc, gc);
         else
             hipLaunchKernelGGL((k_restrict<double, 2>), grid, block, 0, s, (const double*)r, gf,
-                               (double*)bc, (double*)uc, gc, xblocks);
+                               (double*)bc, (double*)uc, gc);
     } else {
         if (dim == 3)
             hipLaunchKernelGGL((k_restrict<float, 3>), grid, block, 0, s, (const float*)r, gf,
-                               (float*)bc, (float*)uc, gc, xblocks);
+                               (float*)bc, (float*)uc, gc);
         else
             hipLaunchKernelGGL((k_restrict<float, 2>), grid, block, 0, s, (const float*)r, gf,
-                               (float*)bc, (float*)uc, gc, xblocks);
+                               (float*)bc, (float*)uc, gc);
     }
     return check_launch("restriction");
 }
@@ -122,24 +113,23 @@ cs_status launch_restrict(int dtype, int dim, const Geo& gf, const void* r, cons
 cs_status launch_prolong_add(int dtype, int dim, const Geo& gc, const void* uc, const Geo& gf,
                              void* uf, hipStream_t s)
 {
-    int64_t xblocks = 0, blocks = 0;
-    if (!row_blocks(gf, &xblocks, &blocks)) { set_error("interpolation: grid too large"); return CS_EUNSUPPORTED; }
-    if (blocks == 0) return CS_OK;
-    const dim3 grid((unsigned)blocks), block(kMX, kMY);
+    dim3 grid;
+    if (!point_grid(gf, &grid)) { set_error("interpolation: grid too large"); return CS_EUNSUPPORTED; }
+    const dim3 block(kMX, kMY);
     if (dtype == 0) {
         if (dim == 3)
             hipLaunchKernelGGL((k_prolong_add<double, 3>), grid, block, 0, s, (const double*)uc, gc,
-                               (double*)uf, gf, xblocks);
+                               (double*)uf, gf);
         else
             hipLaunchKernelGGL((k_prolong_add<double, 2>), grid, block, 0, s, (const double*)uc, gc,
-                               (double*)uf, gf, xblocks);
+                               (double*)uf, gf);
     } else {
         if (dim == 3)
             hipLaunchKernelGGL((k_prolong_add<float, 3>), grid, block, 0, s, (const float*)uc, gc,
-                               (float*)uf, gf, xblocks);
+                               (float*)uf, gf);
         else
             hipLaunchKernelGGL((k_prolong_add<float, 2>), grid, block, 0, s, (const float*)uc, gc,
-                               (float*)uf, gf, xblocks);
+                               (float*)uf, gf);
     }
     return check_launch("interpolation");
 }
