@@ -2,7 +2,7 @@
 
 Each case copies the oracle's C source, plants one mistake (a dropped term, a
 wrong sign, a transposed index, a wrong colour, a misplaced weight, a wrong
-sweep order, a nonzero cost term), compiles the copy on the CPU and runs the
+sweep order, a nonzero cost term, a wrong multigrid transfer), compiles the copy on the CPU and runs the
 pin suites against it.  They have to fail.
 """
 import os
@@ -57,6 +57,24 @@ MUTANTS = {
     "cost_terms_not_zero": (
         "s = s + z * sin(",
         "s = s + (z + 1e-3) * sin("),
+    "restrict_centre_weight": (
+        "static double og_fw(int o) { return o == 0 ? 0.5 : 0.25; }",
+        "static double og_fw(int o) { return o == 0 ? 0.25 : 0.25; }"),
+    "restrict_shifted_block": (
+        "int64_t qf = (dim == 3 ? 2 * K * szf : 0) + 2 * J * syf + 2 * I;",
+        "int64_t qf = (dim == 3 ? 2 * K * szf : 0) + 2 * J * syf + 2 * I + 1;"),
+    "restrict_keeps_coarse_guess": (
+        "                bc[qc] = acc;\n                uc[qc] = 0.0;",
+        "                bc[qc] = acc;"),
+    "prolong_odd_weight": (
+        "wx = (i & 1) ? 0.5 : 1.0;",
+        "wx = (i & 1) ? 0.25 : 1.0;"),
+    "prolong_wrong_coarse_index": (
+        "(j / 2 + bb) * syc + i / 2 + c;",
+        "(j / 2 + bb) * syc + (i + 1) / 2 + c;"),
+    "correction_subtracted": (
+        "uf[q] = uf[q] + acc;",
+        "uf[q] = uf[q] - acc;"),
     "gs_skips_last_colour": (
         "        for (int c = 0; c < nc; ++c)\n            og_colour_pass_f64(",
         "        for (int c = 0; c < nc - 1; ++c)\n            og_colour_pass_f64("),
@@ -77,6 +95,7 @@ def test_pins_reject_mutant(name, tmp_path):
     env = dict(os.environ, COLSTEN_ORACLE_LIB=str(lib))
     proc = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                            os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                           os.path.join(ROOT, "tests", "test_oracle_cost.py")],
+                           os.path.join(ROOT, "tests", "test_oracle_cost.py"),
+                           os.path.join(ROOT, "tests", "test_oracle_mg.py")],
                           cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert proc.returncode != 0, "the pins accepted mutant %s:\n%s" % (name, proc.stdout[-2000:])
