@@ -59,18 +59,30 @@ k_prolong_add(const T* __restrict__ uc, Geo gc, T* __restrict__ uf, Geo gf)
     const int64_t j = 1 + (int64_t)blockIdx.y * kMY + threadIdx.y;
     const int64_t k = 1 + (int64_t)blockIdx.z;
     if (i > gf.nx || j > gf.ny) return;
-    // coarse neighbours along an axis: t/2, and t/2 + 1 when t is odd
-    const int nkz = DIM == 3 ? 1 + (int)(k & 1) : 1;
-    const int nky = 1 + (int)(j & 1), nkx = 1 + (int)(i & 1);
-    const T wz = (DIM == 3 && (k & 1)) ? T(0.5) : T(1);
-    const T wy = (j & 1) ? T(0.5) : T(1), wx = (i & 1) ? T(0.5) : T(1);
-    const T w = wz * wy * wx;
+    // coarse neighbours along an axis: t/2, and t/2 + 1 when t is odd.  All
+    // 2^d candidates (t/2 + 1 <= n_c + 1 stays inside the coarse array) are
+    // loaded at once, and only the neighbours enter the ordered sum.
+    const bool oz = DIM == 3 && (k & 1), oy = (j & 1) != 0, ox = (i & 1) != 0;
+    const T w = (oz ? T(0.5) : T(1)) * (oy ? T(0.5) : T(1)) * (ox ? T(0.5) : T(1));
     const int64_t c0 = (DIM == 3 ? (k / 2) * gc.sz : 0) + (j / 2) * gc.sy + i / 2;
+    constexpr int NZ = DIM == 3 ? 2 : 1;
+    T v[NZ][2][2];
+#pragma unroll
+    for (int a = 0; a < NZ; ++a)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) v[a][bb][c] = uc[c0 + a * gc.sz + bb * gc.sy + c];
     T acc = T(0);
-    for (int a = 0; a < nkz; ++a)
-        for (int bb = 0; bb < nky; ++bb)
-            for (int c = 0; c < nkx; ++c)
-                acc = fma_t(w, uc[c0 + a * gc.sz + bb * gc.sy + c], acc);
+#pragma unroll
+    for (int a = 0; a < NZ; ++a)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const bool in = (a == 0 || oz) && (bb == 0 || oy) && (c == 0 || ox);
+                acc = in ? fma_t(w, v[a][bb][c], acc) : acc;
+            }
     const int64_t q = (DIM == 3 ? k * gf.sz : 0) + j * gf.sy + i;
     uf[q] = uf[q] + acc;
 }

@@ -2,8 +2,8 @@
 
 Each case copies the oracle's C source, plants one mistake (a dropped term, a
 wrong sign, a transposed index, a wrong colour, a misplaced weight, a wrong
-sweep order, a nonzero cost term, a wrong multigrid transfer), compiles the copy on the CPU and runs the
-pin suites against it.  They have to fail.
+sweep order, a nonzero cost term, a wrong multigrid transfer), compiles the
+copy on the CPU and runs the pin suites against it.  They have to fail.
 """
 import os
 import subprocess
