@@ -184,8 +184,10 @@ cs_status cs_apply(cs_grid g, void* y, int32_t cellwise, void* stream);
 /* Residual r_q = b_q - (S u)_q / h^2 over the interior.  r: NULL or a device
  * array with u's layout and dtype (halo untouched).  norms: device pointer to
  * 3 doubles receiving ||r||_2, max |r| and ||b||_2 (unweighted sums over
- * interior points).  The reduction order is fixed, so repeated calls on the
- * same data give identical bits.  FP32 grids are evaluated in FP64. */
+ * interior points), or NULL when only r is wanted (the final reduction is then
+ * skipped).  The reduction order is fixed, so repeated calls on the same data
+ * give identical bits.  FP32 grids are evaluated in FP64.
+ * Errors: CS_EINVAL when r and norms are both NULL or either is bad. */
 cs_status cs_residual(cs_grid g, void* r, double* norms, void* stream);
 
 /* ---- Multigrid grid transfers -------------------------------------------

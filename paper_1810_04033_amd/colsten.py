@@ -410,8 +410,14 @@ class Grid:
     def jacobi(self, omega, nsweeps, tmp, stream=None):
         cs_jacobi_sweeps(self.handle, omega, nsweeps, tmp.data_ptr(), stream)
 
-    def residual(self, r=None, norms=None, stream=None):
-        """Enqueue the residual; returns the device tensor of the 3 norms."""
+    def residual(self, r=None, norms=None, stream=None, want_norms=True):
+        """Enqueue the residual; returns the device tensor of the 3 norms
+        (None with want_norms=False, which only fills r)."""
+        if not want_norms:
+            if r is None:
+                raise ValueError("want_norms=False needs r")
+            cs_residual(self.handle, r.data_ptr(), 0, stream)
+            return None
         out = self.norms if norms is None else norms
         cs_residual(self.handle, 0 if r is None else r.data_ptr(), out.data_ptr(), stream)
         return out

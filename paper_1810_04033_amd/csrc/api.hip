@@ -478,7 +478,8 @@ cs_status cs_residual(cs_grid g, void* r, double* norms, void* stream)
 {
     cs_status st = check_grid(g);
     if (st != CS_OK) return st;
-    if ((st = check_device_range(norms, 3 * sizeof(double), sizeof(double), "norms")) != CS_OK)
+    if (!norms && !r) { set_error("neither r nor norms given"); return CS_EINVAL; }
+    if (norms && (st = check_device_range(norms, 3 * sizeof(double), sizeof(double), "norms")) != CS_OK)
         return st;
     if (r) {
         if (r == g->u || r == g->b) { set_error("r must be a separate array"); return CS_EINVAL; }

@@ -595,6 +595,7 @@ cs_status launch_ir_update(int dim, const Geo& g, void* x, const Geo& g2, const 
 
 cs_status launch_residual_finish(const Partial* partials, int count, double* norms, hipStream_t s)
 {
+    if (!norms) return CS_OK;  // the residual array alone was asked for
     hipLaunchKernelGGL(k_residual_finish, dim3(1), dim3(256), 0, s, partials, count, norms);
     return check_launch("residual finish");
 }

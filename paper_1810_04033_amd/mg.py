@@ -60,7 +60,7 @@ class Multigrid:
         lv = self.levels
         for a, b in zip(lv[:-1], lv[1:]):
             a.grid.gs(self.nu1, tmp=a.tmp, stream=stream)
-            a.grid.residual(r=a.r, stream=stream)
+            a.grid.residual(r=a.r, stream=stream, want_norms=False)
             C.restrict(a.grid, a.r, b.grid, stream)
         lv[-1].grid.gs(self.coarse_sweeps, tmp=lv[-1].tmp, stream=stream)
         for a, b in zip(reversed(lv[:-1]), reversed(lv[1:])):

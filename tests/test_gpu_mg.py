@@ -128,4 +128,19 @@ def test_argument_checks():
         C.restrict(gf, f_u, gc)
     C.restrict(gf, r, gc)
     C.prolong_add(gc, gf)
+    with pytest.raises(C.ColstenError):  # residual with neither r nor norms
+        C.cs_residual(gf.handle, 0, 0)
     torch.cuda.synchronize()
+
+
+def test_residual_array_without_norms_bitwise():
+    n = (33, 17, 9)
+    u, b = G.case(3, n, seed=2600)
+    h = 1.0 / 34
+    _, want = O.residual(u, b, dim=3, stencil=O.FD, h=h, want_r=True)
+    ug, bg = G.upload(u), G.upload(b)
+    g = C.Grid(ug, bg, dim=3, stencil=C.CS_FD, h=h)
+    r = C.grid_like(ug)
+    assert g.residual(r=r, want_norms=False) is None
+    torch.cuda.synchronize()
+    assert np.array_equal(O.interior(G.download(r)), O.interior(want))
