@@ -542,8 +542,25 @@ def run_multigrid(a):
         e1.record(stream)
         torch.cuda.synchronize()
         cycle_ms = e0.elapsed_time(e1) / 5
+        mg.capture()
+        mg.cycle_graph()
+        e0.record(stream)
+        for _ in range(5):
+            mg.cycle_graph()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        cycle_graph_ms = e0.elapsed_time(e1) / 5
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        resg = mg.solve(tol, max_cycles=100, graph=True)
+        torch.cuda.synchronize()
+        mg_graph_s = time.perf_counter() - t0
+        say("%s: captured cycles, %d cycles, %.3f s" % (name, resg.outer, mg_graph_s))
         factors = [res.history[i + 1] / res.history[i] for i in range(1, len(res.history) - 1)]
         row = {"cycles": res.outer, "seconds": round(mg_s, 4), "ms_per_cycle": round(cycle_ms, 3),
+               "seconds_graph": round(mg_graph_s, 4), "ms_per_cycle_graph": round(cycle_graph_ms, 3),
+               "cycles_graph": resg.outer,
                "levels": mg.depth, "rel_residual_gpu": res.rel_residual, "converged": res.converged,
                "mean_factor_per_cycle": float(np.exp(np.mean(np.log(factors)))) if factors else None}
         if not a.no_cpu_baseline:

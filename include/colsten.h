@@ -302,6 +302,18 @@ cs_status cs_graph_gs(cs_grid g, int32_t nsweeps, void* u_tmp, int32_t lexicogra
 /* Record cs_batch_gs_sweeps(bt, nsweeps). */
 cs_status cs_graph_batch_gs(cs_batch bt, int32_t nsweeps, cs_graph* out);
 
+/* Record any sequence of library calls (e.g. a multigrid V-cycle):
+ * cs_graph_begin returns a private stream of the library that is capturing
+ * (thread-local mode); the caller enqueues library calls on it from the same
+ * thread, then cs_graph_end stops the capture, releases the stream and
+ * instantiates the graph.  Only the library's own calls belong in between (they
+ * record kernel nodes only); their arrays must stay allocated until
+ * cs_graph_destroy.  A call that fails in between still needs cs_graph_end,
+ * which then reports CS_EHIP if the capture was invalidated.
+ * Errors: CS_EINVAL (NULL arguments, a stream that is not capturing), CS_EHIP. */
+cs_status cs_graph_begin(void** capture_stream);
+cs_status cs_graph_end(void* capture_stream, cs_graph* out);
+
 /* Enqueue one replay on stream (same device as the capture). */
 cs_status cs_graph_launch(cs_graph gr, void* stream);
 

@@ -85,6 +85,8 @@ _SIGS = {
     "cs_graph_gs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_void_p)]),
     "cs_graph_batch_gs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+    "cs_graph_begin": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p)]),
+    "cs_graph_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "cs_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "cs_graph_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "cs_last_error": (ctypes.c_char_p, []),
@@ -443,6 +445,23 @@ class Graph:
         h = ctypes.c_void_p()
         _check(lib().cs_graph_batch_gs(ctypes.c_void_p(batch.handle), int(nsweeps), ctypes.byref(h)))
         return cls(h.value, (batch,))
+
+    @classmethod
+    def record(cls, enqueue, keep=()):
+        """Capture the library calls enqueue(stream) makes on the capture
+        stream it is given (a raw stream handle); keep: objects whose arrays
+        the graph uses."""
+        s = ctypes.c_void_p()
+        _check(lib().cs_graph_begin(ctypes.byref(s)))
+        h = ctypes.c_void_p()
+        try:
+            enqueue(s.value)
+        except BaseException:
+            if lib().cs_graph_end(s, ctypes.byref(h)) == CS_OK and h.value:
+                lib().cs_graph_destroy(h)
+            raise
+        _check(lib().cs_graph_end(s, ctypes.byref(h)))
+        return cls(h.value, keep)
 
     def launch(self, stream=None):
         _check(lib().cs_graph_launch(ctypes.c_void_p(self.handle), _stream(stream)))

@@ -1,5 +1,7 @@
-// Captured sweep sequences: a fixed number of sweeps of one grid or one batch
-// recorded once into a HIP graph and replayed with a single launch call,
+// Captured sweep sequences: a fixed number of sweeps of one grid or one batch,
+// or any sequence of library calls the caller enqueues between cs_graph_begin
+// and cs_graph_end, recorded once into a HIP graph and replayed with a single
+// launch call,
 // which removes the per-kernel launch cost that dominates small grids, the
 // one-launch-per-colour passes and the hyperplane wavefronts.  Only kernel
 // nodes are recorded (the sweep paths issue no memset or copy calls).
@@ -18,30 +20,42 @@ namespace {
 using cs::hip_fail;
 using cs::set_error;
 
-template <typename F>
-cs_status capture(F&& record, cs_graph* out)
+// Start a thread-local capture on a fresh non-blocking stream of the library.
+cs_status begin_capture(hipStream_t* out)
 {
-    if (!out) { set_error("NULL output handle"); return CS_EINVAL; }
     *out = nullptr;
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     hipStream_t cs_stream = nullptr;
-    if ((e = hipStreamCreateWithFlags(&cs_stream, hipStreamNonBlocking)) != hipSuccess)
-        return hip_fail(e, "hipStreamCreateWithFlags");
+    hipError_t e = hipStreamCreateWithFlags(&cs_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
     if ((e = hipStreamBeginCapture(cs_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
         (void)hipStreamDestroy(cs_stream);
         return hip_fail(e, "hipStreamBeginCapture");
     }
-    const cs_status rec = record(cs_stream);
+    *out = cs_stream;
+    return CS_OK;
+}
+
+// End the capture on cs_stream, release the stream, and (if rec is CS_OK)
+// instantiate the graph into *out.
+cs_status end_capture(hipStream_t cs_stream, cs_status rec, cs_graph* out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
     hipGraph_t graph = nullptr;
-    e = hipStreamEndCapture(cs_stream, &graph);
+    const hipError_t ee = hipStreamEndCapture(cs_stream, &graph);
     (void)hipStreamDestroy(cs_stream);
     if (rec != CS_OK) {
         if (graph) (void)hipGraphDestroy(graph);
         return rec;
     }
-    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    if (ee != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(ee, "hipStreamEndCapture");
+    }
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "hipGetDevice");
+    }
     hipGraphExec_t exec = nullptr;
     if ((e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess) {
         (void)hipGraphDestroy(graph);
@@ -56,6 +70,17 @@ cs_status capture(F&& record, cs_graph* out)
     }
     *out = h;
     return CS_OK;
+}
+
+template <typename F>
+cs_status capture(F&& record, cs_graph* out)
+{
+    if (!out) { set_error("NULL output handle"); return CS_EINVAL; }
+    *out = nullptr;
+    hipStream_t cs_stream = nullptr;
+    cs_status st = begin_capture(&cs_stream);
+    if (st != CS_OK) return st;
+    return end_capture(cs_stream, record(cs_stream), out);
 }
 
 }  // namespace
@@ -81,6 +106,29 @@ cs_status cs_graph_batch_gs(cs_batch bt, int32_t nsweeps, cs_graph* out)
     if (!bt) { set_error("batch is NULL"); return CS_EINVAL; }
     if (nsweeps < 1) { set_error("nsweeps must be >= 1"); return CS_EINVAL; }
     return capture([&](hipStream_t s) { return cs_batch_gs_sweeps(bt, nsweeps, s); }, out);
+}
+
+cs_status cs_graph_begin(void** capture_stream)
+{
+    if (!capture_stream) { set_error("NULL output stream"); return CS_EINVAL; }
+    hipStream_t st = nullptr;
+    cs_status rc = begin_capture(&st);
+    *capture_stream = st;
+    return rc;
+}
+
+cs_status cs_graph_end(void* capture_stream, cs_graph* out)
+{
+    if (!capture_stream || !out) { set_error("NULL argument"); return CS_EINVAL; }
+    *out = nullptr;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing((hipStream_t)capture_stream, &cap);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+    if (cap == hipStreamCaptureStatusNone) {
+        set_error("stream is not capturing");
+        return CS_EINVAL;
+    }
+    return end_capture((hipStream_t)capture_stream, CS_OK, out);
 }
 
 cs_status cs_graph_launch(cs_graph gr, void* stream)

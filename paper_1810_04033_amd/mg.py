@@ -67,10 +67,22 @@ class Multigrid:
             C.prolong_add(b.grid, a.grid, stream)
             a.grid.gs(self.nu2, tmp=a.tmp, stream=stream)
 
-    def solve(self, tol, *, max_cycles=200, stream=None, progress=None):
+    def capture(self):
+        """Record one V-cycle into a HIP graph (one replay call per cycle
+        instead of a library call per kernel); cycle_graph() replays it."""
+        if getattr(self, "graph", None) is None:
+            self.graph = C.Graph.record(lambda s: self.cycle(stream=s), keep=(self.levels,))
+        return self.graph
+
+    def cycle_graph(self, stream=None):
+        """Enqueue one V-cycle as a replay of the captured graph."""
+        self.capture().launch(stream)
+
+    def solve(self, tol, *, max_cycles=200, stream=None, progress=None, graph=False):
         """V-cycles until ||b - A u||_2 / ||b||_2 <= tol.  Returns a
         SolveResult whose `outer` counts the cycles and `sweeps` the fine-grid
-        sweeps; progress(cycles, rel) is called after every cycle."""
+        sweeps; progress(cycles, rel) is called after every cycle.  graph:
+        replay a captured cycle instead of enqueueing its calls."""
         fine = self.levels[0].grid
 
         def rel_of(t):
@@ -81,7 +93,10 @@ class Multigrid:
         hist = [rel]
         cycles = 0
         while rel > tol and cycles < max_cycles:
-            self.cycle(stream)
+            if graph:
+                self.cycle_graph(stream)
+            else:
+                self.cycle(stream)
             cycles += 1
             rel = rel_of(fine.residual(stream=stream))
             hist.append(rel)
@@ -93,5 +108,8 @@ class Multigrid:
         return SolveResult(rel <= tol, cycles * per, cycles, rel, hist)
 
     def close(self):
+        if getattr(self, "graph", None) is not None:
+            self.graph.close()
+            self.graph = None
         for lv in self.levels[1:]:
             lv.grid.close()

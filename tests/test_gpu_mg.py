@@ -3,6 +3,8 @@ above them) against the oracle's V-cycle: the transfers bit for bit on every
 layout, whole V-cycles bit for bit (the sweeps and the residual are the
 oracle's to the bit, so the cycle is too), FD and d-linear stencils in 2D and
 3D, both colour parities; a 127^3 solve to 1e-10; and the argument checks."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -144,3 +146,39 @@ def test_residual_array_without_norms_bitwise():
     assert g.residual(r=r, want_norms=False) is None
     torch.cuda.synchronize()
     assert np.array_equal(O.interior(G.download(r)), O.interior(want))
+
+
+@pytest.mark.parametrize("n,stencil", [((31, 31, 31), C.CS_FD), ((15, 15, 15), C.CS_Q1),
+                                       ((63, 31), C.CS_FD)],
+                         ids=lambda p: "x".join(map(str, p)) if isinstance(p, tuple) else str(p))
+def test_vcycle_graph_replays_bitwise(n, stencil):
+    # a captured cycle, replayed several times with eager work and host
+    # synchronisation between the replays, equals the eager cycles every time
+    dim = len(n)
+    h = 1.0 / (max(n) + 1)
+    _, b = G.case(dim, n, seed=2700)
+    ua, ba = G.upload(np.zeros_like(b)), G.upload(b)
+    ub, bb = G.upload(np.zeros_like(b)), G.upload(b)
+    mga = MG.Multigrid(C.Grid(ua, ba, dim=dim, stencil=stencil, h=h))
+    mgb = MG.Multigrid(C.Grid(ub, bb, dim=dim, stencil=stencil, h=h))
+    mgb.capture()
+    uo = np.zeros_like(b)
+    for _ in range(4):
+        mga.cycle()
+        mgb.cycle_graph()
+        O.mg_vcycle(uo, b, dim=dim, stencil=stencil, h=h)
+        torch.cuda.synchronize()
+        junk = torch.ones(1 << 16, device="cuda", dtype=torch.float64)
+        assert float((junk * 2).sum()) == 2.0 * (1 << 16)
+        assert np.array_equal(G.download(ub), G.download(ua))
+        assert np.array_equal(G.download(ub), uo)
+    res = mgb.solve(1e-10, max_cycles=30, graph=True)
+    assert res.converged
+    mgb.close()
+
+
+def test_graph_end_needs_a_capturing_stream():
+    h = ctypes.c_void_p()
+    s = torch.cuda.current_stream().cuda_stream
+    assert C.lib().cs_graph_end(ctypes.c_void_p(s), ctypes.byref(h)) == C.CS_EINVAL
+    assert C.lib().cs_graph_end(None, ctypes.byref(h)) == C.CS_EINVAL
