@@ -182,3 +182,23 @@ def test_graph_end_needs_a_capturing_stream():
     s = torch.cuda.current_stream().cuda_stream
     assert C.lib().cs_graph_end(ctypes.c_void_p(s), ctypes.byref(h)) == C.CS_EINVAL
     assert C.lib().cs_graph_end(None, ctypes.byref(h)) == C.CS_EINVAL
+
+
+@pytest.mark.parametrize("stencil", [C.CS_FD, C.CS_Q1], ids=["fd7", "q1_27"])
+def test_vcycle_255_bitwise(stencil):
+    # the multigrid workload's size and launch configuration: one V(2,2)-cycle
+    # from u = 0 on 255^3 with the device-made right-hand side, against the
+    # oracle's cycle element by element
+    n = (255, 255, 255)
+    h = 1.0 / 256
+    b = C.empty_grid(n)
+    C.fill_uniform(b, 2, dim=3)
+    u = C.empty_grid(n)
+    mg = MG.Multigrid(C.Grid(u, b, dim=3, stencil=stencil, h=h))
+    mg.cycle()
+    torch.cuda.synchronize()
+    bh = np.ascontiguousarray(b.detach().cpu().numpy())
+    uo = np.zeros_like(bh)
+    O.mg_vcycle(uo, bh, dim=3, stencil=O.FD if stencil == C.CS_FD else O.Q1, h=h)
+    assert np.array_equal(u.detach().cpu().numpy(), uo)
+    mg.close()
