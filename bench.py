@@ -572,6 +572,35 @@ def run_multigrid(a):
                             stencil=O.FD if st == C.CS_FD else O.Q1, h=h)
             row["rel_residual_oracle_fp64"] = float(nr[0] / nr[2])
             row["oracle_cycles"] = res2.outer
+        # the same solve by FP32 V-cycles inside FP64 iterative refinement:
+        # 3 FP32 cycles per refinement step on the correction equation
+        e32 = C.empty_grid(n3, dtype=torch.float32)
+        r32 = C.empty_grid(n3, dtype=torch.float32)
+        g32 = C.Grid(e32, r32, dim=3, stencil=st, h=h)
+        mg32 = MG.Multigrid(g32)
+        per_step = 3
+
+        def inner(s, mg32=mg32):
+            for _ in range(per_step):
+                mg32.cycle(stream=s)
+
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ir = S.ir_solve(g, g32, tol, inner_sweeps=per_step, inner=inner, max_outer=50)
+        torch.cuda.synchronize()
+        ir_s = time.perf_counter() - t0
+        row["fp32_cycles_in_fp64_refinement"] = {
+            "seconds": round(ir_s, 4), "refinement_steps": ir.outer, "fp32_cycles": ir.sweeps,
+            "rel_residual_gpu": ir.rel_residual, "converged": ir.converged}
+        say("%s: FP32 cycles in FP64 refinement, %d steps, %.3f s" % (name, ir.outer, ir_s))
+        if not a.no_cpu_baseline:
+            nr = O.residual(u.detach().cpu().numpy(), b.detach().cpu().numpy(), dim=3,
+                            stencil=O.FD if st == C.CS_FD else O.Q1, h=h)
+            row["fp32_cycles_in_fp64_refinement"]["rel_residual_oracle_fp64"] = float(nr[0] / nr[2])
+        mg32.close()
+        g32.close()
+        del e32, r32
         mg.close()
         if a.mg_gs_compare:
             u2 = C.empty_grid(n3)

@@ -13,8 +13,6 @@ synchronisation is the read-back of the residual norms in solve().
 """
 import math
 
-import torch
-
 from . import colsten as C
 from .solve import SolveResult
 

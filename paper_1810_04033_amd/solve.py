@@ -55,13 +55,16 @@ def gs_solve(grid, tol, *, check_every=10, tmp=None, max_sweeps=10 ** 7, stream=
 
 
 def ir_solve(g64, g32, tol, *, inner_sweeps, tmp32=None, max_outer=10 ** 6, stream=None,
-             progress=None):
+             progress=None, inner=None):
     """FP32 Gauss-Seidel sweeps inside FP64 iterative refinement.
 
     Step i: r_i = b - A x_i (FP64) with r32 = fl32(r_i / s_i) and e = 0 in the
     same pass; stop when ||r_i|| / ||b|| <= tol; `inner_sweeps` FP32 sweeps on
     A e = r32; x_{i+1} = x_i + s_i e (FP64).  s_i is the smallest power of two
-    >= max |r_{i-1}| (r_{-1} = r_0, from one plain residual first)."""
+    >= max |r_{i-1}| (r_{-1} = r_0, from one plain residual first).
+    inner: None, or a callable inner(stream) that replaces the inner sweeps
+    by another FP32 solve of A e = r32 on g32 from e = 0 (e.g. multigrid
+    cycles); `sweeps` then adds inner_sweeps per call."""
     norms = torch.zeros(3, dtype=torch.float64, device=g64.u.device)
     C.cs_residual(g64.handle, 0, norms.data_ptr(), stream)
     n = norms.cpu().tolist()
@@ -77,7 +80,10 @@ def ir_solve(g64, g32, tol, *, inner_sweeps, tmp32=None, max_outer=10 ** 6, stre
             progress(sweeps, rel)
         if rel <= tol or not math.isfinite(rel) or outer == max_outer:
             return SolveResult(rel <= tol, sweeps, outer, rel, hist)
-        g32.gs(inner_sweeps, tmp=tmp32, stream=stream)
+        if inner is None:
+            g32.gs(inner_sweeps, tmp=tmp32, stream=stream)
+        else:
+            inner(stream)
         sweeps += inner_sweeps
         C.cs_ir_update(g64.handle, g32.handle, scale, stream)
         scale = pow2_at_least(n[1])

@@ -202,3 +202,33 @@ def test_vcycle_255_bitwise(stencil):
     O.mg_vcycle(uo, bh, dim=3, stencil=O.FD if stencil == C.CS_FD else O.Q1, h=h)
     assert np.array_equal(u.detach().cpu().numpy(), uo)
     mg.close()
+
+
+@pytest.mark.parametrize("stencil", [C.CS_FD, C.CS_Q1], ids=["fd7", "q1_27"])
+def test_fp32_cycles_inside_fp64_refinement(stencil):
+    # FP32 V-cycles as the inner solve of FP64 iterative refinement reach an
+    # FP64 tolerance FP32 alone cannot, in a few refinement steps; the final
+    # residual is recomputed by the oracle
+    from paper_1810_04033_amd import solve as S
+    n = (63, 63, 63)
+    h = 1.0 / 64
+    b = C.empty_grid(n)
+    C.fill_uniform(b, 11, dim=3)
+    u = C.empty_grid(n)
+    g64 = C.Grid(u, b, dim=3, stencil=stencil, h=h)
+    e = C.empty_grid(n, dtype=torch.float32)
+    r32 = C.empty_grid(n, dtype=torch.float32)
+    g32 = C.Grid(e, r32, dim=3, stencil=stencil, h=h)
+    mg32 = MG.Multigrid(g32)
+
+    def inner(s):
+        for _ in range(3):
+            mg32.cycle(stream=s)
+
+    res = S.ir_solve(g64, g32, 1e-10, inner_sweeps=3, inner=inner, max_outer=10)
+    torch.cuda.synchronize()
+    assert res.converged and res.outer <= 4
+    nr = O.residual(u.detach().cpu().numpy(), b.detach().cpu().numpy(), dim=3,
+                    stencil=O.FD if stencil == C.CS_FD else O.Q1, h=h)
+    assert nr[0] / nr[2] <= 1e-10
+    mg32.close()
