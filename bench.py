@@ -769,7 +769,9 @@ ORDERING_CASES = (
 def run_orderings(a):
     """Lexicographic Gauss-Seidel (the task-graph iterate of Sec. 3, run as
     hyperplane wavefronts, one launch per hyperplane) beside the coloured sweeps
-    (one launch per colour, and the fused single pass where it exists), FP64,
+    (one launch per colour, one persistent launch with a device-wide barrier per
+    colour, one persistent launch with tile dependencies, and the fused single
+    pass where it exists), FP64,
     on the 2D 256^2 grid of the small workload and a 3D 128^3 grid; the
     launch-per-kernel modes also as captured HIP graphs of 5 sweeps."""
     import numpy as np
@@ -797,6 +799,7 @@ def run_orderings(a):
                                                              for _ in range(k // sweeps)],
                  "coloured_per_colour": lambda k: g.gs(k),
                  "coloured_persistent_barrier": lambda k: g.gs_sync(k),
+                 "coloured_tile_dependencies": lambda k: g.gs_dep(k),
                  "coloured_per_colour_graph": lambda k: [graphs["coloured_per_colour_graph"].launch()
                                                          for _ in range(k // sweeps)]}
         if g.fused:
@@ -815,6 +818,8 @@ def run_orderings(a):
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / (a.steps * sweeps)
             row[mode] = {"ms_per_sweep": round(ms, 4), "GLUP/s": round(pts / ms / 1e6, 3)}
+            if mode in ("coloured_persistent_barrier", "coloured_tile_dependencies"):
+                row[mode]["waits_given_up"] = g.sync_failures()
             if mode == "lexicographic_wavefront":
                 lex_ms += ms
                 lex_pts += pts

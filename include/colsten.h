@@ -135,10 +135,25 @@ cs_status cs_jacobi_sweeps(cs_grid g, double omega, int32_t nsweeps, void* u_tmp
  * cooperative launch is refused. */
 cs_status cs_gs_sweeps_sync(cs_grid g, int32_t nsweeps, void* stream);
 
-/* *out = number of barrier waits of cs_gs_sweeps_sync on g that gave up since
- * the grid was created (0 unless something went wrong).  Synchronises stream.
+/* *out = number of waits of cs_gs_sweeps_sync and cs_gs_sweeps_dep on g that
+ * gave up since the grid was created (0 unless something went wrong).
+ * Synchronises stream.
  * Errors: CS_EINVAL (bad grid, out NULL), CS_EHIP. */
 cs_status cs_gs_sync_failures(cs_grid g, int32_t* out, void* stream);
+
+/* The Hyb-depend form of the colouring (Sec. 5): nsweeps sweeps in one
+ * persistent launch without any barrier between colours.  The grid is cut into
+ * tiles (32 x 16 x 8 points in 3D, 64 x 32 in 2D), each with a counter of the
+ * colour phases it has finished; a tile runs colour phase p (sweep p / c,
+ * colour p % c) once its 8 (2D) or 26 (3D) neighbour tiles have finished phase
+ * p - 1, so no tile runs more than one phase ahead of a neighbour and the
+ * iterate is that of the colour passes, bit for bit.  Workgroups are kept
+ * resident (cooperative launch) and take the tiles round robin.  Each wait is
+ * bounded: a wait that gives up is counted (read with cs_gs_sync_failures) and
+ * ends all other waits, so the call always returns; the result of such a call
+ * is not to be used.  Errors: CS_EINVAL (nsweeps < 0, or more than 2^31 colour
+ * phases), CS_EHIP (cooperative launch refused). */
+cs_status cs_gs_sweeps_dep(cs_grid g, int32_t nsweeps, void* stream);
 
 /* nsweeps lexicographic Gauss-Seidel sweeps: the iterate of the sequential
  * in-place loop in z-y-x order (x innermost), which the task graph of Sec. 3

@@ -71,6 +71,7 @@ _SIGS = {
     "cs_ir_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
                                       ctypes.c_void_p]),
     "cs_ir_update": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]),
+    "cs_gs_sweeps_dep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "cs_restrict": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "cs_prolong_add": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "cs_batch_create": (ctypes.c_int, [ctypes.POINTER(cs_grid_desc), ctypes.POINTER(ctypes.c_void_p),
@@ -160,6 +161,10 @@ def cs_gs_fused(handle):
 
 def cs_gs_sweeps_sync(handle, nsweeps, stream=None):
     _check(lib().cs_gs_sweeps_sync(ctypes.c_void_p(handle), ctypes.c_int32(nsweeps), _stream(stream)))
+
+
+def cs_gs_sweeps_dep(handle, nsweeps, stream=None):
+    _check(lib().cs_gs_sweeps_dep(ctypes.c_void_p(handle), ctypes.c_int32(nsweeps), _stream(stream)))
 
 
 def cs_gs_sync_failures(handle, stream=None):
@@ -380,6 +385,11 @@ class Grid:
     def gs_sync(self, nsweeps, stream=None):
         """Sweeps in one persistent launch with a device-wide barrier per colour."""
         cs_gs_sweeps_sync(self.handle, nsweeps, stream)
+
+    def gs_dep(self, nsweeps, stream=None):
+        """Sweeps in one persistent launch, each tile waiting only for its
+        neighbour tiles' previous colour (no barrier between colours)."""
+        cs_gs_sweeps_dep(self.handle, nsweeps, stream)
 
     def sync_failures(self, stream=None):
         return cs_gs_sync_failures(self.handle, stream)

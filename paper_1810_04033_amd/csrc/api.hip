@@ -178,8 +178,13 @@ cs_status cs_grid_create(const cs_grid_desc* desc, void* u, const void* b, cs_gr
         set_error("hipMalloc of the reduction scratch failed: %s", hipGetErrorString(e));
         return CS_ENOMEM;
     }
-    e = hipMalloc((void**)&g->bar, 4 * sizeof(unsigned));
-    if (e == hipSuccess) e = hipMemset(g->bar, 0, 4 * sizeof(unsigned));
+    // barrier words of the persistent sweeps, then one counter per tile of
+    // the dependency-driven sweep
+    int64_t tnx = 0, tny = 0, tnz = 0;
+    dep_tile_counts(g->geo, g->d.dim, &tnx, &tny, &tnz);
+    const size_t words = 4 + (size_t)(tnx * tny * tnz);
+    e = hipMalloc((void**)&g->bar, words * sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemset(g->bar, 0, words * sizeof(unsigned));
     if (e != hipSuccess) {
         (void)hipGetLastError();
         (void)hipFree(g->partials);
@@ -384,6 +389,18 @@ cs_status cs_gs_sweeps_sync(cs_grid g, int32_t nsweeps, void* stream)
     if (nsweeps == 0) return CS_OK;
     return launch_sync_sweeps(g->d.dtype, g->d.dim, g->d.stencil, g->geo, g->u, g->b, h2_of(g),
                               nsweeps, g->bar, (hipStream_t)stream);
+}
+
+cs_status cs_gs_sweeps_dep(cs_grid g, int32_t nsweeps, void* stream)
+{
+    cs_status st = check_grid(g);
+    if (st != CS_OK) return st;
+    if (nsweeps < 0) { set_error("nsweeps must be >= 0"); return CS_EINVAL; }
+    if (nsweeps == 0) return CS_OK;
+    const int64_t phases = (int64_t)nsweeps * (g->d.stencil == CS_FD ? 2 : (1 << g->d.dim));
+    if (phases >= ((int64_t)1 << 31)) { set_error("too many sweeps for the phase counters"); return CS_EINVAL; }
+    return launch_dep_sweeps(g->d.dtype, g->d.dim, g->d.stencil, g->geo, g->u, g->b, h2_of(g),
+                             nsweeps, g->bar, (hipStream_t)stream);
 }
 
 cs_status cs_gs_sync_failures(cs_grid g, int32_t* out, void* stream)

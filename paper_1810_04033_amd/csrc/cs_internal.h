@@ -97,6 +97,12 @@ cs_status launch_ir_update(int dim, const Geo& g, void* x, const Geo& g2, const 
                            double scale, hipStream_t s);
 // Persistent colour sweeps with a device-wide barrier between colours
 // (k_sync.hip); bar: three zeroed words of device memory owned by the grid.
+// The Hyb-depend form (k_sync.hip): tiles wait for their neighbours' previous
+// colour phase through per-tile counters in bar[4 ..]; bar[2] counts waits
+// that gave up, bar[3] is the abort flag.
+void dep_tile_counts(const Geo& g, int dim, int64_t* tnx, int64_t* tny, int64_t* tnz);
+cs_status launch_dep_sweeps(int dtype, int dim, int stencil, const Geo& g, void* u, const void* b,
+                            double h2, int nsweeps, unsigned* bar, hipStream_t s);
 // All sweeps of a small grid in one workgroup, a workgroup barrier per colour
 // (k_sync.hip); the iterate of the colour passes.
 cs_status launch_block_sweeps(int dtype, int dim, int stencil, const Geo& g, void* u,

@@ -164,6 +164,137 @@ cs_status block_sweeps_t(const Geo& g, void* u, const void* b, double h2, int ns
     return check_launch("one-workgroup sweeps");
 }
 
+// ---------------------------------------------------------------------------
+// The Hyb-depend form (Sec. 5): no barrier at all between colours.  The grid
+// is cut into boxes ("tiles"); a tile may run colour phase p (sweep p / c,
+// colour p % c) once every neighbouring tile has finished phase p - 1, and it
+// publishes the number of phases it has finished in a counter of its own.  A
+// tile is then never more than one phase ahead of a neighbour, so every point
+// update reads exactly the values the colour passes give it (colours before
+// its own from this sweep, after it from the last), and the iterate is the
+// colour passes' bit for bit.  Workgroups take tiles t = blockIdx, blockIdx +
+// grid, ... for every phase in turn; a cooperative launch keeps all of them
+// resident, so a waited-for tile always progresses (by induction on the
+// phase).  Publishing and observing follow the device-wide barrier above: a
+// workgroup barrier, one device-scope fence by the first thread, a release
+// store (or acquire loads, one lane per neighbour, then the fence).  Each wait
+// is bounded; a wait that gives up counts a failure and raises an abort flag
+// that ends every other wait at once, so the kernel always finishes.
+constexpr int kDepTX3 = 32, kDepTY3 = 16, kDepTZ3 = 8;
+constexpr int kDepTX2 = 64, kDepTY2 = 32;
+constexpr int kDepThreads = 512;
+
+template <int DIM, int ST>
+__device__ inline int colour_of(int64_t i, int64_t j, int64_t k, int parity)
+{
+    if (ST == FD) return (int)(((i - 1) + (j - 1) + (DIM == 3 ? k - 1 : 0) + parity) & 1);
+    const int px = (int)((i - 1 + parity) & 1), py = (int)((j - 1 + parity) & 1);
+    const int pz = DIM == 3 ? (int)((k - 1 + parity) & 1) : 0;
+    return px + 2 * py + 4 * pz;
+}
+
+__global__ void k_dep_reset(unsigned* bar, int64_t ntiles)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) bar[3] = 0u;
+    if (i < ntiles) bar[4 + i] = 0u;
+}
+
+template <typename T, int DIM, int ST>
+__global__ void __launch_bounds__(kDepThreads)
+k_dep_sweeps(T* u, const T* __restrict__ b, Geo g, T h2, int nsweeps, int64_t tnx, int64_t tny,
+             int64_t tnz, unsigned* bar)
+{
+    constexpr int NC = num_colours<ST, DIM>();
+    constexpr int TX = DIM == 3 ? kDepTX3 : kDepTX2, TY = DIM == 3 ? kDepTY3 : kDepTY2;
+    constexpr int TZ = DIM == 3 ? kDepTZ3 : 1;
+    constexpr int NB = DIM == 3 ? 27 : 9;  // the tile and its neighbours
+    unsigned* done = bar + 4;
+    const int64_t ntiles = tnx * tny * tnz;
+    const int64_t sy = g.sy, sz = g.sz;
+    const int phases = nsweeps * NC;
+    for (int p = 0; p < phases; ++p) {
+        const int c = p % NC;
+        for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+            const int64_t tx = t % tnx, ty = (t / tnx) % tny, tz = t / (tnx * tny);
+            if (p > 0 && (int)threadIdx.x < NB) {
+                const int o = threadIdx.x;
+                const int64_t nx = tx + o % 3 - 1, ny = ty + (o / 3) % 3 - 1;
+                const int64_t nz = DIM == 3 ? tz + o / 9 - 1 : tz;
+                const bool self = nx == tx && ny == ty && nz == tz;
+                if (!self && nx >= 0 && nx < tnx && ny >= 0 && ny < tny && nz >= 0 && nz < tnz) {
+                    const unsigned* w = &done[(nz * tny + ny) * tnx + nx];
+                    unsigned spins = 0;
+                    while (__hip_atomic_load(w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)p) {
+                        if (__hip_atomic_load(&bar[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+                        if (++spins == kSpinLimit) {
+                            __hip_atomic_fetch_add(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            __hip_atomic_store(&bar[3], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
+                    }
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) __threadfence();
+            __syncthreads();
+            const int64_t x0 = 1 + tx * TX, y0 = 1 + ty * TY, z0 = 1 + tz * TZ;
+            for (int w = threadIdx.x; w < TX * TY * TZ; w += blockDim.x) {
+                const int64_t i = x0 + w % TX, j = y0 + (w / TX) % TY;
+                const int64_t k = DIM == 3 ? z0 + w / (TX * TY) : 1;
+                if (i > g.nx || j > g.ny || (DIM == 3 && k > g.nz)) continue;
+                if (colour_of<DIM, ST>(i, j, k, g.parity) != c) continue;
+                const int64_t q = (DIM == 3 ? k * sz : 0) + j * sy + i;
+                auto ld = [&](int ox, int oy, int oz) { return u[q + oz * sz + oy * sy + ox]; };
+                u[q] = gs_value<T, DIM, ST>(h2, b[q], ld);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                __threadfence();
+                __hip_atomic_store(&done[t], (unsigned)(p + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+}
+
+template <typename T, int DIM, int ST>
+cs_status dep_sweeps_t(const Geo& g, void* u, const void* b, double h2, int nsweeps, unsigned* bar,
+                       hipStream_t s)
+{
+    auto kern = k_dep_sweeps<T, DIM, ST>;
+    static const int64_t resident = [&] {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kDepThreads, 0) != hipSuccess ||
+            hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            return (int64_t)0;
+        }
+        // one workgroup per CU: fewer fences per phase
+        return (int64_t)(per_cu > 0 ? 1 : 0) * cus;
+    }();
+    if (resident <= 0) {
+        set_error("dependency sweep: no resident workgroups");
+        return CS_EHIP;
+    }
+    int64_t tnx, tny, tnz;
+    dep_tile_counts(g, DIM, &tnx, &tny, &tnz);
+    const int64_t ntiles = tnx * tny * tnz;
+    hipLaunchKernelGGL(k_dep_reset, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s, bar, ntiles);
+    cs_status st = check_launch("dependency counters reset");
+    if (st != CS_OK) return st;
+    const int64_t blocks = ntiles < resident ? ntiles : resident;
+    Geo gg = g;
+    T h2t = (T)h2;
+    int ns = nsweeps;
+    void* args[] = {&u, (void*)&b, &gg, &h2t, &ns, &tnx, &tny, &tnz, &bar};
+    hipError_t e = hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)blocks),
+                                              dim3(kDepThreads), args, 0, s);
+    if (e != hipSuccess) return hip_fail(e, "hipLaunchCooperativeKernel");
+    return check_launch("dependency-driven colour sweeps");
+}
+
 template <typename T, int DIM, int ST>
 cs_status sync_sweeps_t(const Geo& g, void* u, const void* b, double h2, int nsweeps,
                         unsigned* bar, hipStream_t s)
@@ -200,6 +331,32 @@ cs_status sync_sweeps_t(const Geo& g, void* u, const void* b, double h2, int nsw
 }
 
 }  // namespace
+
+void dep_tile_counts(const Geo& g, int dim, int64_t* tnx, int64_t* tny, int64_t* tnz)
+{
+    const int64_t TX = dim == 3 ? kDepTX3 : kDepTX2, TY = dim == 3 ? kDepTY3 : kDepTY2;
+    const int64_t TZ = dim == 3 ? kDepTZ3 : 1;
+    *tnx = (g.nx + TX - 1) / TX;
+    *tny = (g.ny + TY - 1) / TY;
+    *tnz = dim == 3 ? (g.nz + TZ - 1) / TZ : 1;
+}
+
+cs_status launch_dep_sweeps(int dtype, int dim, int stencil, const Geo& g, void* u, const void* b,
+                            double h2, int nsweeps, unsigned* bar, hipStream_t s)
+{
+    if (dtype == 0) {
+        if (dim == 2)
+            return stencil == FD ? dep_sweeps_t<double, 2, FD>(g, u, b, h2, nsweeps, bar, s)
+                                 : dep_sweeps_t<double, 2, Q1>(g, u, b, h2, nsweeps, bar, s);
+        return stencil == FD ? dep_sweeps_t<double, 3, FD>(g, u, b, h2, nsweeps, bar, s)
+                             : dep_sweeps_t<double, 3, Q1>(g, u, b, h2, nsweeps, bar, s);
+    }
+    if (dim == 2)
+        return stencil == FD ? dep_sweeps_t<float, 2, FD>(g, u, b, h2, nsweeps, bar, s)
+                             : dep_sweeps_t<float, 2, Q1>(g, u, b, h2, nsweeps, bar, s);
+    return stencil == FD ? dep_sweeps_t<float, 3, FD>(g, u, b, h2, nsweeps, bar, s)
+                         : dep_sweeps_t<float, 3, Q1>(g, u, b, h2, nsweeps, bar, s);
+}
 
 cs_status launch_block_sweeps(int dtype, int dim, int stencil, const Geo& g, void* u,
                               const void* b, double h2, int nsweeps, hipStream_t s)
