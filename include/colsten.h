@@ -143,7 +143,8 @@ cs_status cs_gs_sync_failures(cs_grid g, int32_t* out, void* stream);
 
 /* The Hyb-depend form of the colouring (Sec. 5): nsweeps sweeps in one
  * persistent launch without any barrier between colours.  The grid is cut into
- * tiles (32 x 16 x 8 points in 3D, 64 x 32 in 2D), each with a counter of the
+ * tiles (32 x 16 x 8 points in 3D, deepened in z towards one tile per resident
+ * workgroup, 64 x 32 in 2D), each with a counter of the
  * colour phases it has finished; a tile runs colour phase p (sweep p / c,
  * colour p % c) once its 8 (2D) or 26 (3D) neighbour tiles have finished phase
  * p - 1, so no tile runs more than one phase ahead of a neighbour and the

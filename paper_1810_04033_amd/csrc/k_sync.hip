@@ -203,11 +203,11 @@ __global__ void k_dep_reset(unsigned* bar, int64_t ntiles)
 template <typename T, int DIM, int ST>
 __global__ void __launch_bounds__(kDepThreads)
 k_dep_sweeps(T* u, const T* __restrict__ b, Geo g, T h2, int nsweeps, int64_t tnx, int64_t tny,
-             int64_t tnz, unsigned* bar)
+             int64_t tnz, int tzd, unsigned* bar)
 {
     constexpr int NC = num_colours<ST, DIM>();
     constexpr int TX = DIM == 3 ? kDepTX3 : kDepTX2, TY = DIM == 3 ? kDepTY3 : kDepTY2;
-    constexpr int TZ = DIM == 3 ? kDepTZ3 : 1;
+    const int TZ = DIM == 3 ? tzd : 1;  // planes per tile
     constexpr int NB = DIM == 3 ? 27 : 9;  // the tile and its neighbours
     unsigned* done = bar + 4;
     const int64_t ntiles = tnx * tny * tnz;
@@ -240,7 +240,8 @@ k_dep_sweeps(T* u, const T* __restrict__ b, Geo g, T h2, int nsweeps, int64_t tn
             if (threadIdx.x == 0) __threadfence();
             __syncthreads();
             const int64_t x0 = 1 + tx * TX, y0 = 1 + ty * TY, z0 = 1 + tz * TZ;
-            for (int w = threadIdx.x; w < TX * TY * TZ; w += blockDim.x) {
+            const int tile_pts = TX * TY * TZ;
+            for (int w = threadIdx.x; w < tile_pts; w += blockDim.x) {
                 const int64_t i = x0 + w % TX, j = y0 + (w / TX) % TY;
                 const int64_t k = DIM == 3 ? z0 + w / (TX * TY) : 1;
                 if (i > g.nx || j > g.ny || (DIM == 3 && k > g.nz)) continue;
@@ -278,8 +279,19 @@ cs_status dep_sweeps_t(const Geo& g, void* u, const void* b, double h2, int nswe
         set_error("dependency sweep: no resident workgroups");
         return CS_EHIP;
     }
+    // tiles of kDepTZ3 planes (the counters are sized for these), deepened in z
+    // to about one tile per resident workgroup: one publication per workgroup
+    // and phase where the grid allows
     int64_t tnx, tny, tnz;
     dep_tile_counts(g, DIM, &tnx, &tny, &tnz);
+    int tzd = kDepTZ3;
+    if (DIM == 3) {
+        const int64_t f = (tnx * tny * tnz + resident - 1) / resident;
+        tzd = (int)(kDepTZ3 * (f < 1 ? 1 : f));
+        if (tzd > g.nz) tzd = (int)g.nz;
+        if (tzd < 1) tzd = 1;
+        tnz = (g.nz + tzd - 1) / tzd;
+    }
     const int64_t ntiles = tnx * tny * tnz;
     hipLaunchKernelGGL(k_dep_reset, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s, bar, ntiles);
     cs_status st = check_launch("dependency counters reset");
@@ -288,7 +300,7 @@ cs_status dep_sweeps_t(const Geo& g, void* u, const void* b, double h2, int nswe
     Geo gg = g;
     T h2t = (T)h2;
     int ns = nsweeps;
-    void* args[] = {&u, (void*)&b, &gg, &h2t, &ns, &tnx, &tny, &tnz, &bar};
+    void* args[] = {&u, (void*)&b, &gg, &h2t, &ns, &tnx, &tny, &tnz, &tzd, &bar};
     hipError_t e = hipLaunchCooperativeKernel((const void*)kern, dim3((unsigned)blocks),
                                               dim3(kDepThreads), args, 0, s);
     if (e != hipSuccess) return hip_fail(e, "hipLaunchCooperativeKernel");
