@@ -163,3 +163,16 @@ def test_transfers_reject_mismatched_sizes():
         O.restrict(_zeros((7, 7)), _zeros((4, 3)), _zeros((4, 3)), dim=2)
     with pytest.raises(ValueError):
         O.prolong_add(_zeros((3, 3, 2)), _zeros((7, 7, 7)), dim=3)
+
+
+def test_driver_and_oracle_coarsen_alike():
+    # the GPU driver's level rule (host logic, no GPU) and the oracle's agree,
+    # and sizes 2^m - 1 reach one point
+    from paper_1810_04033_amd import mg as MG
+    for n in [(1,), (3, 3), (7, 5), (8, 7), (15, 7, 31), (255, 255, 255), (2, 3, 3), (63, 127)]:
+        assert MG.coarsens(n) == O.mg_coarsens(n)
+    n, levels = (255, 255, 255), 1
+    while MG.coarsens(n):
+        n = tuple((v - 1) // 2 for v in n)
+        levels += 1
+    assert n == (1, 1, 1) and levels == 8
