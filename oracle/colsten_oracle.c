@@ -357,6 +357,70 @@ void og_lex_sweeps_f64(int dim, int stencil, int parity, int64_t nx, int64_t ny,
                     og_update(&g, u, b, og_index(&g, i, j, k));
 }
 
+/* ------------------------------------------------------------------ */
+/* Nested dissection (the other ordering of Sec. 3)                     */
+/* ------------------------------------------------------------------ */
+
+/* Sec. 3 splits the domain into 2^d blocks and a one-cell separator, recursively,
+ * runs the blocks (which do not couple) before their separator, and leaves the
+ * recursion depth and the order inside a separator to the machine.  Reading
+ * taken here: a box whose every edge is at most `leaf` cells is a leaf and is
+ * swept in z-y-x order; otherwise every axis longer than `leaf` is cut at the
+ * cell lo + extent / 2, the sub-boxes (lower before upper half per axis, z
+ * outermost) are processed recursively, then the separator -- the cells of the
+ * box on a cut -- in z-y-x order.  Every cell is updated once per sweep, in
+ * place: Gauss-Seidel in the dissection ordering, a different iterate from the
+ * colouring. */
+static void og_nd_box(const og_grid* g, double* u, const double* b, const int64_t* lo,
+                      const int64_t* hi, int64_t leaf)
+{
+    int cut[3] = {0, 0, 0};
+    int64_t m[3] = {0, 0, 0};
+    int any = 0;
+    for (int a = 0; a < g->dim; ++a) {
+        const int64_t ext = hi[a] - lo[a] + 1;
+        if (ext > leaf) {
+            cut[a] = 1;
+            m[a] = lo[a] + ext / 2;
+            any = 1;
+        }
+    }
+    if (any) {
+        for (int hz = 0; hz <= cut[2]; ++hz)
+            for (int hy = 0; hy <= cut[1]; ++hy)
+                for (int hx = 0; hx <= cut[0]; ++hx) {
+                    const int half[3] = {hx, hy, hz};
+                    int64_t clo[3], chi[3];
+                    int empty = 0;
+                    for (int a = 0; a < 3; ++a) {
+                        clo[a] = lo[a];
+                        chi[a] = hi[a];
+                        if (cut[a]) {
+                            if (half[a] == 0) chi[a] = m[a] - 1;
+                            else clo[a] = m[a] + 1;
+                        }
+                        if (clo[a] > chi[a]) empty = 1;
+                    }
+                    if (!empty) og_nd_box(g, u, b, clo, chi, leaf);
+                }
+    }
+    for (int64_t k = lo[2]; k <= hi[2]; ++k)
+        for (int64_t j = lo[1]; j <= hi[1]; ++j)
+            for (int64_t i = lo[0]; i <= hi[0]; ++i) {
+                const int on_cut = (cut[0] && i == m[0]) || (cut[1] && j == m[1]) || (cut[2] && k == m[2]);
+                if (!any || on_cut) og_update(g, u, b, og_index(g, i, j, k));
+            }
+}
+
+void og_nd_sweeps_f64(int dim, int stencil, int parity, int64_t nx, int64_t ny,
+                      int64_t nz, int64_t sy, int64_t sz, double h,
+                      double* u, const double* b, int nsweeps, int64_t leaf)
+{
+    og_grid g = og_make(dim, stencil, parity, nx, ny, nz, sy, sz, h);
+    const int64_t lo[3] = {1, 1, 1}, hi[3] = {g.nx, g.ny, g.nz};
+    for (int s = 0; s < nsweeps; ++s) og_nd_box(&g, u, b, lo, hi, leaf < 1 ? 1 : leaf);
+}
+
 void og_lex_sweeps_f32(int dim, int stencil, int parity, int64_t nx, int64_t ny,
                        int64_t nz, int64_t sy, int64_t sz, double h,
                        float* u, const float* b, int nsweeps)

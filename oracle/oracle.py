@@ -100,6 +100,8 @@ def _load():
     lib.og_q1_apply_cellwise_coloured.argtypes = [i32, i64, i64, i64, i64, i64, vp, vp]
     lib.og_apply_stencil.restype = None
     lib.og_apply_stencil.argtypes = [i32, i32, i64, i64, i64, i64, i64, vp, vp]
+    lib.og_nd_sweeps_f64.restype = None
+    lib.og_nd_sweeps_f64.argtypes = geo + [vp, vp, i32, i64]
     lib.og_restrict_f64.restype = None
     lib.og_restrict_f64.argtypes = [i32, i64, i64, i64, i64, i64, i64, i64, vp, vp, vp]
     lib.og_prolong_add_f64.restype = None
@@ -195,6 +197,15 @@ def lex_sweeps(u, b, nsweeps, *, dim, stencil, h):
     lib = _load()
     fn = lib.og_lex_sweeps_f64 if u.dtype == np.float64 else lib.og_lex_sweeps_f32
     fn(*_args(u, dim, stencil, 0, h), _ptr(u), _ptr(b), int(nsweeps))
+
+
+def nd_sweeps(u, b, nsweeps, *, dim, stencil, h, leaf=16):
+    """Gauss-Seidel in the nested-dissection ordering of Sec. 3 (the reading of
+    og_nd_sweeps_f64: boxes with every edge <= leaf are leaves), float64."""
+    _check_same(u, b)
+    if u.dtype != np.float64:
+        raise ValueError("nested dissection sweeps are float64")
+    _load().og_nd_sweeps_f64(*_args(u, dim, stencil, 0, h), _ptr(u), _ptr(b), int(nsweeps), int(leaf))
 
 
 def gs_sweeps_cost(u, b, nsweeps, kmax, hetero, *, dim, stencil, h, parity=0,

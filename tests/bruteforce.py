@@ -117,6 +117,22 @@ def gs_sweep_lex(u_ext_flat, b_int, dim, stencil, n, h):
     return out
 
 
+def gs_sweep_order(u_ext_flat, b_int, dim, stencil, n, h, order):
+    """One Gauss-Seidel sweep in an arbitrary ordering of the interior unknowns
+    (order: lexicographic interior indices in update order), by the triangular
+    solve (D + L) u_new = h^2 b - A_IB g - U u_old of the permuted A_II."""
+    a_ii, a_ib, cols, bcols = split(dim, stencil, n)
+    perm = np.asarray(order)
+    ap = a_ii[np.ix_(perm, perm)]
+    rhs = h * h * b_int - a_ib @ u_ext_flat[bcols]
+    lower = np.tril(ap)
+    upper = ap - lower
+    u_new = sla.solve_triangular(lower, rhs[perm] - upper @ u_ext_flat[cols][perm], lower=True)
+    out = u_ext_flat.copy()
+    out[cols[perm]] = u_new
+    return out
+
+
 def residual(u_ext_flat, b_int, dim, stencil, n, h):
     s = operator_ext(dim, stencil, n)
     return b_int - (s @ u_ext_flat) / (h * h)

@@ -75,6 +75,12 @@ MUTANTS = {
     "correction_subtracted": (
         "uf[q] = uf[q] + acc;",
         "uf[q] = uf[q] - acc;"),
+    "nd_cut_shifted": (
+        "            m[a] = lo[a] + ext / 2;",
+        "            m[a] = lo[a] + (ext - 1) / 2;"),
+    "nd_leaves_skipped": (
+        "                if (!any || on_cut) og_update(g, u, b, og_index(g, i, j, k));",
+        "                if (on_cut) og_update(g, u, b, og_index(g, i, j, k));"),
     "gs_skips_last_colour": (
         "        for (int c = 0; c < nc; ++c)\n            og_colour_pass_f64(",
         "        for (int c = 0; c < nc - 1; ++c)\n            og_colour_pass_f64("),
@@ -96,6 +102,7 @@ def test_pins_reject_mutant(name, tmp_path):
     proc = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                            os.path.join(ROOT, "tests", "test_oracle_pins.py"),
                            os.path.join(ROOT, "tests", "test_oracle_cost.py"),
-                           os.path.join(ROOT, "tests", "test_oracle_mg.py")],
+                           os.path.join(ROOT, "tests", "test_oracle_mg.py"),
+                           os.path.join(ROOT, "tests", "test_oracle_nd.py")],
                           cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert proc.returncode != 0, "the pins accepted mutant %s:\n%s" % (name, proc.stdout[-2000:])
