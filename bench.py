@@ -771,7 +771,9 @@ ORDERING_CASES = (
 
 def run_orderings(a):
     """Lexicographic Gauss-Seidel (the task-graph iterate of Sec. 3, run as
-    hyperplane wavefronts, one launch per hyperplane) beside the coloured sweeps
+    hyperplane wavefronts, one launch per hyperplane) and nested-dissection
+    Gauss-Seidel (the other ordering of Sec. 3, one launch per tree height,
+    leaves of edge 16) beside the coloured sweeps
     (one launch per colour, one persistent launch with a device-wide barrier per
     colour, one persistent launch with tile dependencies, and the fused single
     pass where it exists), FP64,
@@ -803,6 +805,7 @@ def run_orderings(a):
                  "coloured_per_colour": lambda k: g.gs(k),
                  "coloured_persistent_barrier": lambda k: g.gs_sync(k),
                  "coloured_tile_dependencies": lambda k: g.gs_dep(k),
+                 "nested_dissection": lambda k: g.gs_nd(k, leaf=16),
                  "coloured_per_colour_graph": lambda k: [graphs["coloured_per_colour_graph"].launch()
                                                          for _ in range(k // sweeps)]}
         if g.fused:

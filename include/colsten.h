@@ -156,6 +156,20 @@ cs_status cs_gs_sync_failures(cs_grid g, int32_t* out, void* stream);
  * phases), CS_EHIP (cooperative launch refused). */
 cs_status cs_gs_sweeps_dep(cs_grid g, int32_t nsweeps, void* stream);
 
+/* Gauss-Seidel in the nested-dissection ordering of Sec. 3 (a different
+ * iterate from the colouring).  The paper leaves the recursion depth and the
+ * order inside a separator open; here a box whose every edge is at most `leaf`
+ * cells is a leaf swept in z-y-x order, and otherwise every axis longer than
+ * `leaf` is cut at the cell lo + extent / 2, the sub-boxes are processed
+ * recursively, then the separator (the cells on a cut) in z-y-x order.  Boxes
+ * of the tree that are not nested never couple, so all nodes of one height run
+ * in one launch (leaves first), one thread per node.  The first call on a grid
+ * with a given leaf builds the tree on the host and uploads it (one device
+ * allocation, a synchronous copy); later calls allocate nothing.
+ * Errors: CS_EINVAL (nsweeps < 0, leaf < 1), CS_EUNSUPPORTED (sizes beyond
+ * 2^30), CS_ENOMEM. */
+cs_status cs_gs_sweeps_nd(cs_grid g, int32_t nsweeps, int32_t leaf, void* stream);
+
 /* nsweeps lexicographic Gauss-Seidel sweeps: the iterate of the sequential
  * in-place loop in z-y-x order (x innermost), which the task graph of Sec. 3
  * preserves; no colouring, so a different iterate from cs_gs_sweeps.  Run as

@@ -72,6 +72,7 @@ _SIGS = {
                                       ctypes.c_void_p]),
     "cs_ir_update": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]),
     "cs_gs_sweeps_dep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "cs_gs_sweeps_nd": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
     "cs_restrict": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "cs_prolong_add": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "cs_batch_create": (ctypes.c_int, [ctypes.POINTER(cs_grid_desc), ctypes.POINTER(ctypes.c_void_p),
@@ -165,6 +166,11 @@ def cs_gs_sweeps_sync(handle, nsweeps, stream=None):
 
 def cs_gs_sweeps_dep(handle, nsweeps, stream=None):
     _check(lib().cs_gs_sweeps_dep(ctypes.c_void_p(handle), ctypes.c_int32(nsweeps), _stream(stream)))
+
+
+def cs_gs_sweeps_nd(handle, nsweeps, leaf, stream=None):
+    _check(lib().cs_gs_sweeps_nd(ctypes.c_void_p(handle), ctypes.c_int32(nsweeps), ctypes.c_int32(leaf),
+                                 _stream(stream)))
 
 
 def cs_gs_sync_failures(handle, stream=None):
@@ -390,6 +396,11 @@ class Grid:
         """Sweeps in one persistent launch, each tile waiting only for its
         neighbour tiles' previous colour (no barrier between colours)."""
         cs_gs_sweeps_dep(self.handle, nsweeps, stream)
+
+    def gs_nd(self, nsweeps, leaf=16, stream=None):
+        """Gauss-Seidel sweeps in the nested-dissection ordering (leaves of
+        edge <= leaf), a different iterate from the colouring."""
+        cs_gs_sweeps_nd(self.handle, nsweeps, leaf, stream)
 
     def sync_failures(self, stream=None):
         return cs_gs_sync_failures(self.handle, stream)

@@ -203,6 +203,11 @@ cs_status cs_grid_destroy(cs_grid g)
     hipError_t e = hipFree(g->partials);
     const hipError_t e2 = hipFree(g->bar);
     if (e == hipSuccess) e = e2;
+    if (g->nd_nodes) {
+        const hipError_t e3 = hipFree(g->nd_nodes);
+        if (e == hipSuccess) e = e3;
+    }
+    delete g->nd_stage_off;
     delete g;
     if (e != hipSuccess) return hip_fail(e, "hipFree");
     return CS_OK;
@@ -401,6 +406,49 @@ cs_status cs_gs_sweeps_dep(cs_grid g, int32_t nsweeps, void* stream)
     if (phases >= ((int64_t)1 << 31)) { set_error("too many sweeps for the phase counters"); return CS_EINVAL; }
     return launch_dep_sweeps(g->d.dtype, g->d.dim, g->d.stencil, g->geo, g->u, g->b, h2_of(g),
                              nsweeps, g->bar, (hipStream_t)stream);
+}
+
+cs_status cs_gs_sweeps_nd(cs_grid g, int32_t nsweeps, int32_t leaf, void* stream)
+{
+    cs_status st = check_grid(g);
+    if (st != CS_OK) return st;
+    if (nsweeps < 0) { set_error("nsweeps must be >= 0"); return CS_EINVAL; }
+    if (leaf < 1) { set_error("leaf must be >= 1"); return CS_EINVAL; }
+    if (nsweeps == 0) return CS_OK;
+    if (g->geo.nx >= (1LL << 30) || g->geo.ny >= (1LL << 30) || g->geo.nz >= (1LL << 30)) {
+        set_error("nested dissection: sizes beyond 2^30");
+        return CS_EUNSUPPORTED;
+    }
+    if (g->nd_leaf != leaf) {
+        std::vector<NdNode> nodes;
+        std::vector<int> off;
+        if ((st = nd_tree(g->geo, g->d.dim, leaf, &nodes, &off)) != CS_OK) return st;
+        if (g->nd_nodes) {
+            hipError_t e = hipFree(g->nd_nodes);
+            g->nd_nodes = nullptr;
+            g->nd_leaf = 0;
+            if (e != hipSuccess) return hip_fail(e, "hipFree");
+        }
+        hipError_t e = hipMalloc((void**)&g->nd_nodes, nodes.size() * sizeof(NdNode));
+        if (e == hipSuccess)
+            e = hipMemcpy(g->nd_nodes, nodes.data(), nodes.size() * sizeof(NdNode), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            if (g->nd_nodes) (void)hipFree(g->nd_nodes);
+            g->nd_nodes = nullptr;
+            set_error("allocation of the dissection tree failed: %s", hipGetErrorString(e));
+            return CS_ENOMEM;
+        }
+        if (!g->nd_stage_off) {
+            g->nd_stage_off = new (std::nothrow) std::vector<int>();
+            if (!g->nd_stage_off) { set_error("out of host memory"); return CS_ENOMEM; }
+        }
+        *g->nd_stage_off = off;
+        g->nd_leaf = leaf;
+    }
+    return launch_nd_sweeps(g->d.dtype, g->d.dim, g->d.stencil, g->geo, g->u, g->b, h2_of(g), nsweeps,
+                            g->nd_nodes, g->nd_stage_off->data(), (int)g->nd_stage_off->size() - 1,
+                            (hipStream_t)stream);
 }
 
 cs_status cs_gs_sync_failures(cs_grid g, int32_t* out, void* stream)

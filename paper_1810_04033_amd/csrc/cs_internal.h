@@ -125,6 +125,15 @@ cs_status launch_residual3_stream(int dtype, int stencil, const Geo& g, const vo
 }  // namespace cs
 
 namespace cs {
+// A node of the nested-dissection tree (k_nd.hip): the box lo..hi (interior
+// coordinates), the cut axes (bit a: axis a cut at m[a]); cut == 0 is a leaf.
+struct NdNode {
+    int32_t lo[3], hi[3], m[3];
+    int32_t cut;
+};
+}  // namespace cs
+
+namespace cs {
 // Multigrid transfers (k_mg.hip): full weighting of the fine residual r into
 // the coarse b (and zero into the coarse u), d-linear interpolation of the
 // coarse u added to the fine u.
@@ -132,6 +141,17 @@ cs_status launch_restrict(int dtype, int dim, const Geo& gf, const void* r, cons
                           void* bc, void* uc, hipStream_t s);
 cs_status launch_prolong_add(int dtype, int dim, const Geo& gc, const void* uc, const Geo& gf,
                              void* uf, hipStream_t s);
+}  // namespace cs
+
+#include <vector>
+namespace cs {
+// The dissection tree of a grid, grouped by height (leaves first), and the
+// sweeps in that ordering (k_nd.hip).
+cs_status nd_tree(const Geo& g, int dim, int64_t leaf, std::vector<NdNode>* nodes,
+                  std::vector<int>* stage_off);
+cs_status launch_nd_sweeps(int dtype, int dim, int stencil, const Geo& g, void* u, const void* b,
+                           double h2, int nsweeps, const NdNode* nodes, const int* stage_off,
+                           int nstages, hipStream_t s);
 }  // namespace cs
 
 struct cs_grid_s {
@@ -145,4 +165,7 @@ struct cs_grid_s {
     cs::Partial* partials;  // kMaxResidualBlocks entries of device scratch
     int pass_mode;        // cs_pass_mode: sweeps per pass over memory
     unsigned* bar;        // device-wide barrier words of the persistent sweep
+    cs::NdNode* nd_nodes; // nested-dissection tree on the device (built on first use)
+    int64_t nd_leaf;      // leaf size it was built for (0: none)
+    std::vector<int>* nd_stage_off;  // node offsets per height
 };
