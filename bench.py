@@ -343,6 +343,10 @@ def run_patches(a):
     for mode in ("per_colour", "fused_per_patch"):
         reset()
         grids = [C.Grid(u, b, dim=3, stencil=C.CS_FD, h=h) for (u, b, t, st, h, par) in ps]
+        for g in grids:
+            # the baselines as named: colour passes, or one fused pass per sweep
+            # (not the automatic schedules of small grids)
+            g.set_pass_mode(C.CS_PASS_ONE)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)

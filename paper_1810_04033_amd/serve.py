@@ -340,6 +340,7 @@ def bench_main(a):
         b = C.empty_grid(n)
         b[1:-1, 1:-1, 1:nx + 1].copy_(torch.from_numpy(t.rhs))
         g = C.Grid(u, b, dim=3, stencil=t.req.stencil, h=h)
+        g.set_pass_mode(C.CS_PASS_ONE)  # colour passes, as named (not the small-grid schedules)
         r = S.gs_solve(g, 1e-8, check_every=k)
         sweeps_seq += r.sweeps
         g.close()
