@@ -163,7 +163,9 @@ cs_status cs_gs_sweeps_dep(cs_grid g, int32_t nsweeps, void* stream);
  * `leaf` is cut at the cell lo + extent / 2, the sub-boxes are processed
  * recursively, then the separator (the cells on a cut) in z-y-x order.  Boxes
  * of the tree that are not nested never couple, so all nodes of one height run
- * in one launch (leaves first), one thread per node.  The first call on a grid
+ * in one launch (leaves first): one thread per node in 2D, one workgroup per
+ * node in 3D stepping through the node's cells by hyperplanes (the same order
+ * for every coupled pair).  The first call on a grid
  * with a given leaf builds the tree on the host and uploads it (one device
  * allocation, a synchronous copy); later calls allocate nothing.
  * Errors: CS_EINVAL (nsweeps < 0, leaf < 1), CS_EUNSUPPORTED (sizes beyond
