@@ -96,6 +96,20 @@ def _omp_threads():
 CPU_SWEEPS = 2  # sweeps of each kind in the host sample
 
 
+def _host_cpu():
+    """Model name of the host CPU and the cores this process may use."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": name, "cores_available": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(openmp=False):
     """The oracle on the host: two sweeps of each kind plus both residuals at
     the full 256^3 size (about 10 s), single thread; with openmp, the sweeps alone with
@@ -125,6 +139,7 @@ def cpu_baseline(openmp=False):
                           "residuals), the oracle built with -fopenmp (a parallel loop per colour "
                           "and per Jacobi sweep), %.1f s" % dt}
     return {"value": 4 * CPU_SWEEPS * N ** 3 / dt / 1e9, "unit": "GLUP/s", "cores": 1, "kind": "oracle",
+            "host": _host_cpu(),
             "sample": "two sweeps of each of the four sweep kinds plus both residual norms on the "
                       "full 256^3 grid, sequential C oracle, %.1f s" % dt}
 
