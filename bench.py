@@ -46,17 +46,20 @@ def _args():
                    help="run the GS rows as one launch per colour pass (no work array)")
     p.add_argument("--workload", default="poisson3d",
                    choices=["poisson3d", "patches", "refine", "serve", "expensive", "orderings",
-                            "multigrid"],
+                            "multigrid", "slab"],
                    help="poisson3d (default, the headline line); patches: 4096 batched patches; "
                         "refine: FP32 sweeps in FP64 refinement to 1e-10; serve: request stream; "
                         "expensive: sweeps with the S(k) stencil cost; orderings: lexicographic "
                         "wavefront GS beside coloured GS; multigrid: V-cycles with the coloured "
-                        "smoother to 1e-10")
+                        "smoother to 1e-10; slab: the sweep rows on one GPU's z-slab")
     p.add_argument("--tune", action="store_true", help="patches: run the tile autotuner first")
     p.add_argument("--refine-n", type=int, default=512, help="refine: interior edge")
     p.add_argument("--mg-n", type=int, default=255, help="multigrid: interior edge, 2^m - 1")
     p.add_argument("--mg-gs-compare", type=int, default=1,
                    help="multigrid: also solve with the coloured sweeps alone (1) or not (0)")
+    p.add_argument("--slab", default="512,512,64;256,256,32",
+                   help="slab: interior shapes nx,ny,nz separated by ';' (one GPU's eighth of "
+                        "512^3 and of 256^3 by default)")
     return p.parse_args()
 
 
@@ -883,6 +886,78 @@ def run_orderings(a):
     print(json.dumps(out), flush=True)
 
 
+XGMI_LINK_GBS = 153.0  # one xGMI link, per direction
+
+
+def run_slab(a):
+    """One GPU's share of a grid cut into z-slabs: the four sweep rows of the
+    headline step on each slab shape (100 sweeps each, FP64, the slab's halo
+    standing in for its neighbours' planes), beside the time a one-link
+    exchange of the planes the next pass needs would take (2 planes per side
+    per sweep, each way)."""
+    import torch
+
+    from paper_1810_04033_amd import colsten as C
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    shapes = [tuple(int(v) for v in s.split(",")) for s in a.slab.split(";")]
+    for n in shapes:
+        if len(n) != 3 or min(n) < 1:
+            raise SystemExit("--slab: shapes are nx,ny,nz;...")
+    res = {}
+    for n in shapes:
+        pts = n[0] * n[1] * n[2]
+        b = C.empty_grid(n)
+        C.fill_uniform(b, 2, dim=3)
+        tmp = C.empty_grid(n)
+        h = 1.0 / (max(n) + 1)
+        rows = {}
+        for name, st in (("fd7", C.CS_FD), ("q1_27", C.CS_Q1)):
+            u = C.empty_grid(n)
+            g = C.Grid(u, b, dim=3, stencil=st, h=h)
+            for kind in ("gs", "jacobi"):
+                def run():
+                    u.zero_()
+                    e0.record(stream)
+                    if kind == "gs":
+                        g.gs(SWEEPS, tmp=tmp)
+                    else:
+                        g.jacobi(OMEGA, SWEEPS, tmp)
+                    e1.record(stream)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                for _ in range(a.warmup):
+                    run()
+                torch.cuda.synchronize()
+                ms = 0.0
+                for _ in range(a.steps):
+                    run()
+                    torch.cuda.synchronize()
+                    ms += e0.elapsed_time(e1)
+                per_sweep_us = ms / a.steps / SWEEPS * 1e3
+                rows[kind + "_" + name] = {"us_per_sweep": round(per_sweep_us, 3),
+                                           "GLUP/s": round(pts / (per_sweep_us * 1e-6) / 1e9, 2),
+                                           "sweeps_per_pass": g.sweeps_per_pass(jacobi=(kind == "jacobi"))}
+            g.close()
+        exch_bytes = 2 * n[0] * n[1] * 8  # per neighbour and sweep, each way
+        res["x".join(map(str, n))] = {
+            "rows": rows,
+            "exchange_bytes_per_neighbour_per_sweep": exch_bytes,
+            "exchange_us_per_sweep_one_link": round(exch_bytes / (XGMI_LINK_GBS * 1e9) * 1e6, 3)}
+    total = sum(len(v["rows"]) for v in res.values())
+    mean = sum(r["GLUP/s"] for v in res.values() for r in v["rows"].values()) / total
+    print(json.dumps({
+        "metric": "GLUP/s on one GPU's z-slab (mean over the four sweep rows and the shapes)",
+        "value": round(mean, 3), "unit": "GLUP/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "one GPU's z-slab of a larger 3D Poisson grid, FP64, seeded "
+                               "uniform[-1,1) RHS, u0=0, 100 sweeps per row",
+                   "slabs": list(res)},
+        "slabs": res}), flush=True)
+
+
 def run_serve(a):
     from paper_1810_04033_amd import serve as SV
     SV.bench_main(a)
@@ -906,6 +981,8 @@ def main():
         run_expensive(a)
     elif a.workload == "orderings":
         run_orderings(a)
+    elif a.workload == "slab":
+        run_slab(a)
     else:
         run_poisson3d(a)
 
