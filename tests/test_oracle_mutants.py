@@ -81,6 +81,18 @@ MUTANTS = {
     "nd_leaves_skipped": (
         "                if (!any || on_cut) og_update(g, u, b, og_index(g, i, j, k));",
         "                if (on_cut) og_update(g, u, b, og_index(g, i, j, k));"),
+    "fp32_jacobi_weight_dropped": (
+        "dst[q] = fmaf(om, og_over_centre_f32(stencil, dim, h2 * b[q] - su), src[q]);",
+        "dst[q] = og_over_centre_f32(stencil, dim, h2 * b[q] - su) + src[q];"),
+    "fp32_lex_sweep_reversed_x": (
+        "                for (int64_t i = 1; i <= g.nx; ++i)\n                    og_update_f32(&g, u, b, og_index(&g, i, j, k));",
+        "                for (int64_t i = g.nx; i >= 1; --i)\n                    og_update_f32(&g, u, b, og_index(&g, i, j, k));"),
+    "fp32_grid_residual_scaled_wrongly": (
+        "                double rq = bq - su / h2;",
+        "                double rq = bq - su * h2;"),
+    "fp32_neighbour_term_dropped": (
+        "                if (w == 0.0f) continue;\n                acc = fmaf(w, u[q + oz * g->sz + oy * g->sy + ox], acc);",
+        "                if (w == 0.0f || (oy == 1 && oz == 0)) continue;\n                acc = fmaf(w, u[q + oz * g->sz + oy * g->sy + ox], acc);"),
     "gs_skips_last_colour": (
         "        for (int c = 0; c < nc; ++c)\n            og_colour_pass_f64(",
         "        for (int c = 0; c < nc - 1; ++c)\n            og_colour_pass_f64("),
@@ -101,6 +113,7 @@ def test_pins_reject_mutant(name, tmp_path):
     env = dict(os.environ, COLSTEN_ORACLE_LIB=str(lib))
     proc = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                            os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                           os.path.join(ROOT, "tests", "test_oracle_fp32_pins.py"),
                            os.path.join(ROOT, "tests", "test_oracle_cost.py"),
                            os.path.join(ROOT, "tests", "test_oracle_mg.py"),
                            os.path.join(ROOT, "tests", "test_oracle_nd.py")],
