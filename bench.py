@@ -46,12 +46,13 @@ def _args():
                    help="run the GS rows as one launch per colour pass (no work array)")
     p.add_argument("--workload", default="poisson3d",
                    choices=["poisson3d", "patches", "refine", "serve", "expensive", "orderings",
-                            "multigrid", "slab"],
+                            "multigrid", "slab", "calib"],
                    help="poisson3d (default, the headline line); patches: 4096 batched patches; "
                         "refine: FP32 sweeps in FP64 refinement to 1e-10; serve: request stream; "
                         "expensive: sweeps with the S(k) stencil cost; orderings: lexicographic "
                         "wavefront GS beside coloured GS; multigrid: V-cycles with the coloured "
-                        "smoother to 1e-10; slab: the sweep rows on one GPU's z-slab")
+                        "smoother to 1e-10; slab: the sweep rows on one GPU's z-slab; calib: a "
+                        "plain 1 GiB device copy for scaling rocprofv3's byte counters")
     p.add_argument("--tune", action="store_true", help="patches: run the tile autotuner first")
     p.add_argument("--refine-n", type=int, default=512, help="refine: interior edge")
     p.add_argument("--mg-n", type=int, default=255, help="multigrid: interior edge, 2^m - 1")
@@ -963,6 +964,22 @@ def run_serve(a):
     SV.bench_main(a)
 
 
+def run_calib(a):
+    """A plain device copy of known size for calibrating rocprofv3's byte
+    counters: three copies of exactly 1 GiB (2^27 doubles) between two device
+    buffers.  The FETCH_SIZE / WRITE_SIZE readings of these dispatches divided
+    by 1 GiB are the scale factors applied to the kernels' counter readings."""
+    import torch
+
+    torch.cuda.set_device(0)
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "calib", "copies": 3, "bytes_per_copy": 1 << 30}), flush=True)
+
+
 def main():
     a = _args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -983,6 +1000,8 @@ def main():
         run_orderings(a)
     elif a.workload == "slab":
         run_slab(a)
+    elif a.workload == "calib":
+        run_calib(a)
     else:
         run_poisson3d(a)
 

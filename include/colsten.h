@@ -79,7 +79,8 @@ typedef struct cs_grid_desc {
 typedef struct cs_grid_s* cs_grid;
 
 /* Bind a grid to the caller's arrays u (unknowns, updated in place) and b
- * (right-hand side).  Both must be device allocations on the current device
+ * (right-hand side): the fixed-size d-dimensional mesh with one value per cell
+ * of Sec. 2, its stencil from Fig. 1 and its colouring of Sec. 3.  Both must be device allocations on the current device
  * covering the whole halo'd extent; the check uses the allocation's address
  * range.  Allocates a small reduction scratch (freed by cs_grid_destroy).
  * Errors: CS_EINVAL on a bad descriptor or pointer, CS_ENOMEM, CS_EHIP. */
@@ -98,7 +99,8 @@ cs_status cs_num_colours(cs_grid g, int32_t* out);
  * Errors: CS_EINVAL if colour is outside [0, c). */
 cs_status cs_colour_pass(cs_grid g, int32_t colour, void* stream);
 
-/* nsweeps full Gauss-Seidel sweeps, each the colours 0..c-1 in order.
+/* nsweeps full Gauss-Seidel sweeps, each the colours 0..c-1 in order (the
+ * in-situ update of Sec. 2 ordered by the colouring of Sec. 3).
  * u_tmp: NULL, or a caller-owned device array with exactly u's layout.  With
  * u_tmp the library runs the sweeps as fused passes over memory, each reading
  * u (or u_tmp) and writing the other array (the same iterate as the colour
@@ -167,9 +169,11 @@ cs_status cs_gs_sweeps_dep(cs_grid g, int32_t nsweeps, void* stream);
  * node in 3D stepping through the node's cells by hyperplanes (the same order
  * for every coupled pair).  The first call on a grid
  * with a given leaf builds the tree on the host and uploads it (one device
- * allocation, a synchronous copy); later calls allocate nothing.
- * Errors: CS_EINVAL (nsweeps < 0, leaf < 1), CS_EUNSUPPORTED (sizes beyond
- * 2^30), CS_ENOMEM. */
+ * allocation, a synchronous copy); later calls allocate nothing.  Under graph
+ * capture the tree must already exist: a call on a capturing stream whose tree
+ * is not built returns CS_EINVAL before touching the stream.
+ * Errors: CS_EINVAL (nsweeps < 0, leaf < 1, tree not built under capture),
+ * CS_EUNSUPPORTED (sizes beyond 2^30), CS_ENOMEM. */
 cs_status cs_gs_sweeps_nd(cs_grid g, int32_t nsweeps, int32_t leaf, void* stream);
 
 /* nsweeps lexicographic Gauss-Seidel sweeps: the iterate of the sequential
@@ -213,7 +217,8 @@ cs_status cs_fill_uniform(const cs_grid_desc* desc, void* a, uint64_t seed, void
  * Errors: CS_EINVAL (bad y, cellwise not 0/1, cellwise with CS_FD). */
 cs_status cs_apply(cs_grid g, void* y, int32_t cellwise, void* stream);
 
-/* Residual r_q = b_q - (S u)_q / h^2 over the interior.  r: NULL or a device
+/* Residual r_q = b_q - (S u)_q / h^2 over the interior: the stencil applied
+ * into a separate output array (the mat-vec of Sec. 2), subtracted from b.  r: NULL or a device
  * array with u's layout and dtype (halo untouched).  norms: device pointer to
  * 3 doubles receiving ||r||_2, max |r| and ||b||_2 (unweighted sums over
  * interior points), or NULL when only r is wanted (the final reduction is then
@@ -251,7 +256,8 @@ cs_status cs_restrict(cs_grid fine, const void* r, cs_grid coarse, void* stream)
 cs_status cs_prolong_add(cs_grid coarse, cs_grid fine, void* stream);
 
 /* ---- FP32 sweeps inside FP64 iterative refinement ----------------------
- * g64: an FP64 grid whose u holds the iterate x and whose b is the right-hand
+ * The paper computes in FP64 only (Sec. 2); these two calls wrap its coloured
+ * sweep (Sec. 3) run in FP32 into an FP64 refinement loop.  g64: an FP64 grid whose u holds the iterate x and whose b is the right-hand
  * side.  g32: an FP32 grid of the same dim, stencil, parity, n and h (its own
  * strides) whose u holds the correction e and whose b array receives the
  * scaled residual.  One refinement step is
@@ -269,7 +275,7 @@ cs_status cs_ir_update(cs_grid g64, cs_grid g32, double scale, void* stream);
 
 /* ---- Batched patches ----------------------------------------------------
  * Many independent 3D patches (the regular patches of block-structured
- * meshes, Sec. 1-2), each with its own descriptor (n, strides, h, parity),
+ * meshes, Sec. 1-2, each swept by the colouring of Sec. 3), each with its own descriptor (n, strides, h, parity),
  * its own u and b, and a work array tmp with u's layout; stencil and dtype
  * may differ between patches.  Patches are grouped by (stencil, dtype, tile
  * variant) and every sweep is one launch per group covering all its patches.

@@ -420,6 +420,16 @@ cs_status cs_gs_sweeps_nd(cs_grid g, int32_t nsweeps, int32_t leaf, void* stream
         return CS_EUNSUPPORTED;
     }
     if (g->nd_leaf != leaf) {
+        // building the tree allocates and copies synchronously, which a
+        // stream under graph capture must not see
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        hipError_t ce = hipStreamIsCapturing((hipStream_t)stream, &cap);
+        if (ce != hipSuccess) return hip_fail(ce, "hipStreamIsCapturing");
+        if (cap != hipStreamCaptureStatusNone) {
+            set_error("nested dissection: the tree for leaf %d is not built; make one "
+                      "uncaptured call with this leaf before capturing", leaf);
+            return CS_EINVAL;
+        }
         std::vector<NdNode> nodes;
         std::vector<int> off;
         if ((st = nd_tree(g->geo, g->d.dim, leaf, &nodes, &off)) != CS_OK) return st;

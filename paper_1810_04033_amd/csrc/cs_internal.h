@@ -111,6 +111,7 @@ cs_status launch_sync_sweeps(int dtype, int dim, int stencil, const Geo& g, void
                              const void* b, double h2, int nsweeps, unsigned* bar, hipStream_t s);
 // z-streaming Jacobi and residual for 3D grids (k_stream.hip).
 bool stream_supported(const Geo& g);
+bool residual3_stream_fits(const Geo& g);
 cs_status launch_jacobi3_stream(int dtype, int stencil, const Geo& g, const void* src, void* dst,
                                 const void* b, double h2, double omega, hipStream_t s);
 // Two Jacobi sweeps in one pass over memory (3D): src -> dst holds the

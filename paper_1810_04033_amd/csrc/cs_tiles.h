@@ -418,185 +418,6 @@ __device__ __forceinline__ void fd3_tile_two(const T* __restrict__ src, T* __res
 // lexicographic offset order, so values equal the eight colour passes bit
 // for bit.
 // ---------------------------------------------------------------------------
-template <int TX, int TY, int NT, int HALO>
-struct Q1Phase {
-    static constexpr int W = TX + 8;
-    static constexpr int COLS = TX + 2 * HALO;
-    static constexpr int ROWS = (TY + 2 * HALO + 1) / 2;  // rows of one type, at most
-    static constexpr int P = (ROWS * COLS + NT - 1) / NT;  // points per thread, at most
-};
-
-// The points of one phase owned by a thread: rows of type rho inside T+halo.
-template <int TX, int TY, int NT, int HALO, int P>
-__device__ __forceinline__ void q1_make_pts(const Geo& g, int64_t x0, int64_t y0, int rho,
-                                            int* pc, int* poff, bool* pout)
-{
-    constexpr int W = TX + 8;
-    constexpr int COLS = TX + 2 * HALO;
-    const int ly_lo = 4 - HALO;
-    const int rt_lo = (int)((y0 - 4 + ly_lo - 1 + g.parity) & 1);
-    const int first = ly_lo + ((rho - rt_lo) & 1);
-    const int nrows = (TY + 2 * HALO - (first - ly_lo) + 1) / 2;
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-        const int sidx = (int)threadIdx.x + NT * i;
-        const int row = sidx / COLS, col = sidx % COLS;
-        const int ly = first + 2 * row, lx = 4 - HALO + col;
-        const int64_t x = x0 - 4 + lx, y = y0 - 4 + ly;
-        const bool ok = row < nrows && x >= 1 && x <= g.nx && y >= 1 && y <= g.ny;
-        pc[i] = ok ? ly * W + lx : -1;
-        poff[i] = ok ? (int)(y * g.sy + x) : 0;
-        pout[i] = ok && lx >= 4 && lx < 4 + TX && ly >= 4 && ly < 4 + TY;
-    }
-}
-
-template <typename T, int P>
-__device__ __forceinline__ void q1_load_b(const T* __restrict__ b, const Geo& g, int64_t k,
-                                          const int* pc, const int* poff, T* v)
-{
-    const bool kin = k >= 1 && k <= g.nz;
-    const T* bp = b + (kin ? k : 0) * g.sz;
-#pragma unroll
-    for (int i = 0; i < P; ++i) v[i] = (kin && pc[i] >= 0) ? bp[poff[i]] : T(0);
-}
-
-// One phase: update the listed points in place in plane slot lk (z neighbours
-// in lm and lp), writing the ones inside T to dst when `write`.
-template <typename T, int W, int P>
-__device__ __forceinline__ void q1_phase(bool active, const int* pc, const int* poff,
-                                         const bool* pout, const T* bv, const T* lm, T* lk,
-                                         const T* lp, T h2, T* dp, bool write)
-{
-    if (!active) return;
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-        const int c = pc[i];
-        if (c < 0) continue;
-        auto ld = [&](int ox, int oy, int oz) -> T {
-            const T* pl = oz < 0 ? lm : (oz > 0 ? lp : lk);
-            return pl[c + oy * W + ox];
-        };
-        const T v = gs_value<T, 3, Q1>(h2, bv[i], ld);
-        lk[c] = v;
-        if (write && pout[i]) st_stream(dp + poff[i], v);
-    }
-}
-
-
-// One 8-colour sweep of the 27-point stencil over the box tb, src -> dst.
-template <typename T, int TX, int TY, int NT>
-__device__ __forceinline__ void q1_3_tile(const T* __restrict__ src, T* __restrict__ dst,
-                                          const T* __restrict__ b, const Geo& g, T h2,
-                                          const TileBox& tb)
-{
-    constexpr int W = TX + 8, HH = TY + 8, NCOL = W * HH;
-    constexpr int M = (NCOL + NT - 1) / NT;
-    using PA = Q1Phase<TX, TY, NT, 3>;
-    using PB = Q1Phase<TX, TY, NT, 2>;
-    using PC = Q1Phase<TX, TY, NT, 1>;
-    using PD = Q1Phase<TX, TY, NT, 0>;
-    __shared__ T L[4][NCOL];
-    const int64_t x0 = tb.x0, y0 = tb.y0, z0 = tb.z0, z1 = tb.z1;
-    const int tid = threadIdx.x;
-    const int par = g.parity;
-
-    // columns of the region T+4 (plane loads into LDS)
-    int coff[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-        const int c = tid + NT * m;
-        const int ly = c / W, lx = c % W;
-        const int64_t x = x0 - 4 + lx, y = y0 - 4 + ly;
-        const bool ok = c < NCOL && x >= 0 && x <= g.nx + 1 && y >= 0 && y <= g.ny + 1;
-        coff[m] = ok ? (int)(y * g.sy + x) : -1;
-    }
-    int ca[PA::P], oa[PA::P], cb[PB::P], ob[PB::P], cc[PC::P], oc[PC::P], cd[PD::P], od[PD::P];
-    bool wa[PA::P], wb[PB::P], wc[PC::P], wd[PD::P];
-    q1_make_pts<TX, TY, NT, 3, PA::P>(g, x0, y0, 0, ca, oa, wa);
-    q1_make_pts<TX, TY, NT, 2, PB::P>(g, x0, y0, 1, cb, ob, wb);
-    q1_make_pts<TX, TY, NT, 1, PC::P>(g, x0, y0, 0, cc, oc, wc);
-    q1_make_pts<TX, TY, NT, 0, PD::P>(g, x0, y0, 1, cd, od, wd);
-
-    auto is_even = [&](int64_t k) { return ((k - 1 + par) & 1) == 0; };
-    const int64_t e_first = is_even(z0 - 1) ? z0 - 1 : z0;
-    const int64_t e_last = is_even(z1) ? z1 : z1 - 1;
-
-    auto load_plane = [&](int64_t k, T* v) {
-        const bool kin = k >= 0 && k <= g.nz + 1;
-        const T* sp = src + (kin ? k : 0) * g.sz;
-#pragma unroll
-        for (int m = 0; m < M; ++m) v[m] = (kin && coff[m] >= 0) ? sp[coff[m]] : T(0);
-    };
-    auto store_plane = [&](const T* v, T* lp) {
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-            const int c = tid + NT * m;
-            if (c < NCOL) lp[c] = v[m];
-        }
-    };
-
-    // prefetched planes e, e+1 and the b values of the next double step; each
-    // double step is long (five barriers), so the prefetch has completed by the
-    // time the values move into place
-    T n0[M], n1[M];
-    T ba[PA::P], bb[PB::P], bc[PC::P], bd[PD::P];
-    {
-        T t[M];
-        load_plane(e_first - 1, t);
-        store_plane(t, L[(e_first - 1) & 3]);
-    }
-    load_plane(e_first, n0);
-    load_plane(e_first + 1, n1);
-    q1_load_b<T, PA::P>(b, g, e_first, ca, oa, ba);
-    q1_load_b<T, PB::P>(b, g, e_first, cb, ob, bb);
-    q1_load_b<T, PC::P>(b, g, e_first - 1, cc, oc, bc);
-    q1_load_b<T, PD::P>(b, g, e_first - 1, cd, od, bd);
-
-    for (int64_t e = e_first; e <= e_last; e += 2) {
-        T* lm2 = L[(e - 2) & 3];
-        T* lm1 = L[(e - 1) & 3];
-        T* l0 = L[e & 3];
-        T* lp1 = L[(e + 1) & 3];
-        store_plane(n0, l0);
-        store_plane(n1, lp1);
-        T ba_n[PA::P], bb_n[PB::P], bc_n[PC::P], bd_n[PD::P];
-        const bool more = e + 2 <= e_last;
-        if (more) {
-            load_plane(e + 2, n0);
-            load_plane(e + 3, n1);
-            q1_load_b<T, PA::P>(b, g, e + 2, ca, oa, ba_n);
-            q1_load_b<T, PB::P>(b, g, e + 2, cb, ob, bb_n);
-            q1_load_b<T, PC::P>(b, g, e + 1, cc, oc, bc_n);
-            q1_load_b<T, PD::P>(b, g, e + 1, cd, od, bd_n);
-        }
-        __syncthreads();
-        const bool ab = e >= 1 && e <= g.nz;
-        const bool wr_e = e >= z0 && e < z1;
-        T* dpe = dst + (ab ? e : 0) * g.sz;
-        q1_phase<T, W, PA::P>(ab, ca, oa, wa, ba, lm1, l0, lp1, h2, dpe, wr_e);
-        __syncthreads();
-        q1_phase<T, W, PB::P>(ab, cb, ob, wb, bb, lm1, l0, lp1, h2, dpe, wr_e);
-        __syncthreads();
-        const int64_t o = e - 1;
-        const bool cdo = o >= z0 && o < z1 && o >= 1 && o <= g.nz;
-        T* dpo = dst + (cdo ? o : 0) * g.sz;
-        q1_phase<T, W, PC::P>(cdo, cc, oc, wc, bc, lm2, lm1, l0, h2, dpo, true);
-        __syncthreads();
-        q1_phase<T, W, PD::P>(cdo, cd, od, wd, bd, lm2, lm1, l0, h2, dpo, true);
-        __syncthreads();
-        if (more) {
-#pragma unroll
-            for (int i = 0; i < PA::P; ++i) ba[i] = ba_n[i];
-#pragma unroll
-            for (int i = 0; i < PB::P; ++i) bb[i] = bb_n[i];
-#pragma unroll
-            for (int i = 0; i < PC::P; ++i) bc[i] = bc_n[i];
-#pragma unroll
-            for (int i = 0; i < PD::P; ++i) bd[i] = bd_n[i];
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
 // The same 27-point sweep with two x-adjacent points per thread.  The finished
 // planes leave through LDS: the tile's rows of planes e-1 and e, final after

@@ -570,7 +570,7 @@ cs_status launch_ir_residual(int dim, int stencil, const Geo& g, const void* x, 
                              double h2, double inv_scale, const Geo& g2, void* r32, void* e32,
                              Partial* partials, double* norms, hipStream_t s)
 {
-    if (dim == 3 && stream_supported(g) && stream_supported(g2))
+    if (dim == 3 && residual3_stream_fits(g) && stream_supported(g2))
         return launch_ir_residual3(stencil, g, x, b, h2, inv_scale, g2, r32, e32, partials, norms, s);
     if (dim == 2)
         return stencil == FD ? ir_residual_t<2, FD>(g, x, b, h2, inv_scale, g2, r32, e32, partials, norms, s)
@@ -676,7 +676,7 @@ cs_status launch_residual(int dtype, int dim, int stencil, const Geo& g, const v
                           const void* b, void* r, double h2, Partial* partials,
                           double* norms, hipStream_t s)
 {
-    if (dim == 3 && stream_supported(g))
+    if (dim == 3 && residual3_stream_fits(g))
         return launch_residual3_stream(dtype, stencil, g, u, b, r, h2, partials, norms, s);
     CS_DISPATCH(residual_t, dtype, dim, stencil, g, u, b, r, h2, partials, norms, s);
 }

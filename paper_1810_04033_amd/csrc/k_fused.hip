@@ -25,8 +25,6 @@
 // are served from that XCD's L2.
 #include "cs_tiles.h"
 
-#include <stdlib.h>
-
 namespace cs {
 
 namespace {
@@ -51,17 +49,14 @@ k_fused_fd3_two(const T* __restrict__ src, T* __restrict__ dst, const T* __restr
     fd3_tile_two<T, TX, TY, NT, D, NB>(src, dst, b, g, h2, tb);
 }
 
-template <typename T, int TX, int TY, int NT, int WPE, bool PAIRS, bool ROWWISE = false>
+template <typename T, int TX, int TY, int NT, int WPE>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_fused_q1_3(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict__ b, Geo g,
              T h2, FusedWork wk)
 {
     const TileBox tb = tile_box<TX, TY>(g, wk.tiles_x, wk.tiles_y, wk.chunks,
                                         xcd_ordered_block(wk.nblocks));
-    if (PAIRS)
-        q1_3_tile_pairs<T, TX, TY, NT, ROWWISE>(src, dst, b, g, h2, tb);
-    else
-        q1_3_tile<T, TX, TY, NT>(src, dst, b, g, h2, tb);
+    q1_3_tile_pairs<T, TX, TY, NT, true>(src, dst, b, g, h2, tb);
 }
 
 // Resident workgroups of a kernel on the current device.  Callers keep the
@@ -140,36 +135,16 @@ cs_status fused_fd3_two_t(const Geo& g, const void* src, void* dst, const void* 
     return check_launch("fused 7-point double sweep");
 }
 
-template <typename T, int TX, int TY, int NT, int WPE, bool PAIRS, bool ROWWISE = false>
+template <typename T, int TX, int TY, int NT, int WPE>
 cs_status fused_q1_3_t(const Geo& g, const void* src, void* dst, const void* b, double h2,
                        hipStream_t s)
 {
-    auto kern = k_fused_q1_3<T, TX, TY, NT, WPE, PAIRS, ROWWISE>;
+    auto kern = k_fused_q1_3<T, TX, TY, NT, WPE>;
     static const int64_t resident = resident_blocks(kern, NT);
     const FusedWork wk = plan_work(resident, g, TX, TY);
     hipLaunchKernelGGL(kern, dim3((unsigned)wk.nblocks), dim3(NT), 0, s, (const T*)src, (T*)dst,
                        (const T*)b, g, (T)h2, wk);
     return check_launch("fused 27-point sweep");
-}
-
-// Tile variants of the fused kernels: COLSTEN_FUSED_VARIANT (7-point) and
-// COLSTEN_Q1_VARIANT (27-point), read once.
-int env_int(const char* name)
-{
-    const char* e = getenv(name);
-    return e ? atoi(e) : 0;
-}
-
-int fused_variant()
-{
-    static int v = env_int("COLSTEN_FUSED_VARIANT");
-    return v;
-}
-
-int q1_variant()
-{
-    static int v = env_int("COLSTEN_Q1_VARIANT");
-    return v;
 }
 
 }  // namespace
@@ -233,38 +208,14 @@ cs_status launch_fused_sweep(int dtype, int dim, int stencil, const Geo& g, cons
         set_error("fused sweep not available for this grid");
         return CS_EUNSUPPORTED;
     }
-#define CS_FD3(TX, TY, NT, D)                                                    \
-    return dtype == 0 ? fused_fd3_t<double, TX, TY, NT, D>(g, src, dst, b, h2, s) \
-                      : fused_fd3_t<float, TX, TY, NT, D>(g, src, dst, b, h2, s)
-#define CS_Q13(TX, TY, NT, WPE, PAIRS)                                                   \
-    return dtype == 0 ? fused_q1_3_t<double, TX, TY, NT, WPE, PAIRS>(g, src, dst, b, h2, s) \
-                      : fused_q1_3_t<float, TX, TY, NT, WPE, PAIRS>(g, src, dst, b, h2, s)
-    if (stencil == Q1) {
-        switch (q1_variant()) {
-        case 1: CS_Q13(64, 16, 512, 3, false);
-        case 2: CS_Q13(64, 12, 256, 3, true);
-        case 3: CS_Q13(32, 16, 128, 5, true);
-        case 4: CS_Q13(64, 8, 128, 4, true);
-        case 5: CS_Q13(128, 8, 256, 2, true);
-        case 6: CS_Q13(32, 32, 256, 3, true);
-        case 7: CS_Q13(64, 16, 256, 2, true);
-        default:
-            // the pair update row by row: FP64 with 512 threads (two
-            // workgroups of 8 waves per CU, 107 VGPRs), FP32 with 256
-            // (measured at 256^3 and 512^3)
-            return dtype == 0
-                       ? fused_q1_3_t<double, 64, 16, 512, 4, true, true>(g, src, dst, b, h2, s)
-                       : fused_q1_3_t<float, 64, 16, 256, 2, true, true>(g, src, dst, b, h2, s);
-        }
-    }
-    switch (fused_variant()) {
-    case 1: CS_FD3(64, 16, 256, 1);
-    case 2: CS_FD3(128, 16, 512, 2);
-    case 3: CS_FD3(64, 32, 512, 2);
-    default: CS_FD3(64, 16, 512, 1);
-    }
-#undef CS_FD3
-#undef CS_Q13
+    if (stencil == Q1)
+        // the pair update row by row: FP64 with 512 threads (two workgroups
+        // of 8 waves per CU, 107 VGPRs), FP32 with 256 (measured at 256^3 and
+        // 512^3)
+        return dtype == 0 ? fused_q1_3_t<double, 64, 16, 512, 4>(g, src, dst, b, h2, s)
+                          : fused_q1_3_t<float, 64, 16, 256, 2>(g, src, dst, b, h2, s);
+    return dtype == 0 ? fused_fd3_t<double, 64, 16, 512, 1>(g, src, dst, b, h2, s)
+                      : fused_fd3_t<float, 64, 16, 512, 1>(g, src, dst, b, h2, s);
 }
 
 }  // namespace cs

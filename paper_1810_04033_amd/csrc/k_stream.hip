@@ -873,6 +873,15 @@ bool stream_supported(const Geo& g)
     return (g.ny + 2) * g.sy < ((int64_t)1 << 31);
 }
 
+// The streaming residual keeps one partial per workgroup, at most
+// kMaxResidualBlocks of them, and needs one 64 x 8 tile per workgroup at
+// least; larger planes take the generic residual, which clamps its grid.
+bool residual3_stream_fits(const Geo& g)
+{
+    const int64_t tiles = ((g.nx + 63) / 64) * ((g.ny + 7) / 8);
+    return stream_supported(g) && tiles <= kMaxResidualBlocks;
+}
+
 cs_status launch_jacobi3_stream(int dtype, int stencil, const Geo& g, const void* src, void* dst,
                                 const void* b, double h2, double omega, hipStream_t s)
 {

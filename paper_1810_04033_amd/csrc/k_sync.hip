@@ -193,6 +193,14 @@ __device__ inline int colour_of(int64_t i, int64_t j, int64_t k, int parity)
     return px + 2 * py + 4 * pz;
 }
 
+// Clears the barrier's arrival count before a persistent launch: a barrier
+// whose wait gave up leaves the count out of step with the generation, and the
+// next launch must not inherit that.  The generation word may start anywhere.
+__global__ void k_barrier_reset(unsigned* bar)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) bar[0] = 0u;
+}
+
 __global__ void k_dep_reset(unsigned* bar, int64_t ntiles)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -332,6 +340,9 @@ cs_status sync_sweeps_t(const Geo& g, void* u, const void* b, double h2, int nsw
     int64_t blocks = (pts / 2 + kSyncThreads - 1) / kSyncThreads;
     if (blocks > resident) blocks = resident;
     if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_barrier_reset, dim3(1), dim3(64), 0, s, bar);
+    cs_status st = check_launch("barrier reset");
+    if (st != CS_OK) return st;
     Geo gg = g;
     T h2t = (T)h2;
     int ns = nsweeps;

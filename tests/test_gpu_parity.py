@@ -161,10 +161,12 @@ def test_config_2d_poisson_256():
 
 @pytest.mark.parametrize("st", [C.CS_FD, C.CS_Q1])
 def test_config_3d_poisson_256_full_size(st):
-    """3D 256^3 interior, h = 1/257, seed-2 uniform RHS, u0 = 0: two GS sweeps
-    in the benchmark's launch configuration (work array given; one double pass
-    for red-black), two Jacobi sweeps (one double pass) and the residual,
-    compared element by element with the oracle: the iterates bit for bit."""
+    """3D 256^3 interior, h = 1/257, seed-2 uniform RHS, u0 = 0, in the
+    benchmark's launch configuration (work array given): four GS sweeps (for
+    red-black two double passes of the fused double sweep over four z-chunks;
+    for the 27-point stencil four single passes), two Jacobi sweeps (one
+    double pass) and the residual, compared element by element with the
+    oracle: the iterates bit for bit."""
     n, h = 256, 1.0 / 257
     b = I.halo_array(I.uniform_field(2, (n, n, n)))
     bg = G.upload(b)
@@ -172,10 +174,11 @@ def test_config_3d_poisson_256_full_size(st):
     ug = G.upload(u0)
     tmp = C.grid_like(ug)
     g = C.Grid(ug, bg, dim=3, stencil=st, h=h)
-    g.gs(2, tmp=tmp)
+    assert g.sweeps_per_pass() == (2 if st == C.CS_FD else 1)
+    g.gs(4, tmp=tmp)
     got_norms = g.residual().cpu().numpy()
     uo = u0.copy()
-    O.gs_sweeps(uo, b, 2, dim=3, stencil=st, h=h)
+    O.gs_sweeps(uo, b, 4, dim=3, stencil=st, h=h)
     assert np.array_equal(G.download(ug), uo)
     np.testing.assert_allclose(got_norms, O.residual(uo, b, dim=3, stencil=st, h=h), rtol=1e-12)
     uj = I.halo_array(np.zeros((n, n, n)))
@@ -184,3 +187,32 @@ def test_config_3d_poisson_256_full_size(st):
     gj.jacobi(2.0 / 3.0, 2, tmp)
     O.jacobi_sweeps(uj, b, 2, 2.0 / 3.0, dim=3, stencil=st, h=h)
     assert np.array_equal(G.download(ujg), uj)
+
+
+@pytest.mark.parametrize("st", [C.CS_FD, C.CS_Q1])
+def test_residual_on_planes_beyond_the_streaming_grid(st):
+    """A 1100 x 1100 x 4 grid needs more 64 x 8 plane tiles than the streaming
+    residual keeps partials for; cs_residual and cs_ir_residual take the
+    generic kernels there and still match the oracle."""
+    n = (1100, 1100, 4)
+    u, b = G.case(3, n, seed=710)
+    h = 1.0 / 1101
+    norms, r = O.residual(u, b, dim=3, stencil=st, h=h, want_r=True)
+    ug, bg = G.upload(u), G.upload(b)
+    rg = C.grid_like(ug)
+    g = C.Grid(ug, bg, dim=3, stencil=st, h=h)
+    got = g.residual(r=rg).cpu().numpy()
+    assert G.relmax(O.interior(G.download(rg)), O.interior(r)) <= 1e-13
+    np.testing.assert_allclose(got, norms, rtol=1e-12, atol=0)
+    e = C.empty_grid(n, dtype=torch.float32)
+    r32 = C.empty_grid(n, dtype=torch.float32)
+    e.fill_(1.0)
+    g32 = C.Grid(e, r32, dim=3, stencil=st, h=h)
+    scale = 2.0 ** np.ceil(np.log2(np.max(np.abs(r))))
+    nrm = torch.zeros(3, dtype=torch.float64, device="cuda")
+    C.cs_ir_residual(g.handle, g32.handle, float(scale), nrm.data_ptr())
+    np.testing.assert_allclose(nrm.cpu().numpy(), norms, rtol=1e-12, atol=0)
+    want32 = (O.interior(r) / scale).astype(np.float32)
+    got32 = O.interior(G.download(r32))
+    assert np.max(np.abs(got32 - want32)) <= 2.0 ** -23
+    assert np.all(O.interior(G.download(e)) == 0.0)

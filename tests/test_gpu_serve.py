@@ -40,3 +40,34 @@ def test_mixed_stream_converges_and_is_mix_independent():
         a = alone[r.rid]
         assert a.sweeps == done[r.rid].sweeps
         assert np.array_equal(a.result, done[r.rid].result)
+
+
+def test_workload_sizes_stream_is_mix_independent():
+    """32 requests drawn as the serving workload draws them (edges log-uniform
+    in [16, 128], aspect <= 4, both stencils, FP64 and refinement): every one
+    converges under the oracle's FP64 residual, and for each of the four
+    (stencil, precision) classes the request with the widest x extent -- all in
+    the large tile class, several with an edge above 64 -- gives the same
+    sweeps and the same iterate, bit for bit, alone and in the mix."""
+    reqs = I.request_stream(21, 32, 2000.0)
+    probes = []
+    for cls in ((0, False), (0, True), (1, False), (1, True)):
+        members = [r for r in reqs if (r.stencil, r.mixed) == cls]
+        assert members
+        probes.append(max(members, key=lambda r: r.n[0]))
+    assert all(p.n[0] > 40 for p in probes)
+    assert sum(max(p.n) > 64 for p in probes) >= 3
+    done, sch = _serve(reqs, k=20, budget=4 << 30, max_active=64)
+    assert all(t.status == SV.DONE for t in done.values())
+    assert sch.stats.max_active > 8
+    for r in reqs:
+        t = done[r.rid]
+        nx, ny, nz = r.n
+        b = I.halo_array(I.uniform_field(r.rhs_seed, (nz, ny, nx)))
+        nr = O.residual(t.result, b, dim=3, stencil=r.stencil, h=1.0 / (max(r.n) + 1))
+        assert nr[0] / nr[2] <= 1e-8
+    for r in probes:
+        alone, _ = _serve([I.Request(r.rid, 0.0, r.n, r.stencil, r.mixed, r.rhs_seed)], k=20)
+        a = alone[r.rid]
+        assert a.sweeps == done[r.rid].sweeps
+        assert np.array_equal(a.result, done[r.rid].result)
