@@ -227,6 +227,25 @@ cs_status cs_apply(cs_grid g, void* y, int32_t cellwise, void* stream);
  * Errors: CS_EINVAL when r and norms are both NULL or either is bad. */
 cs_status cs_residual(cs_grid g, void* r, double* norms, void* stream);
 
+/* The residual of cs_residual for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no grid handle, no allocation, no host synchronisation.  desc,
+ * u, b, r and norms mean what they mean for cs_grid_create and cs_residual
+ * (u, b and r device arrays of desc's layout and dtype, r may be NULL, norms
+ * may be NULL but not both), validated the same way; the values and their bits
+ * equal cs_residual's on a grid of the same descriptor.  The first-stage
+ * partial sums live in a fixed array of the library in device memory
+ * (2048 x 24 bytes per device, held until the process ends), looked up once per
+ * device on the first call made with that device current.  Every grid size the
+ * descriptor rules accept fits it: the first reduction stage never uses more
+ * than 2048 partials.  Calls that overlap on one device share that array and
+ * race; calls on one stream, or otherwise ordered, do not.
+ * Errors: as cs_residual, plus CS_EINVAL for a bad descriptor or array,
+ * CS_EUNSUPPORTED for a device ordinal of 64 or more, CS_EHIP if the array's
+ * address cannot be looked up. */
+cs_status cs_residual_noalloc(const cs_grid_desc* desc, const void* u, const void* b, void* r,
+                              double* norms, void* stream);
+
 /* ---- Multigrid grid transfers -------------------------------------------
  * A geometric multigrid V-cycle whose smoother is the coloured Gauss-Seidel
  * sweep (the paper names multigrid as the setting its smoothers serve,

@@ -62,6 +62,8 @@ _SIGS = {
     "cs_jacobi_sweeps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32,
                                         ctypes.c_void_p, ctypes.c_void_p]),
     "cs_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cs_residual_noalloc": (ctypes.c_int, [ctypes.POINTER(cs_grid_desc), ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "cs_fill_uniform": (ctypes.c_int, [ctypes.POINTER(cs_grid_desc), ctypes.c_void_p, ctypes.c_uint64,
                                        ctypes.c_void_p]),
     "cs_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
@@ -228,6 +230,11 @@ def cs_jacobi_sweeps(handle, omega, nsweeps, u_tmp_ptr, stream=None):
 def cs_residual(handle, r_ptr, norms_ptr, stream=None):
     _check(lib().cs_residual(ctypes.c_void_p(handle), ctypes.c_void_p(r_ptr), ctypes.c_void_p(norms_ptr),
                              _stream(stream)))
+
+
+def cs_residual_noalloc(desc, u_ptr, b_ptr, r_ptr, norms_ptr, stream=None):
+    _check(lib().cs_residual_noalloc(ctypes.byref(desc), ctypes.c_void_p(u_ptr), ctypes.c_void_p(b_ptr),
+                                     ctypes.c_void_p(r_ptr), ctypes.c_void_p(norms_ptr), _stream(stream)))
 
 
 def cs_ir_residual(h64, h32, scale, norms_ptr, stream=None):

@@ -135,6 +135,11 @@ cs_status validate_desc_pub(const cs_grid_desc* d)
     return validate_desc(d);
 }
 
+int64_t span_of_pub(const cs_grid_desc& d)
+{
+    return span_of(d);
+}
+
 }  // namespace cs
 
 using namespace cs;

@@ -7,11 +7,6 @@
 
 #include "cs_batch.h"
 
-namespace cs {
-cs_status check_device_range_pub(const void* p, size_t bytes, size_t align, const char* name);
-cs_status validate_desc_pub(const cs_grid_desc* d);
-}  // namespace cs
-
 using namespace cs;
 
 namespace {

@@ -37,6 +37,10 @@ struct Partial {
 constexpr int kMaxResidualBlocks = 2048;
 
 void set_error(const char* fmt, ...);
+// Argument checks shared by the create calls (api.hip).
+cs_status check_device_range_pub(const void* p, size_t bytes, size_t align, const char* name);
+cs_status validate_desc_pub(const cs_grid_desc* d);
+int64_t span_of_pub(const cs_grid_desc& d);
 cs_status hip_fail(hipError_t e, const char* what);
 // Maps the last launch error to CS_EHIP (and records it); CS_OK otherwise.
 cs_status check_launch(const char* what);
