@@ -380,8 +380,10 @@ def run_patches(a):
 
     value = pts * sweeps / (ms * 1e-3) / 1e9
     # bytes moved per sweep: 24 per point of a patch swept one sweep per pass,
-    # 12 per point of a patch whose sweeps run two per pass
-    bytes_per_sweep = sum(24 * e ** 3 // k for e, k in zip(edges, per_pass))
+    # 12 per point of a patch whose sweeps run two per pass, 24 / sweeps per
+    # point of a patch swept resident in LDS (all sweeps in one pass)
+    per_pass = [k if k else sweeps for k in per_pass]
+    bytes_per_sweep = sum(24 * e ** 3 / k for e, k in zip(edges, per_pass))
     paired_pts = sum(e ** 3 for e, k in zip(edges, per_pass) if k == 2)
     achieved = bytes_per_sweep / (ms * 1e-3 / sweeps) / 1e9
     out = {

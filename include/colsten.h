@@ -307,16 +307,22 @@ cs_status cs_batch_create(const cs_grid_desc* descs, void* const* u, const void*
                           void* const* tmp, int32_t count, cs_batch* out);
 cs_status cs_batch_destroy(cs_batch bt);
 
-/* nsweeps Gauss-Seidel sweeps of every patch (colours in canonical order),
- * each patch reading its u / tmp alternately; the result ends in u (one copy
- * back where a patch's last pass wrote tmp).  Patches of the large 7-point
- * tile class run two red-black sweeps per pass (an odd last sweep alone); the
- * iterate is the same, rounded identically.  The halo of every tmp is
- * overwritten with u's. */
+/* nsweeps Gauss-Seidel sweeps of every patch (colours in canonical order).
+ * Patches small enough to live in one workgroup's LDS (by default up to about
+ * 24^3 in FP64 and 32^3 in FP32, see cs_batch_resident_policy) run all nsweeps
+ * sweeps in one launch, one workgroup per patch, the patch loaded once,
+ * swept colour by colour in LDS with a workgroup barrier after each colour,
+ * and written back to u.  The other patches read their u / tmp alternately,
+ * one launch per tile group and pass; the result ends in u (one copy back
+ * where a patch's last pass wrote tmp).  Patches of the large 7-point tile
+ * class run two red-black sweeps per pass (an odd last sweep alone).  Every
+ * schedule gives the same iterate, rounded identically.  The halo of every
+ * tmp of a tiled patch is overwritten with u's. */
 cs_status cs_batch_gs_sweeps(cs_batch bt, int32_t nsweeps, void* stream);
 
 /* *out = sweeps per pass over memory (1 or 2) of patch index (the caller's
- * order) in cs_batch_gs_sweeps.  Errors: CS_EINVAL (NULL, index out of
+ * order) in cs_batch_gs_sweeps, or 0 for a patch swept resident in LDS (all
+ * sweeps of a call in one pass).  Errors: CS_EINVAL (NULL, index out of
  * range). */
 cs_status cs_batch_sweeps_per_pass(cs_batch bt, int32_t index, int32_t* out);
 
@@ -339,6 +345,14 @@ cs_status cs_batch_tile_policy(int32_t stencil, int32_t dtype, int32_t small_max
  * either way.  Set by the autotuner.  Errors: CS_EINVAL for a bad stencil or
  * dtype, or pair_large not 0/1. */
 cs_status cs_batch_pass_policy(int32_t stencil, int32_t dtype, int32_t pair_large);
+
+/* Resident schedule for batches created afterwards (process-wide, per stencil
+ * and dtype): enable = 1 (default) sweeps every patch that fits one
+ * workgroup's LDS and registers resident there (all sweeps of a call in one
+ * launch), 0 sends every patch to the tile kernels; the iterate is the same
+ * either way.  Set by the autotuner.  Errors: CS_EINVAL for a bad stencil or
+ * dtype, or enable not 0/1. */
+cs_status cs_batch_resident_policy(int32_t stencil, int32_t dtype, int32_t enable);
 
 /* ---- Captured sweep sequences (HIP graphs) -------------------------------
  * A fixed number of sweeps recorded once into a HIP graph and replayed with

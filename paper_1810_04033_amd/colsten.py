@@ -86,6 +86,7 @@ _SIGS = {
     "cs_batch_sweeps_per_pass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "cs_batch_tile_policy": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "cs_batch_pass_policy": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "cs_batch_resident_policy": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "cs_graph_gs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_void_p)]),
     "cs_graph_batch_gs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
@@ -296,6 +297,11 @@ def cs_batch_sweeps_per_pass(handle, index):
 def cs_batch_pass_policy(stencil, dtype, pair_large):
     _check(lib().cs_batch_pass_policy(ctypes.c_int32(stencil), ctypes.c_int32(dtype),
                                       ctypes.c_int32(int(pair_large))))
+
+
+def cs_batch_resident_policy(stencil, dtype, enable):
+    _check(lib().cs_batch_resident_policy(ctypes.c_int32(stencil), ctypes.c_int32(dtype),
+                                          ctypes.c_int32(int(enable))))
 
 
 def cs_batch_tile_policy(stencil, dtype, small_max, mid_max):

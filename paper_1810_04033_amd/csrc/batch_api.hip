@@ -13,6 +13,7 @@ namespace {
 
 struct Group {
     int dtype = 0, stencil = 0, variant = 0;
+    int tier = 0;        // LDS-resident tier (1, 2), or 0 for the tile kernels
     bool pairs = false;  // two sweeps per launch
     std::vector<BatchPatch> host;
     BatchPatch* dev = nullptr;
@@ -23,6 +24,7 @@ struct Group {
 int g_small_max[2][2] = {{16, 16}, {16, 16}};
 int g_mid_max[2][2] = {{40, 40}, {40, 40}};
 int g_pair_large[2][2] = {{1, 1}, {1, 1}};  // pair the sweeps of the large tile class
+int g_resident[2][2] = {{1, 1}, {1, 1}};    // sweep patches that fit in LDS there
 
 int pick_variant(int stencil, int dtype, int64_t nx)
 {
@@ -80,6 +82,17 @@ cs_status cs_batch_pass_policy(int32_t stencil, int32_t dtype, int32_t pair_larg
     return CS_OK;
 }
 
+cs_status cs_batch_resident_policy(int32_t stencil, int32_t dtype, int32_t enable)
+{
+    if ((stencil != CS_FD && stencil != CS_Q1) || (dtype != CS_F64 && dtype != CS_F32) ||
+        (enable != 0 && enable != 1)) {
+        set_error("bad resident policy");
+        return CS_EINVAL;
+    }
+    g_resident[stencil][dtype] = enable;
+    return CS_OK;
+}
+
 cs_status cs_batch_create(const cs_grid_desc* descs, void* const* u, const void* const* b,
                           void* const* tmp, int32_t count, cs_batch* out)
 {
@@ -128,8 +141,9 @@ cs_status cs_batch_create(const cs_grid_desc* descs, void* const* u, const void*
         p.hh = d.h * d.h;
         p.h2 = d.dtype == CS_F32 ? (double)(float)p.hh : p.hh;
         p.index = i;
-        const int variant = pick_variant(d.stencil, d.dtype, d.n[0]);
-        const bool pairs = batch_variant_pairs(d.stencil, variant) && g_pair_large[d.stencil][d.dtype];
+        const int tier = g_resident[d.stencil][d.dtype] ? batch_resident_tier(d.dtype, d.stencil, p.g) : 0;
+        const int variant = tier ? 0 : pick_variant(d.stencil, d.dtype, d.n[0]);
+        const bool pairs = !tier && batch_variant_pairs(d.stencil, variant) && g_pair_large[d.stencil][d.dtype];
         int tx = 0, ty = 0;
         batch_variant_tile(d.stencil, variant, &tx, &ty);
         p.tiles_x = (int)((d.n[0] + tx - 1) / tx);
@@ -140,19 +154,21 @@ cs_status cs_batch_create(const cs_grid_desc* descs, void* const* u, const void*
         int k = -1;
         for (size_t j = 0; j < bt->groups.size(); ++j)
             if (bt->groups[j].dtype == d.dtype && bt->groups[j].stencil == d.stencil &&
-                bt->groups[j].variant == variant && bt->groups[j].pairs == pairs)
+                bt->groups[j].variant == variant && bt->groups[j].pairs == pairs &&
+                bt->groups[j].tier == tier)
                 k = (int)j;
         if (k < 0) {
             Group gr;
             gr.dtype = d.dtype;
             gr.stencil = d.stencil;
             gr.variant = variant;
+            gr.tier = tier;
             gr.pairs = pairs;
             bt->groups.push_back(gr);
             k = (int)bt->groups.size() - 1;
         }
         bt->groups[k].host.push_back(p);
-        bt->per_pass.push_back(pairs ? 2 : 1);
+        bt->per_pass.push_back(tier ? 0 : (pairs ? 2 : 1));
     }
     // z chunks: enough work items to fill the GPU (about 2048) when the batch
     // holds few patches, never chunks thinner than 8 planes (16 for the tile
@@ -160,8 +176,9 @@ cs_status cs_batch_create(const cs_grid_desc* descs, void* const* u, const void*
     // value: every point is computed the same way in any tile.
     int64_t total_tiles = 0;
     for (auto& gr : bt->groups)
-        for (auto& p : gr.host) total_tiles += (int64_t)p.tiles_x * p.tiles_y;
-    const int64_t want = (2048 + total_tiles - 1) / total_tiles;
+        if (!gr.tier)
+            for (auto& p : gr.host) total_tiles += (int64_t)p.tiles_x * p.tiles_y;
+    const int64_t want = total_tiles > 0 ? (2048 + total_tiles - 1) / total_tiles : 1;
     for (auto& gr : bt->groups) {
         const int depth = gr.pairs ? 16 : 8;
         for (auto& p : gr.host)
@@ -175,7 +192,7 @@ cs_status cs_batch_create(const cs_grid_desc* descs, void* const* u, const void*
         int64_t it = 0, rit = 0;
         for (auto& p : gr.host) {
             p.item_begin = it;
-            it += (int64_t)p.tiles_x * p.tiles_y * p.chunks;
+            it += gr.tier ? 1 : (int64_t)p.tiles_x * p.tiles_y * p.chunks;
             p.res_begin = rit;
             rit += p.res_items;
         }
@@ -208,8 +225,15 @@ cs_status cs_batch_gs_sweeps(cs_batch bt, int32_t nsweeps, void* stream)
     if (nsweeps == 0) return CS_OK;
     hipStream_t s = (hipStream_t)stream;
     cs_status st;
+    // LDS-resident groups: every sweep in one launch, in place in u
     for (auto& gr : bt->groups)
-        if ((st = launch_batch_halo(gr.dtype, gr.dev, (int)gr.host.size(), s)) != CS_OK) return st;
+        if (gr.tier &&
+            (st = launch_batch_resident(gr.dtype, gr.stencil, gr.tier, gr.dev, (int)gr.host.size(),
+                                        nsweeps, s)) != CS_OK)
+            return st;
+    for (auto& gr : bt->groups)
+        if (!gr.tier && (st = launch_batch_halo(gr.dtype, gr.dev, (int)gr.host.size(), s)) != CS_OK)
+            return st;
     // Each launch reads u (phase 0) or tmp (phase 1) and writes the other; a
     // group whose sweeps run two per launch flips less often, so the copy back
     // into u is decided per group.
@@ -218,6 +242,7 @@ cs_status cs_batch_gs_sweeps(cs_batch bt, int32_t nsweeps, void* stream)
         const bool pair = nsweeps - it >= 2;
         for (size_t gi = 0; gi < bt->groups.size(); ++gi) {
             Group& gr = bt->groups[gi];
+            if (gr.tier) continue;
             const bool two = gr.pairs;
             if (two && !pair) continue;
             const int runs = (two || !pair) ? 1 : 2;

@@ -28,6 +28,13 @@ void batch_variant_tile(int stencil, int variant, int* tx, int* ty);
 bool batch_variant_pairs(int stencil, int variant);
 cs_status launch_batch_sweep(int dtype, int stencil, int variant, const BatchPatch* tab, int count,
                              int64_t items, int phase, bool two, hipStream_t s);
+// Resident tier of a patch: 1 (small) or 2 (large) when the whole patch fits
+// one workgroup's LDS and registers, else 0.
+int batch_resident_tier(int dtype, int stencil, const Geo& g);
+// All nsweeps sweeps of every patch of a resident group in one launch, one
+// workgroup per patch, in place in u.
+cs_status launch_batch_resident(int dtype, int stencil, int tier, const BatchPatch* tab, int count,
+                                int nsweeps, hipStream_t s);
 cs_status launch_batch_halo(int dtype, const BatchPatch* tab, int count, hipStream_t s);
 cs_status launch_batch_copyback(int dtype, const BatchPatch* tab, int count, int64_t res_items,
                                 hipStream_t s);

@@ -77,6 +77,95 @@ k_batch_q1_3(const BatchPatch* __restrict__ tab, int count, int phase)
     q1_3_tile_pairs<T, TX, TY, NT, ROWWISE>(src, dst, (const T*)P.b, P.g, (T)P.h2, tb);
 }
 
+// All sweeps of a small patch in one workgroup with the patch resident in
+// LDS: the halo'd box of u is loaded once, every colour phase updates its
+// points in place in LDS with a workgroup barrier after it, and the interior
+// goes back to u after the last sweep -- one launch and one trip through HBM
+// for all sweeps.  A phase is one colour for red-black and, for the 27-point
+// stencil, the two colours {2m, 2m+1}, which differ only in x parity and so
+// never read each other (zero face weights): running them together is
+// running them one after the other.  Each thread keeps the LDS offsets and the
+// right-hand-side values of its points of every phase in registers (at most
+// PMAX per phase; the host admits only patches that fit).  The point update is
+// the colour pass's, so the iterate equals the colour passes' bit for bit.
+template <typename T, int ST, int NT, int CAP, int PMAX>
+__global__ void __launch_bounds__(NT)
+k_batch_resident(const BatchPatch* __restrict__ tab, int nsweeps)
+{
+    constexpr int NPH = ST == FD ? 2 : 4;
+    __shared__ T L[CAP];
+    const BatchPatch P = tab[blockIdx.x];
+    const Geo& g = P.g;
+    const int nx = (int)g.nx, ny = (int)g.ny, nz = (int)g.nz;
+    const int wx = nx + 2, lsz = wx * (ny + 2), total = lsz * (nz + 2);
+    T* u = (T*)P.u;
+    const T* __restrict__ b = (const T*)P.b;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < total; t += NT) {
+        const int k = t / lsz, r = t - k * lsz, j = r / wx, i = r - j * wx;
+        L[t] = u[k * g.sz + j * g.sy + i];
+    }
+    int off[NPH][PMAX];
+    T bv[NPH][PMAX];
+#pragma unroll
+    for (int ph = 0; ph < NPH; ++ph) {
+#pragma unroll
+        for (int sl = 0; sl < PMAX; ++sl) {
+            const int w = tid + NT * sl;
+            int i = 0, j = 0, k = 0;
+            bool ok;
+            if (ST == FD) {
+                const int cx = (nx + 1) / 2;
+                ok = w < cx * ny * nz;
+                if (ok) {
+                    const int m = w % cx, row = w / cx;
+                    j = 1 + row % ny;
+                    k = 1 + row / ny;
+                    i = 1 + ((ph + (j - 1) + (k - 1) + g.parity) & 1) + 2 * m;
+                    ok = i <= nx;
+                }
+            } else {
+                const int j0 = 1 + (((ph & 1) + g.parity) & 1);
+                const int k0 = 1 + (((ph >> 1) + g.parity) & 1);
+                const int ry = (ny - j0) / 2 + 1, rz = (nz - k0) / 2 + 1;
+                ok = j0 <= ny && k0 <= nz && w < nx * ry * rz;
+                if (ok) {
+                    i = 1 + w % nx;
+                    j = j0 + 2 * ((w / nx) % ry);
+                    k = k0 + 2 * (w / (nx * ry));
+                }
+            }
+            off[ph][sl] = ok ? k * lsz + j * wx + i : -1;
+            bv[ph][sl] = ok ? b[k * g.sz + j * g.sy + i] : T(0);
+        }
+    }
+    __syncthreads();
+    const T h2 = (T)P.h2;
+    for (int sw = 0; sw < nsweeps; ++sw) {
+#pragma unroll
+        for (int ph = 0; ph < NPH; ++ph) {
+#pragma unroll
+            for (int sl = 0; sl < PMAX; ++sl) {
+                int q = off[ph][sl];
+                if (q < 0) continue;
+                T bq = bv[ph][sl];
+                // opaque to the compiler, so it does not hoist each point's
+                // neighbour addresses and h^2 b out of the sweep loop (that
+                // keeps them all live at once and spills)
+                asm volatile("" : "+v"(q), "+v"(bq));
+                auto ld = [&](int ox, int oy, int oz) { return L[q + oz * lsz + oy * wx + ox]; };
+                L[q] = gs_value<T, 3, ST>(h2, bq, ld);
+            }
+            __syncthreads();
+        }
+    }
+    const int inner = nx * ny * nz;
+    for (int t = tid; t < inner; t += NT) {
+        const int i = 1 + t % nx, row = t / nx, j = 1 + row % ny, k = 1 + row / ny;
+        u[k * g.sz + j * g.sy + i] = L[k * lsz + j * wx + i];
+    }
+}
+
 // Halo copy u -> tmp, one workgroup per patch.
 template <typename T>
 __global__ void __launch_bounds__(256) k_batch_halo(const BatchPatch* __restrict__ tab)
@@ -278,6 +367,71 @@ cs_status launch_batch_sweep(int dtype, int stencil, int variant, const BatchPat
 #undef CS_BFD
 #undef CS_BQ1
     return check_launch("batched sweep");
+}
+
+// The two resident tiers: (threads, LDS elements, points per phase and
+// thread).  Small: 512 threads and 6144 elements (a 16^3 patch with its
+// halo); large: 1024 threads and up to 140.8 KB (FP64, a 24^3 patch) or
+// 160 KB (FP32, a 32^3 patch) of LDS, one workgroup per CU.
+namespace {
+constexpr int kResSmallNT = 512, kResSmallCap = 6144;
+constexpr int kResLargeNT = 1024, kResLargeCap64 = 17600, kResLargeCap32 = 40000;
+template <int ST, bool F64, bool LARGE>
+constexpr int res_pmax()
+{
+    return !LARGE ? (ST == FD ? 4 : 2) : (F64 ? (ST == FD ? 7 : 4) : (ST == FD ? 16 : 8));
+}
+bool res_fits(int stencil, const Geo& g, int nt, int cap, int pmax)
+{
+    const int64_t elems = (g.nx + 2) * (g.ny + 2) * (g.nz + 2);
+    const int64_t per_phase = stencil == FD ? (g.nx + 1) / 2 * g.ny * g.nz
+                                            : g.nx * ((g.ny + 1) / 2) * ((g.nz + 1) / 2);
+    return elems <= cap && per_phase <= (int64_t)nt * pmax;
+}
+}  // namespace
+
+int batch_resident_tier(int dtype, int stencil, const Geo& g)
+{
+    const bool f64 = dtype == 0;
+    const int ps = stencil == FD ? res_pmax<FD, true, false>() : res_pmax<Q1, true, false>();
+    if (res_fits(stencil, g, kResSmallNT, kResSmallCap, ps)) return 1;
+    const int pl = f64 ? (stencil == FD ? res_pmax<FD, true, true>() : res_pmax<Q1, true, true>())
+                       : (stencil == FD ? res_pmax<FD, false, true>() : res_pmax<Q1, false, true>());
+    if (res_fits(stencil, g, kResLargeNT, f64 ? kResLargeCap64 : kResLargeCap32, pl)) return 2;
+    return 0;
+}
+
+cs_status launch_batch_resident(int dtype, int stencil, int tier, const BatchPatch* tab, int count,
+                                int nsweeps, hipStream_t s)
+{
+    if (count <= 0 || nsweeps <= 0) return CS_OK;
+    const dim3 grid((unsigned)count);
+#define CS_RES(T, ST, LARGE, CAP)                                                                 \
+    hipLaunchKernelGGL((k_batch_resident<T, ST, LARGE ? kResLargeNT : kResSmallNT, CAP,          \
+                                         res_pmax<ST, sizeof(T) == 8, LARGE>()>),               \
+                       grid, dim3(LARGE ? kResLargeNT : kResSmallNT), 0, s, tab, nsweeps)
+    if (tier == 1) {
+        if (dtype == 0) {
+            if (stencil == FD) CS_RES(double, FD, false, kResSmallCap);
+            else CS_RES(double, Q1, false, kResSmallCap);
+        } else {
+            if (stencil == FD) CS_RES(float, FD, false, kResSmallCap);
+            else CS_RES(float, Q1, false, kResSmallCap);
+        }
+    } else if (tier == 2) {
+        if (dtype == 0) {
+            if (stencil == FD) CS_RES(double, FD, true, kResLargeCap64);
+            else CS_RES(double, Q1, true, kResLargeCap64);
+        } else {
+            if (stencil == FD) CS_RES(float, FD, true, kResLargeCap32);
+            else CS_RES(float, Q1, true, kResLargeCap32);
+        }
+    } else {
+        set_error("no resident tier %d", tier);
+        return CS_EUNSUPPORTED;
+    }
+#undef CS_RES
+    return check_launch("batched resident sweeps");
 }
 
 cs_status launch_batch_halo(int dtype, const BatchPatch* tab, int count, hipStream_t s)

@@ -8,7 +8,10 @@ stencil the large tiles are timed with two sweeps per pass and with one, per
 edge and on a batch mixing (in equal counts) the edges that pick them, and the
 schedule that is faster on the mix is set with cs_batch_pass_policy (both give
 the same iterate; batches of equal patches are chunked differently from mixed
-ones, so the mix decides).  Results are cached
+ones, so the mix decides).  Last, the patches small enough to be swept
+resident in one workgroup's LDS (all sweeps in one launch) are timed that way
+and with the chosen tiles, on a mix of those edges, and the faster schedule is
+set with cs_batch_resident_policy.  Results are cached
 as JSON keyed by GPU architecture, stencil and dtype (COLSTEN_TUNE_CACHE,
 default ~/.cache/colsten_tune.json), so later processes apply them without
 re-timing.
@@ -48,10 +51,11 @@ def _time_batch(edge, stencil, dtype, variant, points_target, sweeps, pair=True)
     return _time_edges([edge], stencil, dtype, points_target, sweeps, pair)
 
 
-def _time_edges(edges, stencil, dtype, points_target, sweeps, pair):
+def _time_edges(edges, stencil, dtype, points_target, sweeps, pair, resident=False):
     """GLUP/s of a batch of cubic patches cycling through edges (equal counts)
     up to about points_target points, under the current tile policy."""
     C.cs_batch_pass_policy(stencil, C._DT[dtype], pair)
+    C.cs_batch_resident_policy(stencil, C._DT[dtype], int(resident))
     sizes, total = [], 0
     while not sizes or total < points_target:
         sizes.append(edges[len(sizes) % len(edges)])
@@ -107,7 +111,19 @@ def tune(stencil, dtype=torch.float64, edges=(8, 16, 24, 32, 48, 64), points_tar
                   % (large, "two sweeps" if p else "one sweep", mix[p]), file=sys.stderr, flush=True)
     pair = not mix or mix[True] >= mix[False]
     C.cs_batch_pass_policy(stencil, C._DT[dtype], pair)
+    # the resident schedule, on a mix of the edges it takes
+    fits = [e for e in edges if _resident_fits(e, stencil, dtype)]
+    res = {}
+    if fits:
+        for r in (True, False):
+            res[r] = _time_edges(fits, stencil, dtype, points_target, sweeps, pair, resident=r)
+            print("tune: mix of edges %s, %s: %.1f GLUP/s" % (fits, "resident" if r else "tiles", res[r]),
+                  file=sys.stderr, flush=True)
+    resident = bool(res) and res[True] >= res[False]
+    C.cs_batch_resident_policy(stencil, C._DT[dtype], int(resident))
     rec = {"small_max": small_max, "mid_max": mid_max, "pair_large": bool(pair),
+           "resident": resident,
+           "glups_resident_mix": {("resident" if r else "tiles"): round(v, 2) for r, v in res.items()},
            "glups": {str(e): [round(x, 2) for x in table[e]] for e in edges},
            "glups_large_one_sweep_per_pass": {str(e): round(single[e], 2) for e in single},
            "glups_large_mix": {("two_sweeps" if p else "one_sweep") + "_per_pass": round(v, 2)
@@ -142,4 +158,16 @@ def apply_cached(stencil, dtype=torch.float64):
     if rec:
         C.cs_batch_tile_policy(stencil, C._DT[dtype], rec["small_max"], rec["mid_max"])
         C.cs_batch_pass_policy(stencil, C._DT[dtype], rec.get("pair_large", True))
+        C.cs_batch_resident_policy(stencil, C._DT[dtype], int(rec.get("resident", True)))
     return rec
+
+
+def _resident_fits(edge, stencil, dtype):
+    """Whether a cubic patch of this edge is swept resident in LDS (asked of
+    the library through a one-patch batch)."""
+    C.cs_batch_resident_policy(stencil, C._DT[dtype], 1)
+    u = C.empty_grid((edge,) * 3, dtype=dtype)
+    bt = C.Batch([(u, C.grid_like(u), C.grid_like(u), stencil, 1.0 / (edge + 1), 0)])
+    fits = bt.sweeps_per_pass(0) == 0
+    bt.close()
+    return fits

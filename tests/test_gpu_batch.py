@@ -135,12 +135,14 @@ def test_patch_workload_4096_sampled():
 
 def test_sweeps_per_pass_by_tile_class():
     """Patches of the large 7-point tile class run two sweeps per pass, the
-    others (small and middle classes, 27-point) one; bad queries are rejected."""
+    other tiled ones (middle class, 27-point) one, and patches that fit in LDS
+    all sweeps of a call in one pass (reported as 0); bad queries are
+    rejected."""
     ps = [_patch(n, st, torch.float64, 0, seed=1700 + i)
           for i, (n, st) in enumerate([((8, 8, 8), C.CS_FD), ((64, 64, 64), C.CS_FD),
                                        ((64, 64, 64), C.CS_Q1), ((30, 30, 30), C.CS_FD)])]
     bt = _batch(ps)
-    assert [bt.sweeps_per_pass(i) for i in range(4)] == [1, 2, 1, 1]
+    assert [bt.sweeps_per_pass(i) for i in range(4)] == [0, 2, 1, 1]
     for bad in (-1, 4):
         with pytest.raises(C.ColstenError) as e:
             bt.sweeps_per_pass(bad)
@@ -165,10 +167,73 @@ def test_pass_policy_one_sweep_per_pass_same_iterate():
             bt.close()
         finally:
             C.cs_batch_pass_policy(C.CS_FD, C.CS_F64, 1)
-    assert res[1][1] == [2, 2, 1] and res[0][1] == [1, 1, 1]
+    assert res[1][1] == [2, 2, 0] and res[0][1] == [1, 1, 0]
     for a, b in zip(res[1][0], res[0][0]):
         assert np.array_equal(a, b)
     for bad in ((2, 0, 1), (0, 2, 1), (0, 0, 2)):
         with pytest.raises(C.ColstenError) as e:
             C.cs_batch_pass_policy(*bad)
         assert e.value.status == C.CS_EINVAL
+
+
+RESIDENT = [((1, 1, 1), torch.float64, 1), ((2, 3, 4), torch.float64, 1), ((8, 8, 8), torch.float64, 1),
+            ((16, 16, 16), torch.float64, 1), ((17, 16, 16), torch.float64, 2),
+            ((24, 24, 24), torch.float64, 2), ((25, 24, 24), torch.float64, 0),
+            ((12, 40, 20), torch.float64, 2), ((7, 5, 61), torch.float64, 2),
+            ((16, 16, 16), torch.float32, 1), ((31, 30, 29), torch.float32, 2),
+            ((32, 32, 32), torch.float32, 2), ((33, 32, 32), torch.float32, 0)]
+
+
+@pytest.mark.parametrize("nsw", [1, 4, 5])
+@pytest.mark.parametrize("st", [C.CS_FD, C.CS_Q1])
+def test_resident_patches_equal_tiles_and_oracle(nsw, st):
+    """Patches that fit in LDS run every sweep of a call in one launch; with
+    the resident policy off the same patches take the tile kernels.  Both give
+    the same iterate bit for bit, across the tier boundaries (16^3 small tier,
+    24^3 FP64 and 32^3 FP32 large tier, one more point along x leaves it),
+    non-cubic shapes, both parities and an odd layout, and equal the oracle."""
+    res = {}
+    for policy in (1, 0):
+        for dt in (torch.float64, torch.float32):
+            C.cs_batch_resident_policy(st, C._DT[dt], policy)
+        try:
+            ps = [_patch(n, st, dt, i % 2, seed=2100 + 5 * i + st, layout="odd" if i % 5 == 4 else "aligned")
+                  for i, (n, dt, _) in enumerate(RESIDENT)]
+            bt = _batch(ps)
+            per = [bt.sweeps_per_pass(i) for i in range(len(ps))]
+            bt.gs(nsw)
+            torch.cuda.synchronize()
+            res[policy] = ([G.download(p["ug"]) for p in ps], per, ps)
+            bt.close()
+        finally:
+            for dt in (torch.float64, torch.float32):
+                C.cs_batch_resident_policy(st, C._DT[dt], 1)
+    for i, (n, dt, tier) in enumerate(RESIDENT):
+        assert (res[1][1][i] == 0) == (tier > 0), (n, dt)
+        assert res[0][1][i] != 0
+        assert np.array_equal(res[1][0][i], res[0][0][i]), (n, dt)
+        p = res[1][2][i]
+        assert G.relmax(res[1][0][i], _oracle(p, nsw)) <= TOL[dt], (n, dt)
+    with pytest.raises(C.ColstenError):
+        C.cs_batch_resident_policy(st, 0, 2)
+
+
+def test_resident_patch_alone_equals_patch_in_mix():
+    """A resident patch gives the same bits alone and in a mix with tiled and
+    other resident patches of both stencils."""
+    probe_n, probe_seed = (20, 18, 22), 2300
+    mix = [_patch(n, st, torch.float64, 0, seed=2310 + 3 * i + st)
+           for i, n in enumerate([(8, 8, 8), (48, 48, 48), (24, 24, 24), (64, 20, 30)])
+           for st in (C.CS_FD, C.CS_Q1)]
+    for st in (C.CS_FD, C.CS_Q1):
+        probe = _patch(probe_n, st, torch.float64, 1, seed=probe_seed + st)
+        alone = _patch(probe_n, st, torch.float64, 1, seed=probe_seed + st)
+        bm = _batch(mix[:3] + [probe] + mix[3:])
+        bm.gs(7)
+        ba = _batch([alone])
+        assert ba.sweeps_per_pass(0) == 0
+        ba.gs(7)
+        torch.cuda.synchronize()
+        assert torch.equal(probe["ug"], alone["ug"])
+        bm.close()
+        ba.close()
