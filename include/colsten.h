@@ -407,9 +407,12 @@ cs_status cs_gs_fused(cs_grid g, int32_t* out);
  *     sweeps run up to 4 (red-black) or 2 (four colours) per pass.
  *   CS_PASS_ONE: one sweep per pass.
  *   CS_PASS_TWO: as CS_PASS_AUTO, but two 3D sweeps per pass wherever a kernel
- *     for it exists (3D Jacobi, fused 3D red-black), whatever the grid size.
- * A remainder of sweeps runs in smaller passes.  The 8-colour sweeps are
- * always one per pass. */
+ *     for it exists (3D Jacobi, fused 3D red-black and 8-colour), whatever the
+ *     grid size.
+ * A remainder of sweeps runs in smaller passes.  The fused 3D 8-colour sweeps
+ * run one per pass unless CS_PASS_TWO asks for two (their double pass, the
+ * second sweep trailing the first by two planes, gives the same iterate but
+ * was measured slower on MI355X). */
 typedef enum { CS_PASS_AUTO = 0, CS_PASS_ONE = 1, CS_PASS_TWO = 2 } cs_pass_mode;
 
 /* Set the grid's pass mode (a cs_pass_mode).  Errors: CS_EINVAL (bad grid or

@@ -486,7 +486,7 @@ __device__ __forceinline__ void q1_load_b_pairs(const T* __restrict__ b, const G
 template <typename T, int W, int P, bool ROWWISE>
 __device__ __forceinline__ void q1_phase_pairs(bool active, const int* pc, const T* bv,
                                                const T* lm, T* lk, const T* lp, const int* pfl,
-                                               T h2)
+                                               T h2, int maxring = 1 << 20)
 {
     // The two points of a pair form the lanes of a 2-vector: the terms with
     // ox = -1 and ox = +1 are the aligned column pairs (x-1, x) and (x+1, x+2)
@@ -500,7 +500,7 @@ __device__ __forceinline__ void q1_phase_pairs(bool active, const int* pc, const
 #pragma unroll
     for (int i = 0; i < P; ++i) {
         const int c = pc[i];
-        if (c < 0) continue;
+        if (c < 0 || (pfl[i] >> 2) > maxring) continue;
         v2 acc = {T(0), T(0)};
         if (ROWWISE) {
 #pragma unroll
@@ -702,6 +702,241 @@ __device__ __forceinline__ void q1_3_tile_pairs(const T* __restrict__ src, T* __
         step(e, ba, bb, bc, bd, ba2, bb2, bc2, bd2);
         if (e + 2 > e_last) break;
         step(e + 2, ba2, bb2, bc2, bd2, ba, bb, bc, bd);
+    }
+    if (pend_e >= 0) write_plane(slot(pend_e), dst + pend_e * g.sz);
+    if (pend_o >= 0) write_plane(slot(pend_o), dst + pend_o * g.sz);
+}
+
+// ---------------------------------------------------------------------------
+// Two 8-colour sweeps of the 27-point stencil per pass over memory.
+//
+// The second sweep trails the first: at double step e (e an even plane) the
+// eight row phases run in the order of the colour passes,
+//     A1(e) B1(e) C1(e-1) D1(e-1)  A2(e-2) B2(e-2) C2(e-3) D2(e-3)
+// (A..D as in the one-sweep body, 1 and 2 the sweep).  A2(e-2) reads the
+// first-sweep values of planes e-3..e-1, all final after D1(e-1); C2(e-3)
+// reads the second-sweep A and B rows of planes e-4 and e-2 and the first-
+// sweep D rows of its own plane, which D2 overwrites only after.  So each
+// update reads exactly the values of the sixteen colour passes, and planes e-3
+// and e-2 are final after the step.  The values are updated in place in the
+// LDS plane slots: a first-sweep value is last read before the second-sweep
+// phase of its plane overwrites it.
+//
+// Neighbouring tiles run independently, so the first sweep is recomputed on a
+// ring of 7 points around the tile T (A1 on T+7 down to D1 on T+4) and the
+// second on T+3 .. T; u is loaded on T+8.  A pair list per row type serves
+// both sweeps (the second-sweep phase skips the pairs of rows outside its
+// ring), so a point is updated by the same thread in both sweeps and its
+// right-hand side is loaded once per pass and kept in registers for two
+// steps.  Along x every phase covers the full width of T+7; values computed on
+// an x ring beyond the phase's own are never read by a value that is used.
+// Along z a chunk [z0, z1) computes first-sweep rows on the planes z0-3 ..
+// z1+2 and second-sweep rows on z0-1 .. z1, so its own planes are exact.
+// Seven plane slots: the six planes e-4 .. e+1 a step reads and one more, so
+// the finished planes e-3 and e-2 are stored by whole rows during the next
+// step.
+// ---------------------------------------------------------------------------
+template <int TX, int TY, int NT, int RING>
+struct Q1Pairs2 {
+    static constexpr int NPC = (TX + 14) / 2;             // pair columns across T+7
+    static constexpr int ROWS = (TY + 2 * RING + 1) / 2;  // rows of one type, at most
+    static constexpr int P = (ROWS * NPC + NT - 1) / NT;  // pairs per thread, at most
+};
+
+// Pairs of one row type rho on the rows of T+RING and the columns of T+7:
+// LDS index of the left point (region T+8, x0 - 8 at column 0), in-plane
+// offset, and flags: bit0/bit1 left/right point interior, bits 2.. the row's
+// ring (its distance from T along y).
+template <int TX, int TY, int NT, int RING, int P>
+__device__ __forceinline__ void q1_make_pairs2(const Geo& g, int64_t x0, int64_t y0, int rho,
+                                               int* pc, int* poff, int* pfl)
+{
+    constexpr int H = 8, W = TX + 16, NPC = (TX + 14) / 2;
+    const int ly_lo = H - RING;
+    const int rt_lo = (int)((y0 - H + ly_lo - 1 + g.parity) & 1);
+    const int first = ly_lo + ((rho - rt_lo) & 1);
+    const int nrows = (TY + 2 * RING - (first - ly_lo) + 1) / 2;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const int sidx = (int)threadIdx.x + NT * i;
+        const int row = sidx / NPC, pcol = sidx % NPC;
+        const int ly = first + 2 * row, lx = 1 + 2 * pcol;
+        const int64_t x = x0 - H + lx, y = y0 - H + ly;
+        const bool rowok = row < nrows && y >= 1 && y <= g.ny;
+        const bool in0 = rowok && x >= 1 && x <= g.nx;
+        const bool in1 = rowok && x + 1 >= 1 && x + 1 <= g.nx;
+        const int below = H - ly, above = ly - (H + TY - 1);
+        const int ring = below > 0 ? below : (above > 0 ? above : 0);
+        pc[i] = (in0 || in1) ? ly * W + lx : -1;
+        poff[i] = (in0 || in1) ? (int)(y * g.sy + x) : 0;
+        pfl[i] = (in0 ? 1 : 0) | (in1 ? 2 : 0) | (ring << 2);
+    }
+}
+
+template <typename T, int TX, int TY, int NT>
+__device__ __forceinline__ void q1_3_tile_two(const T* __restrict__ src, T* __restrict__ dst,
+                                              const T* __restrict__ b, const Geo& g, T h2,
+                                              const TileBox& tb)
+{
+    static_assert(TX % 2 == 0, "pairs need an even tile width");
+    constexpr int H = 8, W = TX + 16, HH = TY + 16, NCOL = W * HH;
+    constexpr int M = (NCOL + NT - 1) / NT;
+    using PA = Q1Pairs2<TX, TY, NT, 7>;
+    using PB = Q1Pairs2<TX, TY, NT, 6>;
+    using PC = Q1Pairs2<TX, TY, NT, 5>;
+    using PD = Q1Pairs2<TX, TY, NT, 4>;
+    constexpr int NS = 7;
+    __shared__ __attribute__((aligned(16))) T L[NS][NCOL];
+    const int64_t x0 = tb.x0, y0 = tb.y0, z0 = tb.z0, z1 = tb.z1;
+    auto slot = [&](int64_t p) -> T* {
+        const int k = (int)(p - z0 + 2 * NS) % NS;  // p >= z0 - 8
+        return (T*)__builtin_assume_aligned(L[k], 16);
+    };
+    const int tid = threadIdx.x;
+    const int par = g.parity;
+
+    // output points of the tile, whole rows per wavefront
+    constexpr int PO = (TX * TY + NT - 1) / NT;
+    static_assert(PO <= 32, "output mask is 32 bits");
+    int olds[PO], oglb[PO];
+    unsigned omask = 0;
+#pragma unroll
+    for (int i = 0; i < PO; ++i) {
+        const int p = tid + NT * i;
+        const int ty = p / TX, tx = p % TX;
+        const bool ok = p < TX * TY && x0 + tx <= g.nx && y0 + ty <= g.ny;
+        olds[i] = (H + ty) * W + H + tx;
+        oglb[i] = ok ? (int)((y0 + ty) * g.sy + x0 + tx) : 0;
+        omask |= ok ? 1u << i : 0u;
+    }
+    auto write_plane = [&](const T* lp, T* dp) {
+#pragma unroll
+        for (int i = 0; i < PO; ++i)
+            if ((omask >> i) & 1u) st_stream(dp + oglb[i], lp[olds[i]]);
+    };
+
+    int coff[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int c = tid + NT * m;
+        const int ly = c / W, lx = c % W;
+        const int64_t x = x0 - H + lx, y = y0 - H + ly;
+        const bool ok = c < NCOL && x >= 0 && x <= g.nx + 1 && y >= 0 && y <= g.ny + 1;
+        coff[m] = ok ? (int)(y * g.sy + x) : -1;
+    }
+    int ca[PA::P], oa[PA::P], fa[PA::P], cb[PB::P], ob[PB::P], fb[PB::P];
+    int cc[PC::P], oc[PC::P], fc[PC::P], cd[PD::P], od[PD::P], fd[PD::P];
+    q1_make_pairs2<TX, TY, NT, 7, PA::P>(g, x0, y0, 0, ca, oa, fa);
+    q1_make_pairs2<TX, TY, NT, 6, PB::P>(g, x0, y0, 1, cb, ob, fb);
+    q1_make_pairs2<TX, TY, NT, 5, PC::P>(g, x0, y0, 0, cc, oc, fc);
+    q1_make_pairs2<TX, TY, NT, 4, PD::P>(g, x0, y0, 1, cd, od, fd);
+
+    auto is_even = [&](int64_t k) { return ((k - 1 + par) & 1) == 0; };
+    // planes on which each sweep's rows are needed (see above)
+    auto in1 = [&](int64_t p, int64_t lo, int64_t hi) {
+        return p >= lo && p <= hi && p >= 1 && p <= g.nz;
+    };
+    const int64_t e_first = is_even(z0 - 3) ? z0 - 3 : z0 - 2;
+    const int64_t e_last = is_even(z1 - 1) ? z1 + 1 : z1 + 2;
+
+    auto load_plane = [&](int64_t k, T* v) {
+        const bool kin = k >= 0 && k <= g.nz + 1;
+        const T* sp = src + (kin ? k : 0) * g.sz;
+#pragma unroll
+        for (int m = 0; m < M; ++m) v[m] = (kin && coff[m] >= 0) ? sp[coff[m]] : T(0);
+    };
+    auto store_plane = [&](const T* v, T* lp) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int c = tid + NT * m;
+            if (c < NCOL) lp[c] = v[m];
+        }
+    };
+
+    // b of each row type for three double steps: the first sweep of this step
+    // (cur), the second sweep of this step (old, loaded two steps ago) and the
+    // next step (nxt, in flight); the loop rotates the three register sets.
+    T ba0[2 * PA::P], ba1[2 * PA::P], ba2[2 * PA::P];
+    T bb0[2 * PB::P], bb1[2 * PB::P], bb2[2 * PB::P];
+    T bc0[2 * PC::P], bc1[2 * PC::P], bc2[2 * PC::P];
+    T bd0[2 * PD::P], bd1[2 * PD::P], bd2[2 * PD::P];
+    T n0[M], n1[M];
+    {
+        T t[M];
+        for (int64_t p = e_first - 4; p < e_first; ++p) {
+            load_plane(p, t);
+            store_plane(t, slot(p));
+        }
+    }
+    load_plane(e_first, n0);
+    load_plane(e_first + 1, n1);
+    // set 0: the first step's first sweep
+    q1_load_b_pairs<T, PA::P>(b, g, e_first, oa, fa, ba0);
+    q1_load_b_pairs<T, PB::P>(b, g, e_first, ob, fb, bb0);
+    q1_load_b_pairs<T, PC::P>(b, g, e_first - 1, oc, fc, bc0);
+    q1_load_b_pairs<T, PD::P>(b, g, e_first - 1, od, fd, bd0);
+    // the second sweep starts two steps later (its first planes, e_first - 2
+    // and e_first - 3, lie below z0 - 1): nothing to load for it yet
+#pragma unroll
+    for (int i = 0; i < 2 * PA::P; ++i) ba2[i] = T(0);
+#pragma unroll
+    for (int i = 0; i < 2 * PB::P; ++i) bb2[i] = T(0);
+#pragma unroll
+    for (int i = 0; i < 2 * PC::P; ++i) bc2[i] = T(0);
+#pragma unroll
+    for (int i = 0; i < 2 * PD::P; ++i) bd2[i] = T(0);
+
+    int64_t pend_e = -1, pend_o = -1;
+    auto step = [&](int64_t e, const T* cA, const T* cB, const T* cC, const T* cD, const T* oA,
+                    const T* oB, const T* oC, const T* oD, T* nA, T* nB, T* nC, T* nD) {
+        store_plane(n0, slot(e));
+        store_plane(n1, slot(e + 1));
+        if (e + 2 <= e_last) {
+            load_plane(e + 2, n0);
+            load_plane(e + 3, n1);
+            q1_load_b_pairs<T, PA::P>(b, g, e + 2, oa, fa, nA);
+            q1_load_b_pairs<T, PB::P>(b, g, e + 2, ob, fb, nB);
+            q1_load_b_pairs<T, PC::P>(b, g, e + 1, oc, fc, nC);
+            q1_load_b_pairs<T, PD::P>(b, g, e + 1, od, fd, nD);
+        }
+        __syncthreads();
+        if (pend_e >= 0) write_plane(slot(pend_e), dst + pend_e * g.sz);
+        if (pend_o >= 0) write_plane(slot(pend_o), dst + pend_o * g.sz);
+        // first sweep: A, B on plane e; C, D on plane e-1
+        const bool ab1 = in1(e, z0 - 3, z1 + 2);
+        q1_phase_pairs<T, W, PA::P, true>(ab1, ca, cA, slot(e - 1), slot(e), slot(e + 1), fa, h2);
+        __syncthreads();
+        q1_phase_pairs<T, W, PB::P, true>(ab1, cb, cB, slot(e - 1), slot(e), slot(e + 1), fb, h2);
+        __syncthreads();
+        const bool cd1 = in1(e - 1, z0 - 2, z1 + 1);
+        q1_phase_pairs<T, W, PC::P, true>(cd1, cc, cC, slot(e - 2), slot(e - 1), slot(e), fc, h2);
+        __syncthreads();
+        q1_phase_pairs<T, W, PD::P, true>(cd1, cd, cD, slot(e - 2), slot(e - 1), slot(e), fd, h2);
+        __syncthreads();
+        // second sweep: A, B on plane e-2; C, D on plane e-3
+        const bool ab2 = in1(e - 2, z0 - 1, z1);
+        q1_phase_pairs<T, W, PA::P, true>(ab2, ca, oA, slot(e - 3), slot(e - 2), slot(e - 1), fa, h2, 3);
+        __syncthreads();
+        q1_phase_pairs<T, W, PB::P, true>(ab2, cb, oB, slot(e - 3), slot(e - 2), slot(e - 1), fb, h2, 2);
+        __syncthreads();
+        const bool cd2 = in1(e - 3, z0, z1 - 1);
+        q1_phase_pairs<T, W, PC::P, true>(cd2, cc, oC, slot(e - 4), slot(e - 3), slot(e - 2), fc, h2, 1);
+        __syncthreads();
+        q1_phase_pairs<T, W, PD::P, true>(cd2, cd, oD, slot(e - 4), slot(e - 3), slot(e - 2), fd, h2, 0);
+        __syncthreads();
+        // planes e-2 (A, B rows) and e-3 (C, D rows) are final; their slots
+        // are refilled at the top of double steps e+4 and e+2 respectively,
+        // after the write at the next step
+        pend_e = (e - 2 >= z0 && e - 2 < z1 && e - 2 >= 1 && e - 2 <= g.nz) ? e - 2 : -1;
+        pend_o = (e - 3 >= z0 && e - 3 < z1 && e - 3 >= 1 && e - 3 <= g.nz) ? e - 3 : -1;
+    };
+    // register sets rotate (cur, old, nxt): (0, 2, 1) -> (1, 0, 2) -> (2, 1, 0)
+    for (int64_t e = e_first; e <= e_last; e += 6) {
+        step(e, ba0, bb0, bc0, bd0, ba2, bb2, bc2, bd2, ba1, bb1, bc1, bd1);
+        if (e + 2 > e_last) break;
+        step(e + 2, ba1, bb1, bc1, bd1, ba0, bb0, bc0, bd0, ba2, bb2, bc2, bd2);
+        if (e + 4 > e_last) break;
+        step(e + 4, ba2, bb2, bc2, bd2, ba1, bb1, bc1, bd1, ba0, bb0, bc0, bd0);
     }
     if (pend_e >= 0) write_plane(slot(pend_e), dst + pend_e * g.sz);
     if (pend_o >= 0) write_plane(slot(pend_o), dst + pend_o * g.sz);

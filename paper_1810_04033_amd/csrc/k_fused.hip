@@ -59,6 +59,16 @@ k_fused_q1_3(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict
     q1_3_tile_pairs<T, TX, TY, NT, true>(src, dst, b, g, h2, tb);
 }
 
+template <typename T, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT)
+k_fused_q1_3_two(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict__ b, Geo g,
+                 T h2, FusedWork wk)
+{
+    const TileBox tb = tile_box<TX, TY>(g, wk.tiles_x, wk.tiles_y, wk.chunks,
+                                        xcd_ordered_block(wk.nblocks));
+    q1_3_tile_two<T, TX, TY, NT>(src, dst, b, g, h2, tb);
+}
+
 // Resident workgroups of a kernel on the current device.  Callers keep the
 // result in a static of their own template instantiation, so it is queried once
 // per kernel (the library runs on devices of one kind); a cache here would be
@@ -135,6 +145,26 @@ cs_status fused_fd3_two_t(const Geo& g, const void* src, void* dst, const void* 
     return check_launch("fused 7-point double sweep");
 }
 
+// Two 27-point sweeps per launch: a chunk computes 3 extra planes of the
+// first sweep on each side, so chunks are kept at least 16 planes deep.
+template <typename T, int TX, int TY, int NT>
+int64_t q1_two_resident()
+{
+    static const int64_t resident = resident_blocks(k_fused_q1_3_two<T, TX, TY, NT>, NT);
+    return resident;
+}
+
+template <typename T, int TX, int TY, int NT>
+cs_status fused_q1_3_two_t(const Geo& g, const void* src, void* dst, const void* b, double h2,
+                           hipStream_t s)
+{
+    auto kern = k_fused_q1_3_two<T, TX, TY, NT>;
+    const FusedWork wk = plan_work(q1_two_resident<T, TX, TY, NT>(), g, TX, TY, 16);
+    hipLaunchKernelGGL(kern, dim3((unsigned)wk.nblocks), dim3(NT), 0, s, (const T*)src, (T*)dst,
+                       (const T*)b, g, (T)h2, wk);
+    return check_launch("fused 27-point double sweep");
+}
+
 template <typename T, int TX, int TY, int NT, int WPE>
 cs_status fused_q1_3_t(const Geo& g, const void* src, void* dst, const void* b, double h2,
                        hipStream_t s)
@@ -174,14 +204,23 @@ bool fused_supported(int dtype, int dim, int stencil, const Geo& g)
 #define CS_F2_D32 2
 #define CS_F2_NB32 1
 #endif
+// Tile and threads of the 27-point double sweep (one workgroup per CU: seven
+// LDS planes of the region T+8).
+#ifndef CS_Q2_TX
+#define CS_Q2_TX 64
+#define CS_Q2_TY 16
+#define CS_Q2_NT 1024
+#endif
+
 bool fused_two_available(int dtype, int dim, int stencil, const Geo& g)
 {
-    return dim == 3 && stencil == FD && fused_supported(dtype, dim, stencil, g);
+    return dim == 3 && fused_supported(dtype, dim, stencil, g);
 }
 
 bool fused_two_preferred(int dtype, int dim, int stencil, const Geo& g)
 {
     if (!fused_two_available(dtype, dim, stencil, g)) return false;
+    if (stencil == Q1) return false;
     return dtype == 0
                ? fused_two_fills<double, CS_F2_TX, CS_F2_TY, CS_F2_NT, CS_F2_D, CS_F2_NB>(g)
                : fused_two_fills<float, CS_F2_TX32, CS_F2_TY32, CS_F2_NT32, CS_F2_D32, CS_F2_NB32>(g);
@@ -194,6 +233,9 @@ cs_status launch_fused_two(int dtype, int dim, int stencil, const Geo& g, const 
         set_error("fused double sweep not available for this grid");
         return CS_EUNSUPPORTED;
     }
+    if (stencil == Q1)
+        return dtype == 0 ? fused_q1_3_two_t<double, CS_Q2_TX, CS_Q2_TY, CS_Q2_NT>(g, src, dst, b, h2, s)
+                          : fused_q1_3_two_t<float, CS_Q2_TX, CS_Q2_TY, CS_Q2_NT>(g, src, dst, b, h2, s);
     return dtype == 0
                ? fused_fd3_two_t<double, CS_F2_TX, CS_F2_TY, CS_F2_NT, CS_F2_D, CS_F2_NB>(
                      g, src, dst, b, h2, s)
