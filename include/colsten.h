@@ -307,6 +307,48 @@ cs_status cs_batch_create(const cs_grid_desc* descs, void* const* u, const void*
                           void* const* tmp, int32_t count, cs_batch* out);
 cs_status cs_batch_destroy(cs_batch bt);
 
+/* A batch whose patches change over time without allocation or host
+ * synchronisation (the active set of a request server): cs_batch_reserve
+ * allocates, once, device tables for up to `capacity` patches, room for
+ * `partials` residual partial sums (a patch needs ceil(n[1] n[2] / 16)) and
+ * two pinned host staging buffers; the batch starts empty.  cs_batch_assign
+ * replaces its patches (same arguments and checks as cs_batch_create, plus
+ * `rows`): the tables are written into a staging buffer and copied to the
+ * device asynchronously on `stream`, so the batch must then be used on that
+ * stream (or after it).  A staging buffer is reused only once the copy that
+ * last read it has run, so an assignment waits only when two earlier ones
+ * are still queued.  rows: NULL (patch i reports in norms row i) or one
+ * distinct row >= 0 per patch, the row in the norms (and scales) arrays of
+ * cs_batch_residual and cs_batch_ir_*, so a patch keeps its row while others
+ * come and go.  Errors: CS_EINVAL (capacity or partials exceeded, bad
+ * patch, repeated row), CS_ENOMEM (reserve), CS_EHIP. */
+cs_status cs_batch_reserve(int32_t capacity, int64_t partials, cs_batch* out);
+cs_status cs_batch_assign(cs_batch bt, const cs_grid_desc* descs, void* const* u, const void* const* b,
+                          void* const* tmp, const int32_t* rows, int32_t count, void* stream);
+
+/* FP32 sweeps inside FP64 iterative refinement for every patch of an FP32
+ * batch at once (the batched form of cs_ir_residual / cs_ir_update).
+ * cs_batch_ir_attach pairs each patch of bt (in its assignment order; its u is
+ * the correction e, its b receives the scaled residual) with an FP64 patch
+ * of the same n and stencil: its iterate x and right-hand side b (descs64,
+ * any strides).  Copied asynchronously on stream like cs_batch_assign; a new
+ * assignment drops the pairing.
+ * cs_batch_ir_residual: for every patch, with row r, s = the smallest power of
+ * two >= norms[3 r + 1] (the previous max |r|; put max |b| there before the
+ * first step), scales[r] = s, then r = b - A x (FP64), r32 = fl32(r / s),
+ * e = 0 on the interior, and norms[3 r .. 3 r + 2] = ||r||_2, max |r|, ||b||_2.
+ * cs_batch_ir_update: x <- x + scales[r] * e (FP64) for every patch.
+ * One refinement step is update, residual, then m FP32 sweeps of bt
+ * (cs_batch_gs_sweeps); e = 0 makes the first update exact.  norms and scales
+ * are device arrays of 3 and 1 doubles per row.  Each patch's values are
+ * computed from its own data only, as cs_ir_residual and cs_ir_update compute
+ * them (norms summed in a different order).
+ * Errors: CS_EINVAL (mismatched patches, no pairing, bad arrays). */
+cs_status cs_batch_ir_attach(cs_batch bt, const cs_grid_desc* descs64, void* const* x,
+                             const void* const* b, void* stream);
+cs_status cs_batch_ir_residual(cs_batch bt, double* scales, double* norms, void* stream);
+cs_status cs_batch_ir_update(cs_batch bt, const double* scales, void* stream);
+
 /* nsweeps Gauss-Seidel sweeps of every patch (colours in canonical order).
  * Patches small enough to live in one workgroup's LDS (by default up to about
  * 24^3 in FP64 and 32^3 in FP32, see cs_batch_resident_policy) run all nsweeps
@@ -326,9 +368,9 @@ cs_status cs_batch_gs_sweeps(cs_batch bt, int32_t nsweeps, void* stream);
  * range). */
 cs_status cs_batch_sweeps_per_pass(cs_batch bt, int32_t index, int32_t* out);
 
-/* Per-patch residual norms: norms (device, count x 3 doubles) receives, for
- * patch i at 3*i, ||r||_2, max |r| and ||b||_2 of r = b - A u (FP64
- * arithmetic).  Each patch's reduction order depends only on its own shape,
+/* Per-patch residual norms: norms (device, 3 doubles per row) receives, for
+ * patch i at 3 * row(i) (row i unless assigned otherwise), ||r||_2, max |r| and
+ * ||b||_2 of r = b - A u (FP64 arithmetic).  Each patch's reduction order depends only on its own shape,
  * so its norms do not depend on the rest of the batch. */
 cs_status cs_batch_residual(cs_batch bt, double* norms, void* stream);
 

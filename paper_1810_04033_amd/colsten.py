@@ -81,6 +81,15 @@ _SIGS = {
                                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "cs_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "cs_batch_reserve": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_void_p)]),
+    "cs_batch_assign": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(cs_grid_desc), ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_void_p]),
+    "cs_batch_ir_attach": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(cs_grid_desc),
+                                          ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                          ctypes.c_void_p]),
+    "cs_batch_ir_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cs_batch_ir_update": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "cs_batch_gs_sweeps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "cs_batch_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "cs_batch_sweeps_per_pass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
@@ -278,6 +287,43 @@ def cs_batch_create(descs, u_ptrs, b_ptrs, tmp_ptrs):
 
 def cs_batch_destroy(handle):
     _check(lib().cs_batch_destroy(ctypes.c_void_p(handle)))
+
+
+def cs_batch_reserve(capacity, partials):
+    out = ctypes.c_void_p()
+    _check(lib().cs_batch_reserve(int(capacity), int(partials), ctypes.byref(out)))
+    return out.value
+
+
+def cs_batch_assign(handle, descs, u_ptrs, b_ptrs, tmp_ptrs, rows=None, stream=None):
+    n = len(descs)
+    arr = (cs_grid_desc * max(n, 1))(*descs)
+    vp = ctypes.c_void_p * max(n, 1)
+    r = None if rows is None else (ctypes.c_int32 * max(n, 1))(*[int(x) for x in rows])
+    _check(lib().cs_batch_assign(ctypes.c_void_p(handle), arr, vp(*u_ptrs), vp(*b_ptrs), vp(*tmp_ptrs),
+                                 r, n, _stream(stream)))
+
+
+def cs_batch_ir_attach(handle, descs64, x_ptrs, b_ptrs, stream=None):
+    n = len(descs64)
+    arr = (cs_grid_desc * max(n, 1))(*descs64)
+    vp = ctypes.c_void_p * max(n, 1)
+    _check(lib().cs_batch_ir_attach(ctypes.c_void_p(handle), arr, vp(*x_ptrs), vp(*b_ptrs), _stream(stream)))
+
+
+def cs_batch_ir_residual(handle, scales_ptr, norms_ptr, stream=None):
+    _check(lib().cs_batch_ir_residual(ctypes.c_void_p(handle), ctypes.c_void_p(scales_ptr),
+                                      ctypes.c_void_p(norms_ptr), _stream(stream)))
+
+
+def cs_batch_ir_update(handle, scales_ptr, stream=None):
+    _check(lib().cs_batch_ir_update(ctypes.c_void_p(handle), ctypes.c_void_p(scales_ptr), _stream(stream)))
+
+
+def residual_items(n):
+    """Residual partial sums a patch of interior shape n = (nx, ny, nz) needs in
+    a batch (one per 16 rows)."""
+    return (n[1] * n[2] + 15) // 16
 
 
 def cs_batch_gs_sweeps(handle, nsweeps, stream=None):

@@ -1,5 +1,5 @@
-// C ABI of the batched patches: validation, grouping, device tables and the
-// per-sweep launches.
+// C ABI of the batched patches: validation, grouping, device tables, the
+// per-sweep launches and the batched refinement steps.
 #include <algorithm>
 #include <cmath>
 #include <new>
@@ -38,23 +38,231 @@ int64_t span_of3(const cs_grid_desc& d)
     return (d.n[2] + 1) * d.stride[2] + (d.n[1] + 1) * d.stride[1] + d.n[0] + 2;
 }
 
+// Host plan of a batch: its groups (tables not yet on the device), the sweeps
+// per pass of every patch in the caller's order, the residual partials it
+// needs, the number of norm rows, and every patch in the caller's order.
+struct Plan {
+    std::vector<Group> groups;
+    std::vector<int> per_pass;
+    std::vector<BatchPatch> by_index;
+    int64_t partials = 0;
+    int rows = 0;
+};
+
+cs_status plan_batch(const cs_grid_desc* descs, void* const* u, const void* const* b,
+                     void* const* tmp, const int32_t* rows, int32_t count, Plan* pl)
+{
+    if (count < 0) { set_error("count must be >= 0"); return CS_EINVAL; }
+    if (count > 0 && (!descs || !u || !b || !tmp)) { set_error("NULL array"); return CS_EINVAL; }
+    std::vector<int32_t> seen;
+    for (int32_t i = 0; i < count; ++i) {
+        const cs_grid_desc& d = descs[i];
+        cs_status st = validate_desc_pub(&d);
+        if (st != CS_OK) return st;
+        if (d.dim != 3) { set_error("patch %d: batches hold 3D patches", i); return CS_EUNSUPPORTED; }
+        if ((d.n[1] + 2) * d.stride[1] >= ((int64_t)1 << 31)) {
+            set_error("patch %d: plane too large for 32-bit offsets", i);
+            return CS_EUNSUPPORTED;
+        }
+        const size_t elem = d.dtype == CS_F64 ? 8 : 4;
+        const size_t bytes = (size_t)span_of3(d) * elem;
+        if ((st = check_device_range_pub(u[i], bytes, elem, "patch u")) != CS_OK ||
+            (st = check_device_range_pub(b[i], bytes, elem, "patch b")) != CS_OK ||
+            (st = check_device_range_pub(tmp[i], bytes, elem, "patch tmp")) != CS_OK)
+            return st;
+        if (u[i] == tmp[i] || u[i] == b[i] || tmp[i] == b[i]) {
+            set_error("patch %d: u, b and tmp must be separate arrays", i);
+            return CS_EINVAL;
+        }
+        const int32_t row = rows ? rows[i] : i;
+        if (row < 0 || row >= (1 << 30)) { set_error("patch %d: norm row %d out of range", i, row); return CS_EINVAL; }
+        seen.push_back(row);
+        BatchPatch p{};
+        p.g.nx = d.n[0];
+        p.g.ny = d.n[1];
+        p.g.nz = d.n[2];
+        p.g.sy = d.stride[1];
+        p.g.sz = d.stride[2];
+        p.g.parity = d.parity;
+        p.u = u[i];
+        p.tmp = tmp[i];
+        p.b = b[i];
+        p.hh = d.h * d.h;
+        p.h2 = d.dtype == CS_F32 ? (double)(float)p.hh : p.hh;
+        p.index = row;
+        p.stencil = d.stencil;
+        p.dtype = d.dtype;
+        const int tier = g_resident[d.stencil][d.dtype] ? batch_resident_tier(d.dtype, d.stencil, p.g) : 0;
+        const int variant = tier ? 0 : pick_variant(d.stencil, d.dtype, d.n[0]);
+        const bool pairs = !tier && batch_variant_pairs(d.stencil, variant) && g_pair_large[d.stencil][d.dtype];
+        int tx = 0, ty = 0;
+        batch_variant_tile(d.stencil, variant, &tx, &ty);
+        p.tiles_x = (int)((d.n[0] + tx - 1) / tx);
+        p.tiles_y = (int)((d.n[1] + ty - 1) / ty);
+        p.chunks = 1;  // set below, once the batch's total tile count is known
+        p.res_items = (int)batch_residual_items(p.g);
+        int k = -1;
+        for (size_t j = 0; j < pl->groups.size(); ++j)
+            if (pl->groups[j].dtype == d.dtype && pl->groups[j].stencil == d.stencil &&
+                pl->groups[j].variant == variant && pl->groups[j].pairs == pairs &&
+                pl->groups[j].tier == tier)
+                k = (int)j;
+        if (k < 0) {
+            Group gr;
+            gr.dtype = d.dtype;
+            gr.stencil = d.stencil;
+            gr.variant = variant;
+            gr.tier = tier;
+            gr.pairs = pairs;
+            pl->groups.push_back(gr);
+            k = (int)pl->groups.size() - 1;
+        }
+        pl->groups[k].host.push_back(p);
+        pl->by_index.push_back(p);
+        pl->per_pass.push_back(tier ? 0 : (pairs ? 2 : 1));
+        pl->rows = std::max(pl->rows, row + 1);
+    }
+    std::sort(seen.begin(), seen.end());
+    if (std::adjacent_find(seen.begin(), seen.end()) != seen.end()) {
+        set_error("two patches share a norm row");
+        return CS_EINVAL;
+    }
+    // z chunks: enough work items to fill the GPU (about 2048) when the batch
+    // holds few patches, never chunks thinner than 8 planes (16 for the tile
+    // class that also runs double sweeps).  The split does not change any
+    // value: every point is computed the same way in any tile.
+    int64_t total_tiles = 0;
+    for (auto& gr : pl->groups)
+        if (!gr.tier)
+            for (auto& p : gr.host) total_tiles += (int64_t)p.tiles_x * p.tiles_y;
+    const int64_t want = total_tiles > 0 ? (2048 + total_tiles - 1) / total_tiles : 1;
+    for (auto& gr : pl->groups) {
+        const int depth = gr.pairs ? 16 : 8;
+        for (auto& p : gr.host)
+            p.chunks = (int)std::max<int64_t>(1, std::min<int64_t>(want, p.g.nz / depth));
+    }
+    int64_t partial_total = 0;
+    for (auto& gr : pl->groups) {
+        std::stable_sort(gr.host.begin(), gr.host.end(), [](const BatchPatch& a, const BatchPatch& c) {
+            return a.g.nx * a.g.ny * a.g.nz > c.g.nx * c.g.ny * c.g.nz;
+        });
+        int64_t it = 0, rit = 0;
+        for (auto& p : gr.host) {
+            p.item_begin = it;
+            it += gr.tier ? 1 : (int64_t)p.tiles_x * p.tiles_y * p.chunks;
+            p.res_begin = rit;
+            rit += p.res_items;
+        }
+        if (it > 0x7fffffff || rit > 0x7fffffff) { set_error("batch too large"); return CS_EUNSUPPORTED; }
+        gr.items = it;
+        gr.res_items = rit;
+        gr.partial_base = partial_total;
+        partial_total += rit;
+    }
+    pl->partials = partial_total;
+    return CS_OK;
+}
+
 }  // namespace
 
+// A batch owns a device table arena of `capacity` patches, a partials arena,
+// two pinned host staging buffers for each table and the events of the
+// copies out of them; the tables of an assignment are written into a staging
+// buffer and copied asynchronously, so reassigning allocates nothing.
 struct cs_batch_s {
     int count = 0;
     int device = 0;
+    int capacity = 0;
+    int rows = 0;                 // norm rows in use (largest row + 1)
+    int64_t partial_cap = 0;
     std::vector<Group> groups;
-    std::vector<int> per_pass;  // sweeps per launch of each patch (caller's order)
+    std::vector<int> per_pass;    // sweeps per launch of each patch (caller's order)
+    std::vector<BatchPatch> by_index;
+    BatchPatch* arena = nullptr;
     Partial* partials = nullptr;
+    BatchPatch* stage[2] = {nullptr, nullptr};
+    hipEvent_t staged[2] = {nullptr, nullptr};
+    int next = 0;
+    // refinement pairing (cs_batch_ir_attach): FP64 iterate and right-hand
+    // side of each patch of this (FP32) batch
+    IrPatch* ir_arena = nullptr;
+    IrPatch* ir_stage[2] = {nullptr, nullptr};
+    hipEvent_t ir_ev[2] = {nullptr, nullptr};
+    int ir_next = 0;
+    bool ir_ok = false;
+    int64_t ir_items = 0;
 };
 
 static void free_batch(cs_batch_s* bt)
 {
     if (!bt) return;
-    for (auto& gr : bt->groups)
-        if (gr.dev) (void)hipFree(gr.dev);
+    if (bt->arena) (void)hipFree(bt->arena);
     if (bt->partials) (void)hipFree(bt->partials);
+    if (bt->ir_arena) (void)hipFree(bt->ir_arena);
+    for (int i = 0; i < 2; ++i) {
+        if (bt->stage[i]) (void)hipHostFree(bt->stage[i]);
+        if (bt->ir_stage[i]) (void)hipHostFree(bt->ir_stage[i]);
+        if (bt->staged[i]) (void)hipEventDestroy(bt->staged[i]);
+        if (bt->ir_ev[i]) (void)hipEventDestroy(bt->ir_ev[i]);
+    }
     delete bt;
+}
+
+static cs_status alloc_batch(int capacity, int64_t partial_cap, cs_batch_s** out)
+{
+    *out = nullptr;
+    cs_batch_s* bt = new (std::nothrow) cs_batch_s();
+    if (!bt) { set_error("out of host memory"); return CS_ENOMEM; }
+    hipError_t e = hipGetDevice(&bt->device);
+    if (e != hipSuccess) { free_batch(bt); return hip_fail(e, "hipGetDevice"); }
+    bt->capacity = capacity;
+    bt->partial_cap = partial_cap;
+    const size_t cap = (size_t)std::max(capacity, 1);
+    e = hipMalloc((void**)&bt->arena, sizeof(BatchPatch) * cap);
+    if (e == hipSuccess) e = hipMalloc((void**)&bt->partials, sizeof(Partial) * (size_t)std::max<int64_t>(partial_cap, 1));
+    if (e == hipSuccess) e = hipMalloc((void**)&bt->ir_arena, sizeof(IrPatch) * cap);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        e = hipHostMalloc((void**)&bt->stage[i], sizeof(BatchPatch) * cap, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&bt->ir_stage[i], sizeof(IrPatch) * cap, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&bt->staged[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&bt->ir_ev[i], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_batch(bt);
+        set_error("allocation of the batch tables failed: %s", hipGetErrorString(e));
+        return CS_ENOMEM;
+    }
+    *out = bt;
+    return CS_OK;
+}
+
+// Take over a plan: its tables go through the next staging buffer (once the
+// copy that last used it has run) into the arena, asynchronously on s.
+static cs_status install_plan(cs_batch_s* bt, Plan& pl, hipStream_t s)
+{
+    const int st_i = bt->next;
+    hipError_t e = hipEventSynchronize(bt->staged[st_i]);
+    if (e != hipSuccess) return hip_fail(e, "waiting for a staging buffer");
+    size_t off = 0;
+    for (auto& gr : pl.groups) {
+        std::copy(gr.host.begin(), gr.host.end(), bt->stage[st_i] + off);
+        gr.dev = bt->arena + off;
+        off += gr.host.size();
+    }
+    if (off > 0) {
+        e = hipMemcpyAsync(bt->arena, bt->stage[st_i], sizeof(BatchPatch) * off, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipEventRecord(bt->staged[st_i], s);
+        if (e != hipSuccess) return hip_fail(e, "patch table upload");
+    }
+    bt->next ^= 1;
+    bt->groups.swap(pl.groups);
+    bt->per_pass.swap(pl.per_pass);
+    bt->by_index.swap(pl.by_index);
+    bt->count = (int)bt->per_pass.size();
+    bt->rows = pl.rows;
+    bt->ir_ok = false;
+    return CS_OK;
 }
 
 extern "C" {
@@ -99,117 +307,137 @@ cs_status cs_batch_create(const cs_grid_desc* descs, void* const* u, const void*
     if (!out) { set_error("out is NULL"); return CS_EINVAL; }
     *out = nullptr;
     if (count < 1 || !descs || !u || !b || !tmp) { set_error("empty batch or NULL array"); return CS_EINVAL; }
-    cs_batch_s* bt = new (std::nothrow) cs_batch_s();
-    if (!bt) { set_error("out of host memory"); return CS_ENOMEM; }
-    bt->count = count;
-    if (hipGetDevice(&bt->device) != hipSuccess) { free_batch(bt); return hip_fail(hipGetLastError(), "hipGetDevice"); }
-    std::vector<BatchPatch> all;
-    std::vector<int> gid;
-    for (int32_t i = 0; i < count; ++i) {
-        const cs_grid_desc& d = descs[i];
-        cs_status st = validate_desc_pub(&d);
-        if (st != CS_OK) { free_batch(bt); return st; }
-        if (d.dim != 3) { set_error("patch %d: batches hold 3D patches", i); free_batch(bt); return CS_EUNSUPPORTED; }
-        if ((d.n[1] + 2) * d.stride[1] >= ((int64_t)1 << 31)) {
-            set_error("patch %d: plane too large for 32-bit offsets", i);
-            free_batch(bt);
-            return CS_EUNSUPPORTED;
-        }
-        const size_t elem = d.dtype == CS_F64 ? 8 : 4;
-        const size_t bytes = (size_t)span_of3(d) * elem;
-        if ((st = check_device_range_pub(u[i], bytes, elem, "patch u")) != CS_OK ||
-            (st = check_device_range_pub(b[i], bytes, elem, "patch b")) != CS_OK ||
-            (st = check_device_range_pub(tmp[i], bytes, elem, "patch tmp")) != CS_OK) {
-            free_batch(bt);
-            return st;
-        }
-        if (u[i] == tmp[i] || u[i] == b[i] || tmp[i] == b[i]) {
-            set_error("patch %d: u, b and tmp must be separate arrays", i);
-            free_batch(bt);
-            return CS_EINVAL;
-        }
-        BatchPatch p{};
-        p.g.nx = d.n[0];
-        p.g.ny = d.n[1];
-        p.g.nz = d.n[2];
-        p.g.sy = d.stride[1];
-        p.g.sz = d.stride[2];
-        p.g.parity = d.parity;
-        p.u = u[i];
-        p.tmp = tmp[i];
-        p.b = b[i];
-        p.hh = d.h * d.h;
-        p.h2 = d.dtype == CS_F32 ? (double)(float)p.hh : p.hh;
-        p.index = i;
-        const int tier = g_resident[d.stencil][d.dtype] ? batch_resident_tier(d.dtype, d.stencil, p.g) : 0;
-        const int variant = tier ? 0 : pick_variant(d.stencil, d.dtype, d.n[0]);
-        const bool pairs = !tier && batch_variant_pairs(d.stencil, variant) && g_pair_large[d.stencil][d.dtype];
-        int tx = 0, ty = 0;
-        batch_variant_tile(d.stencil, variant, &tx, &ty);
-        p.tiles_x = (int)((d.n[0] + tx - 1) / tx);
-        p.tiles_y = (int)((d.n[1] + ty - 1) / ty);
-        p.chunks = 1;  // set below, once the batch's total tile count is known
-        p.res_items = (int)batch_residual_items(p.g);
-        // group key
-        int k = -1;
-        for (size_t j = 0; j < bt->groups.size(); ++j)
-            if (bt->groups[j].dtype == d.dtype && bt->groups[j].stencil == d.stencil &&
-                bt->groups[j].variant == variant && bt->groups[j].pairs == pairs &&
-                bt->groups[j].tier == tier)
-                k = (int)j;
-        if (k < 0) {
-            Group gr;
-            gr.dtype = d.dtype;
-            gr.stencil = d.stencil;
-            gr.variant = variant;
-            gr.tier = tier;
-            gr.pairs = pairs;
-            bt->groups.push_back(gr);
-            k = (int)bt->groups.size() - 1;
-        }
-        bt->groups[k].host.push_back(p);
-        bt->per_pass.push_back(tier ? 0 : (pairs ? 2 : 1));
-    }
-    // z chunks: enough work items to fill the GPU (about 2048) when the batch
-    // holds few patches, never chunks thinner than 8 planes (16 for the tile
-    // class that also runs double sweeps).  The split does not change any
-    // value: every point is computed the same way in any tile.
-    int64_t total_tiles = 0;
-    for (auto& gr : bt->groups)
-        if (!gr.tier)
-            for (auto& p : gr.host) total_tiles += (int64_t)p.tiles_x * p.tiles_y;
-    const int64_t want = total_tiles > 0 ? (2048 + total_tiles - 1) / total_tiles : 1;
-    for (auto& gr : bt->groups) {
-        const int depth = gr.pairs ? 16 : 8;
-        for (auto& p : gr.host)
-            p.chunks = (int)std::max<int64_t>(1, std::min<int64_t>(want, p.g.nz / depth));
-    }
-    int64_t partial_total = 0;
-    for (auto& gr : bt->groups) {
-        std::stable_sort(gr.host.begin(), gr.host.end(), [](const BatchPatch& a, const BatchPatch& c) {
-            return a.g.nx * a.g.ny * a.g.nz > c.g.nx * c.g.ny * c.g.nz;
-        });
-        int64_t it = 0, rit = 0;
-        for (auto& p : gr.host) {
-            p.item_begin = it;
-            it += gr.tier ? 1 : (int64_t)p.tiles_x * p.tiles_y * p.chunks;
-            p.res_begin = rit;
-            rit += p.res_items;
-        }
-        if (it > 0x7fffffff || rit > 0x7fffffff) { set_error("batch too large"); free_batch(bt); return CS_EUNSUPPORTED; }
-        gr.items = it;
-        gr.res_items = rit;
-        gr.partial_base = partial_total;
-        partial_total += rit;
-        hipError_t e = hipMalloc((void**)&gr.dev, sizeof(BatchPatch) * gr.host.size());
-        if (e != hipSuccess) { (void)hipGetLastError(); set_error("hipMalloc of the patch table failed"); free_batch(bt); return CS_ENOMEM; }
-        e = hipMemcpy(gr.dev, gr.host.data(), sizeof(BatchPatch) * gr.host.size(), hipMemcpyHostToDevice);
-        if (e != hipSuccess) { cs_status s2 = hip_fail(e, "patch table upload"); free_batch(bt); return s2; }
-    }
-    hipError_t e = hipMalloc((void**)&bt->partials, sizeof(Partial) * (size_t)partial_total);
-    if (e != hipSuccess) { (void)hipGetLastError(); set_error("hipMalloc of the batch partials failed"); free_batch(bt); return CS_ENOMEM; }
+    Plan pl;
+    cs_status st = plan_batch(descs, u, b, tmp, nullptr, count, &pl);
+    if (st != CS_OK) return st;
+    cs_batch_s* bt = nullptr;
+    if ((st = alloc_batch(count, pl.partials, &bt)) != CS_OK) return st;
+    if ((st = install_plan(bt, pl, nullptr)) != CS_OK) { free_batch(bt); return st; }
+    hipError_t e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) { free_batch(bt); return hip_fail(e, "patch table upload"); }
     *out = bt;
     return CS_OK;
+}
+
+cs_status cs_batch_reserve(int32_t capacity, int64_t partials, cs_batch* out)
+{
+    if (!out) { set_error("out is NULL"); return CS_EINVAL; }
+    *out = nullptr;
+    if (capacity < 1 || capacity > (1 << 24) || partials < 1 || partials > ((int64_t)1 << 31)) {
+        set_error("capacity must lie in [1, 2^24] and partials in [1, 2^31]");
+        return CS_EINVAL;
+    }
+    cs_batch_s* bt = nullptr;
+    cs_status st = alloc_batch(capacity, partials, &bt);
+    if (st != CS_OK) return st;
+    *out = bt;
+    return CS_OK;
+}
+
+cs_status cs_batch_assign(cs_batch bt, const cs_grid_desc* descs, void* const* u, const void* const* b,
+                          void* const* tmp, const int32_t* rows, int32_t count, void* stream)
+{
+    if (!bt) { set_error("batch is NULL"); return CS_EINVAL; }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != bt->device) {
+        (void)hipGetLastError();
+        set_error("batch belongs to device %d", bt->device);
+        return CS_EINVAL;
+    }
+    if (count > bt->capacity) { set_error("%d patches exceed the reserved %d", count, bt->capacity); return CS_EINVAL; }
+    Plan pl;
+    cs_status st = plan_batch(descs, u, b, tmp, rows, count, &pl);
+    if (st != CS_OK) return st;
+    if (pl.partials > bt->partial_cap) {
+        set_error("the patches need %lld residual partials, %lld reserved", (long long)pl.partials,
+                  (long long)bt->partial_cap);
+        return CS_EINVAL;
+    }
+    return install_plan(bt, pl, (hipStream_t)stream);
+}
+
+cs_status cs_batch_ir_attach(cs_batch bt, const cs_grid_desc* descs64, void* const* x,
+                             const void* const* b, void* stream)
+{
+    if (!bt) { set_error("batch is NULL"); return CS_EINVAL; }
+    bt->ir_ok = false;
+    const int count = bt->count;
+    if (count > 0 && (!descs64 || !x || !b)) { set_error("NULL array"); return CS_EINVAL; }
+    const int st_i = bt->ir_next;
+    hipError_t e = hipEventSynchronize(bt->ir_ev[st_i]);
+    if (e != hipSuccess) return hip_fail(e, "waiting for a staging buffer");
+    int64_t items = 0;
+    for (int i = 0; i < count; ++i) {
+        const BatchPatch& p = bt->by_index[(size_t)i];
+        const cs_grid_desc& d = descs64[i];
+        cs_status st = validate_desc_pub(&d);
+        if (st != CS_OK) return st;
+        if (d.dim != 3 || d.dtype != CS_F64 || p.dtype != CS_F32 || d.stencil != p.stencil ||
+            d.n[0] != p.g.nx || d.n[1] != p.g.ny || d.n[2] != p.g.nz) {
+            set_error("patch %d: the FP64 patch must match its FP32 patch (3D, n, stencil)", i);
+            return CS_EINVAL;
+        }
+        const size_t bytes = (size_t)span_of3(d) * 8;
+        if ((st = check_device_range_pub(x[i], bytes, 8, "patch x")) != CS_OK ||
+            (st = check_device_range_pub(b[i], bytes, 8, "patch b")) != CS_OK)
+            return st;
+        if (x[i] == b[i] || x[i] == p.u || x[i] == p.b || x[i] == p.tmp) {
+            set_error("patch %d: x must be separate from b and the FP32 arrays", i);
+            return CS_EINVAL;
+        }
+        IrPatch q{};
+        q.g.nx = d.n[0];
+        q.g.ny = d.n[1];
+        q.g.nz = d.n[2];
+        q.g.sy = d.stride[1];
+        q.g.sz = d.stride[2];
+        q.g.parity = d.parity;
+        q.g2 = p.g;
+        q.x = (double*)x[i];
+        q.b = (const double*)b[i];
+        q.e = (float*)p.u;
+        q.r32 = (float*)p.b;
+        q.hh = d.h * d.h;
+        q.stencil = d.stencil;
+        q.row = p.index;
+        q.res_begin = items;
+        q.res_items = p.res_items;
+        items += p.res_items;
+        bt->ir_stage[st_i][i] = q;
+    }
+    if (items > bt->partial_cap) { set_error("refinement residual needs more partials than reserved"); return CS_EINVAL; }
+    if (count > 0) {
+        e = hipMemcpyAsync(bt->ir_arena, bt->ir_stage[st_i], sizeof(IrPatch) * (size_t)count,
+                           hipMemcpyHostToDevice, (hipStream_t)stream);
+        if (e == hipSuccess) e = hipEventRecord(bt->ir_ev[st_i], (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "refinement table upload");
+    }
+    bt->ir_next ^= 1;
+    bt->ir_items = items;
+    bt->ir_ok = true;
+    return CS_OK;
+}
+
+cs_status cs_batch_ir_residual(cs_batch bt, double* scales, double* norms, void* stream)
+{
+    if (!bt) { set_error("batch is NULL"); return CS_EINVAL; }
+    if (!bt->ir_ok) { set_error("no FP64 patches attached since the last assignment"); return CS_EINVAL; }
+    if (bt->count == 0) return CS_OK;
+    cs_status st = check_device_range_pub(norms, sizeof(double) * 3 * (size_t)bt->rows, sizeof(double), "norms");
+    if (st == CS_OK) st = check_device_range_pub(scales, sizeof(double) * (size_t)bt->rows, sizeof(double), "scales");
+    if (st != CS_OK) return st;
+    return launch_batch_ir_residual(bt->ir_arena, bt->count, bt->ir_items, bt->partials, scales,
+                                    norms, (hipStream_t)stream);
+}
+
+cs_status cs_batch_ir_update(cs_batch bt, const double* scales, void* stream)
+{
+    if (!bt) { set_error("batch is NULL"); return CS_EINVAL; }
+    if (!bt->ir_ok) { set_error("no FP64 patches attached since the last assignment"); return CS_EINVAL; }
+    if (bt->count == 0) return CS_OK;
+    cs_status st = check_device_range_pub(scales, sizeof(double) * (size_t)bt->rows, sizeof(double), "scales");
+    if (st != CS_OK) return st;
+    return launch_batch_ir_update(bt->ir_arena, bt->count, bt->ir_items, scales, (hipStream_t)stream);
 }
 
 cs_status cs_batch_destroy(cs_batch bt)
@@ -288,7 +516,8 @@ cs_status cs_batch_sweeps_per_pass(cs_batch bt, int32_t index, int32_t* out)
 cs_status cs_batch_residual(cs_batch bt, double* norms, void* stream)
 {
     if (!bt) { set_error("batch is NULL"); return CS_EINVAL; }
-    cs_status st = check_device_range_pub(norms, sizeof(double) * 3 * (size_t)bt->count,
+    if (bt->count == 0) return CS_OK;
+    cs_status st = check_device_range_pub(norms, sizeof(double) * 3 * (size_t)bt->rows,
                                           sizeof(double), "norms");
     if (st != CS_OK) return st;
     for (auto& gr : bt->groups)

@@ -14,9 +14,27 @@ struct BatchPatch {
     double h2;        // h^2 as the sweeps use it (rounded to FP32 for FP32 patches)
     double hh;        // h*h in FP64 (residual)
     int tiles_x, tiles_y, chunks;
-    int index;        // position of the patch in the caller's arrays
+    int index;        // row of the patch in the norms (the caller's position by default)
+    int stencil, dtype;
     int64_t item_begin;  // first work item of this patch in the sweep launch
     int64_t res_begin;   // first row-block item in the residual / copy launches
+    int res_items;
+};
+
+// One patch of the refinement pairing of an FP32 batch: the FP64 iterate x
+// and right-hand side b, and the FP32 correction e and scaled residual r32
+// (the FP32 patch's u and b), in the caller's order.
+struct IrPatch {
+    Geo g;            // x and b
+    Geo g2;           // e and r32
+    double* x;
+    const double* b;
+    float* e;
+    float* r32;
+    double hh;        // h*h (FP64)
+    int stencil;
+    int row;          // row in the norms and scales
+    int64_t res_begin;
     int res_items;
 };
 
@@ -35,6 +53,14 @@ int batch_resident_tier(int dtype, int stencil, const Geo& g);
 // workgroup per patch, in place in u.
 cs_status launch_batch_resident(int dtype, int stencil, int tier, const BatchPatch* tab, int count,
                                 int nsweeps, hipStream_t s);
+// Refinement steps of every patch of an IR table: r = b - A x in FP64, with
+// the scale s = the smallest power of two >= the row's previous max |r|
+// (norms[3 row + 1] on entry) written to scales[row], r32 = fl32(r / s),
+// e = 0, and the row's norms; and x += scales[row] * e.
+cs_status launch_batch_ir_residual(const IrPatch* tab, int count, int64_t items, Partial* partials,
+                                   double* scales, double* norms, hipStream_t s);
+cs_status launch_batch_ir_update(const IrPatch* tab, int count, int64_t items, const double* scales,
+                                 hipStream_t s);
 cs_status launch_batch_halo(int dtype, const BatchPatch* tab, int count, hipStream_t s);
 cs_status launch_batch_copyback(int dtype, const BatchPatch* tab, int count, int64_t res_items,
                                 hipStream_t s);

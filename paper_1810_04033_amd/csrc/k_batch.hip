@@ -297,7 +297,162 @@ k_batch_finish(const BatchPatch* __restrict__ tab, const Partial* __restrict__ p
     norms[3 * P.index + 2] = sqrt(c);
 }
 
+// ---- batched refinement steps ---------------------------------------------
+
+__device__ inline int find_ir(const IrPatch* __restrict__ tab, int count, int64_t w)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].res_begin <= w)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// The smallest power of two >= v (1 for v <= 0 or not finite), exactly:
+// a positive finite double is a power of two iff its significand field is
+// zero (normal) or a single bit (subnormal); otherwise the next one up is
+// formed from the exponent (or the leading significand bit) alone.
+__device__ inline double pow2_at_least(double v)
+{
+    if (!(v > 0.0) || !(v <= 1.7976931348623157e308)) return 1.0;
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+    const unsigned long long man = bits & ((1ull << 52) - 1);
+    const unsigned ex = (unsigned)(bits >> 52) & 0x7ffu;
+    if (ex == 0) {  // subnormal: v = man * 2^-1074
+        const unsigned long long p = 1ull << (63 - __clzll((long long)man));
+        return __longlong_as_double((long long)(man == p ? man : p << 1));
+    }
+    if (man == 0) return v;
+    return __longlong_as_double((long long)((unsigned long long)(ex + 1) << 52));
+}
+
+template <int ST>
+__device__ __forceinline__ void ir_rows(const IrPatch& P, int64_t item, double inv, double& s_r2,
+                                        double& mx, double& s_b2)
+{
+    const Geo& g = P.g;
+    const int64_t rows = g.ny * g.nz, sy = g.sy, sz = g.sz;
+    for (int rr = threadIdx.y; rr < kRowsPerItem; rr += 4) {
+        const int64_t row = item * kRowsPerItem + rr;
+        if (row >= rows) break;
+        const int64_t j = 1 + row % g.ny, k = 1 + row / g.ny;
+        for (int64_t i = 1 + threadIdx.x; i <= g.nx; i += 64) {
+            const int64_t q = k * sz + j * sy + i;
+            const int64_t q2 = k * P.g2.sz + j * P.g2.sy + i;
+            auto ld = [&](int ox, int oy, int oz) { return P.x[q + oz * sz + oy * sy + ox]; };
+            const double su = ordered_sum<double, 3, ST, true>(ld);
+            const double bq = P.b[q];
+            const double rq = bq - su / P.hh;
+            P.r32[q2] = (float)(rq * inv);
+            P.e[q2] = 0.0f;
+            s_r2 += rq * rq;
+            s_b2 += bq * bq;
+            mx = fmax(mx, fabs(rq));
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_batch_ir_residual(const IrPatch* __restrict__ tab, int count, const double* norms,
+                    double* __restrict__ scales, Partial* __restrict__ partials)
+{
+    __shared__ double sh[3 * 256];
+    const int64_t w = blockIdx.x;
+    const IrPatch P = tab[find_ir(tab, count, w)];
+    const int64_t item = w - P.res_begin;
+    // the scale of this step from the previous residual's max |r|
+    const double sc = pow2_at_least(norms[3 * P.row + 1]);
+    if (item == 0 && threadIdx.x == 0 && threadIdx.y == 0) scales[P.row] = sc;
+    const double inv = 1.0 / sc;  // exact: sc is a power of two
+    double s_r2 = 0.0, mx = 0.0, s_b2 = 0.0;
+    if (P.stencil == FD)
+        ir_rows<FD>(P, item, inv, s_r2, mx, s_b2);
+    else
+        ir_rows<Q1>(P, item, inv, s_r2, mx, s_b2);
+    const int t = threadIdx.y * 64 + threadIdx.x;
+    sh[t] = s_r2;
+    sh[256 + t] = mx;
+    sh[512 + t] = s_b2;
+    __syncthreads();
+    for (int wdt = 128; wdt > 0; wdt >>= 1) {
+        if (t < wdt) {
+            sh[t] = sh[t] + sh[t + wdt];
+            sh[256 + t] = fmax(sh[256 + t], sh[256 + t + wdt]);
+            sh[512 + t] = sh[512 + t] + sh[512 + t + wdt];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        partials[w].sum_r2 = sh[0];
+        partials[w].max_r = sh[256];
+        partials[w].sum_b2 = sh[512];
+    }
+}
+
+__global__ void __launch_bounds__(64)
+k_batch_ir_finish(const IrPatch* __restrict__ tab, const Partial* __restrict__ partials,
+                  double* __restrict__ norms)
+{
+    const IrPatch P = tab[blockIdx.x];
+    if (threadIdx.x != 0) return;
+    double a = 0.0, m = 0.0, c = 0.0;
+    for (int i = 0; i < P.res_items; ++i) {
+        const Partial q = partials[P.res_begin + i];
+        a += q.sum_r2;
+        m = fmax(m, q.max_r);
+        c += q.sum_b2;
+    }
+    norms[3 * P.row + 0] = sqrt(a);
+    norms[3 * P.row + 1] = m;
+    norms[3 * P.row + 2] = sqrt(c);
+}
+
+__global__ void __launch_bounds__(256)
+k_batch_ir_update(const IrPatch* __restrict__ tab, int count, const double* __restrict__ scales)
+{
+    const int64_t w = blockIdx.x;
+    const IrPatch P = tab[find_ir(tab, count, w)];
+    const int64_t item = w - P.res_begin;
+    const Geo& g = P.g;
+    const double sc = scales[P.row];
+    const int64_t rows = g.ny * g.nz;
+    for (int rr = threadIdx.y; rr < kRowsPerItem; rr += 4) {
+        const int64_t row = item * kRowsPerItem + rr;
+        if (row >= rows) break;
+        const int64_t j = 1 + row % g.ny, k = 1 + row / g.ny;
+        for (int64_t i = 1 + threadIdx.x; i <= g.nx; i += 64) {
+            const int64_t q = k * g.sz + j * g.sy + i;
+            const int64_t q2 = k * P.g2.sz + j * P.g2.sy + i;
+            P.x[q] = P.x[q] + (double)P.e[q2] * sc;
+        }
+    }
+}
+
 }  // namespace
+
+cs_status launch_batch_ir_residual(const IrPatch* tab, int count, int64_t items, Partial* partials,
+                                   double* scales, double* norms, hipStream_t s)
+{
+    if (count <= 0 || items <= 0) return CS_OK;
+    hipLaunchKernelGGL(k_batch_ir_residual, dim3((unsigned)items), dim3(64, 4), 0, s, tab, count,
+                       (const double*)norms, scales, partials);
+    cs_status st = check_launch("batched refinement residual");
+    if (st != CS_OK) return st;
+    hipLaunchKernelGGL(k_batch_ir_finish, dim3(count), dim3(64), 0, s, tab, partials, norms);
+    return check_launch("batched refinement residual finish");
+}
+
+cs_status launch_batch_ir_update(const IrPatch* tab, int count, int64_t items, const double* scales,
+                                 hipStream_t s)
+{
+    if (count <= 0 || items <= 0) return CS_OK;
+    hipLaunchKernelGGL(k_batch_ir_update, dim3((unsigned)items), dim3(64, 4), 0, s, tab, count, scales);
+    return check_launch("batched refinement update");
+}
 
 int64_t batch_residual_items(const Geo& g)
 {

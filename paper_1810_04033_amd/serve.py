@@ -4,14 +4,19 @@ Requests (3D patch, stencil, precision, right-hand side) arrive over time.
 The scheduler admits a waiting request as soon as a slot and enough of the HBM
 budget are free, keeps its state resident on the device, and advances all
 active requests together in steps: one step runs `sweeps_per_step` coloured
-Gauss-Seidel sweeps of every active patch in the same batched launches, then
-reads back every patch's residual norms in one copy.  Requests whose relative
-residual reached the tolerance retire (latency = retirement - arrival); their
-memory is released and waiting requests are admitted at the next step.
+Gauss-Seidel sweeps of every active patch in the same batched launches (the
+refinement requests' FP64 residual and correction in one batched launch
+each), then copies every patch's residual norms to the host asynchronously.
+The GPU executor reads a step's norms while the next step runs (lag 1): a
+request whose relative residual reached the tolerance retires one step after
+the step that reached it (latency = retirement - arrival), having run that one
+more step; its memory is released and waiting requests are admitted at the
+next step.
 
 Each request's sweeps happen in steps of fixed size regardless of what else
-is active, and the batched kernels compute every patch independently, so a
-request's result is the same alone and in any mix.
+is active, retirement always lags by the same one step, and the batched
+kernels compute every patch independently, so a request's result is the same
+alone and in any mix.
 
 The scheduler is independent of the executor: `GpuExecutor` drives libcolsten;
 tests drive the scheduler logic with a CPU stand-in executor.
@@ -52,7 +57,8 @@ class ServeStats:
     steps: int = 0
     max_active: int = 0
     peak_bytes: int = 0
-    busy_s: float = 0.0
+    busy_s: float = 0.0         # host time inside executor steps
+    gpu_busy_s: float = 0.0     # device time of the steps' work (when the executor times it)
     latencies: list = field(default_factory=list)
 
     def summary(self, t_first_arrival, t_last_done):
@@ -63,7 +69,8 @@ class ServeStats:
                 "p50_latency_s": float(np.percentile(lat, 50)),
                 "p99_latency_s": float(np.percentile(lat, 99)),
                 "mean_latency_s": float(np.mean(lat)), "max_active": self.max_active,
-                "peak_bytes": self.peak_bytes, "span_s": span}
+                "peak_bytes": self.peak_bytes, "span_s": span,
+                "gpu_busy_fraction": self.gpu_busy_s / span if self.gpu_busy_s > 0 else None}
 
 
 class Scheduler:
@@ -142,7 +149,11 @@ class Scheduler:
         self._admit(now)
         for t in [t for t in self.active if t.cancel]:
             self._retire(t, CANCELLED, now)
+        lag = getattr(self.ex, "lag", 0)
         if not self.active:
+            if lag and self.ex.pending():
+                self._results(self.ex.drain(), self.clock())
+                return True
             if not self.waiting:
                 return False
             # idle until the next arrival
@@ -151,11 +162,20 @@ class Scheduler:
                 time.sleep(min(1e-4, max(0.0, nxt - self.clock())))
             return True
         t0 = self.clock()
-        rels = self.ex.step(self.active, self.k)
+        out = self.ex.step(self.active, self.k)
         now = self.clock()
         self.stats.busy_s += now - t0
         self.stats.steps += 1
-        for t, rel in zip(list(self.active), rels):
+        # an executor with lag 1 returns the residuals of the step before the
+        # one it just enqueued, as (ticket, rel) pairs
+        self._results(out if lag else list(zip(list(self.active), out)), now)
+        return True
+
+    def _results(self, pairs, now):
+        active = set(id(t) for t in self.active)
+        for t, rel in pairs:
+            if id(t) not in active:
+                continue  # retired or cancelled since that step was enqueued
             t.rel_residual = rel
             if not math.isfinite(rel):
                 self._retire(t, DIVERGED, now)
@@ -163,36 +183,68 @@ class Scheduler:
                 self._retire(t, DONE, now)
             elif t.sweeps >= self.max_sweeps:
                 self._retire(t, NOT_CONVERGED, now)
-        return True
 
     def run(self, tickets):
         for t in tickets:
             self.submit(t)
         while self.step():
             pass
+        self.stats.gpu_busy_s = getattr(self.ex, "gpu_ms", 0.0) * 1e-3
         return self.finished
 
 
 class GpuExecutor:
-    """Runs admitted requests on the GPU through libcolsten.
+    """Runs admitted requests on the GPU through libcolsten, on one stream.
 
-    FP64 requests hold u, b and a work array; mixed-precision requests hold the
-    FP64 iterate and RHS plus the FP32 correction, its RHS and work array.  All
-    active patches' sweeps go through one batch (rebuilt when the active set
-    changes); the FP64 norms of FP64 patches come from one batched residual and
-    those of refinement patches from their per-request refinement residual."""
+    Two reserved batches hold the active patches: the FP64 requests (u, b and
+    a work array) and the refinement requests' FP32 correction e, its scaled
+    right-hand side r32 and work array, paired with their FP64 iterate x and
+    right-hand side b.  Each request keeps one norm row (its slot) for its
+    life, so a change of the active set only reassigns the batches: their
+    tables go to the device by asynchronous copies from pinned staging buffers,
+    with no allocation and no synchronisation.  A step enqueues, for the
+    refinement requests, the batched correction x += s e and the batched FP64
+    residual (scale and FP32 copy on the device), the sweeps of both batches,
+    the FP64 requests' batched residual and an asynchronous copy of all norms
+    to pinned host memory; it then waits for the previous step's norms, which
+    arrived while this step was queued (lag 1)."""
 
-    def __init__(self, stream=None, keep_results=False):
+    lag = 1
+
+    def __init__(self, stream=None, keep_results=False, max_active=256, max_edge=128):
         import torch
         from . import colsten as C
         self.torch = torch
         self.C = C
-        self.stream = stream
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.keep_results = keep_results
-        self._key = None
-        self._batch = None
-        self._fp64 = []
-        self._norm_rows = None
+        self.max_active = int(max_active)
+        self.max_edge = int(max_edge)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        partials = self.max_active * C.residual_items((max_edge, max_edge, max_edge))
+        self.b64 = C.cs_batch_reserve(self.max_active, partials)
+        self.b32 = C.cs_batch_reserve(self.max_active, partials)
+        self.norms = torch.zeros(self.max_active, 3, dtype=torch.float64, device=dev)
+        self.scales = torch.ones(self.max_active, dtype=torch.float64, device=dev)
+        self.host = [torch.zeros(self.max_active, 3, dtype=torch.float64).pin_memory() for _ in range(2)]
+        self.buf = 0
+        self.free_rows = list(range(self.max_active - 1, -1, -1))
+        self.dirty = True
+        self.has_mixed = False
+        self.has_fp64 = False
+        self._pending = None
+
+    def close(self):
+        for h in ("b64", "b32"):
+            if getattr(self, h, None):
+                self.C.cs_batch_destroy(getattr(self, h))
+                setattr(self, h, None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
     @staticmethod
     def bytes_needed(req):
@@ -203,85 +255,101 @@ class GpuExecutor:
     def admit(self, t):
         torch, C = self.torch, self.C
         nx, ny, nz = t.req.n
+        if max(t.req.n) > self.max_edge:
+            raise ValueError("request edge %d beyond the executor's %d" % (max(t.req.n), self.max_edge))
         n = (nx, ny, nz)
         h = 1.0 / (max(n) + 1)
-        b = C.empty_grid(n)
-        b[1:-1, 1:-1, 1:nx + 1].copy_(torch.from_numpy(t.rhs), non_blocking=False)
-        u = C.empty_grid(n)
-        st = {"h": h, "u": u, "b": b}
-        if t.req.mixed:
-            e = C.empty_grid(n, dtype=torch.float32)
-            r32 = C.empty_grid(n, dtype=torch.float32)
-            st.update(e=e, r32=r32, tmp=C.grid_like(e),
-                      g64=C.Grid(u, b, dim=3, stencil=t.req.stencil, h=h),
-                      g32=C.Grid(e, r32, dim=3, stencil=t.req.stencil, h=h),
-                      norms=torch.zeros(3, dtype=torch.float64, device=u.device),
-                      scale=pow2_at_least(float(np.max(np.abs(t.rhs)))), first=True)
-        else:
-            st["tmp"] = C.grid_like(u)
+        with torch.cuda.stream(self.stream):
+            b = C.empty_grid(n)
+            rhs = torch.from_numpy(t.rhs).pin_memory()
+            b[1:-1, 1:-1, 1:nx + 1].copy_(rhs, non_blocking=True)
+            u = C.empty_grid(n)
+            st = {"h": h, "u": u, "b": b, "row": self.free_rows.pop()}
+            if t.req.mixed:
+                e = C.empty_grid(n, dtype=torch.float32)
+                st.update(e=e, r32=C.empty_grid(n, dtype=torch.float32), tmp=C.grid_like(e))
+                # the first scale comes from max |r_0| = max |b| (x = 0)
+                self.norms[st["row"], 1].fill_(float(np.max(np.abs(t.rhs))))
+            else:
+                st["tmp"] = C.grid_like(u)
         t.state = st
+        self.dirty = True
 
     def release(self, t):
         st = t.state
-        if st is not None and self.keep_results:
-            t.result = st["u"].detach().cpu().numpy()
         if st is not None:
-            for k in ("g64", "g32"):
-                if k in st:
-                    st[k].close()
+            if self.keep_results:
+                with self.torch.cuda.stream(self.stream):
+                    t.result = st["u"].detach().cpu().numpy()
+            self.free_rows.append(st["row"])
         t.state = None
-        self._key = None
+        self.dirty = True
 
-    def _rebuild(self, tickets):
+    def _assign(self, tickets):
         C = self.C
-        key = tuple(id(t) for t in tickets)
-        if key == self._key:
-            return
-        if self._batch is not None:
-            self._batch.close()
-        patches = []
-        self._fp64 = []
-        for t in tickets:
-            st = t.state
-            if t.req.mixed:
-                patches.append((st["e"], st["r32"], st["tmp"], t.req.stencil, st["h"], 0))
-            else:
-                patches.append((st["u"], st["b"], st["tmp"], t.req.stencil, st["h"], 0))
-                self._fp64.append(len(patches) - 1)
-        self._batch = C.Batch(patches)
-        self._key = key
+        f64 = [t for t in tickets if not t.req.mixed]
+        mix = [t for t in tickets if t.req.mixed]
+        C.cs_batch_assign(self.b64, [C.describe(t.state["u"], dim=3, stencil=t.req.stencil, h=t.state["h"])
+                                     for t in f64],
+                          [t.state["u"].data_ptr() for t in f64], [t.state["b"].data_ptr() for t in f64],
+                          [t.state["tmp"].data_ptr() for t in f64], [t.state["row"] for t in f64],
+                          self.stream)
+        C.cs_batch_assign(self.b32, [C.describe(t.state["e"], dim=3, stencil=t.req.stencil, h=t.state["h"])
+                                     for t in mix],
+                          [t.state["e"].data_ptr() for t in mix], [t.state["r32"].data_ptr() for t in mix],
+                          [t.state["tmp"].data_ptr() for t in mix], [t.state["row"] for t in mix],
+                          self.stream)
+        C.cs_batch_ir_attach(self.b32, [C.describe(t.state["u"], dim=3, stencil=t.req.stencil, h=t.state["h"])
+                                        for t in mix],
+                             [t.state["u"].data_ptr() for t in mix], [t.state["b"].data_ptr() for t in mix],
+                             self.stream)
+        self.has_fp64, self.has_mixed = bool(f64), bool(mix)
+        self.dirty = False
 
     def step(self, tickets, k):
-        C, torch = self.C, self.torch
-        self._rebuild(tickets)
-        for t in tickets:
-            if t.req.mixed:
-                st = t.state
-                if not st["first"]:
-                    C.cs_ir_update(st["g64"].handle, st["g32"].handle, st["scale_prev"], self.stream)
-                C.cs_ir_residual(st["g64"].handle, st["g32"].handle, st["scale"],
-                                 st["norms"].data_ptr(), self.stream)
-        self._batch.gs(k, self.stream)
+        torch, C = self.torch, self.C
+        if self.dirty:
+            self._assign(tickets)
+        s = self.stream
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        if self.has_mixed:
+            C.cs_batch_ir_update(self.b32, self.scales.data_ptr(), s)
+            C.cs_batch_ir_residual(self.b32, self.scales.data_ptr(), self.norms.data_ptr(), s)
+        C.cs_batch_gs_sweeps(self.b64, k, s)
+        C.cs_batch_gs_sweeps(self.b32, k, s)
+        if self.has_fp64:
+            C.cs_batch_residual(self.b64, self.norms.data_ptr(), s)
+        with torch.cuda.stream(s):
+            self.host[self.buf].copy_(self.norms, non_blocking=True)
+        e1.record(s)
         for t in tickets:
             t.sweeps += k
-        if self._fp64:
-            self._batch.residual(self.stream)
-        rows = []
-        for i, t in enumerate(tickets):
-            rows.append(t.state["norms"] if t.req.mixed else self._batch.norms[i])
-        host = torch.stack(rows).cpu().numpy()
-        rels = []
-        for t, nr in zip(tickets, host):
-            rel = nr[0] / nr[2] if nr[2] > 0 else nr[0]
-            rels.append(float(rel))
-            if t.req.mixed:
-                st = t.state
-                st["first"] = False
-                st["scale_prev"] = st["scale"]
-                st["scale"] = pow2_at_least(float(nr[1]))
-                # the residual just read is that of x before this step's
-                # correction: the sweeps of the step count from the next one
-        return rels
+        prev = self._pending
+        self._pending = ([(t, t.state["row"]) for t in tickets], self.buf, e0, e1)
+        self.buf ^= 1
+        return self._collect(prev)
+
+    def pending(self):
+        return self._pending is not None
+
+    def drain(self):
+        prev, self._pending = self._pending, None
+        return self._collect(prev)
+
+    def _collect(self, prev):
+        if prev is None:
+            return []
+        pairs, buf, e0, e1 = prev
+        e1.synchronize()
+        self.gpu_ms = getattr(self, "gpu_ms", 0.0) + e0.elapsed_time(e1)
+        host = self.host[buf].numpy()
+        out = []
+        for t, row in pairs:
+            nr = host[row]
+            out.append((t, float(nr[0] / nr[2] if nr[2] > 0 else nr[0])))
+        return out
 
     def result(self, t):
         return t.state["u"].detach().cpu().numpy()
@@ -297,17 +365,23 @@ def make_tickets(reqs):
 
 
 def bench_main(a):
-    """Serving benchmark: Poisson arrivals of 3D patch solves (edges
-    log-uniform in [16, 128], aspect <= 4, 7/27-point and FP64/refinement
-    50/50, tol 1e-8), admitted by a 32 GiB HBM budget and 256 slots."""
+    """Serving benchmark: see serve_measure; prints one JSON line."""
     import json
+    print(json.dumps(serve_measure(int(getattr(a, "serve_count", 0) or 300))), flush=True)
+
+
+def serve_measure(count):
+    """Poisson arrivals of `count` 3D patch solves (edges log-uniform in
+    [16, 128], aspect <= 4, 7/27-point and FP64/refinement 50/50, tol 1e-8),
+    admitted by a 32 GiB HBM budget and 256 slots: at 2000 requests/s, at 0.8
+    times the capacity that run measured, and the same requests one patch per
+    launch in FP64."""
     import torch
     from . import colsten as C
     from . import inputs as I
     from . import solve as S
 
     torch.cuda.set_device(0)
-    count = int(getattr(a, "serve_count", 0) or 300)
     k = 50
     results = {}
 
@@ -316,9 +390,11 @@ def bench_main(a):
         tickets = make_tickets(reqs)
         t_start = time.perf_counter()
         clock = lambda: time.perf_counter() - t_start  # noqa: E731
-        sch = Scheduler(GpuExecutor(), budget_bytes=32 << 30, max_active=256, sweeps_per_step=k,
+        ex = GpuExecutor(max_active=256)
+        sch = Scheduler(ex, budget_bytes=32 << 30, max_active=256, sweeps_per_step=k,
                         tol=1e-8, clock=clock)
         done = sch.run(tickets)
+        ex.close()
         t_last = max(t.finished_s for t in done)
         return sch.stats.summary(reqs[0].arrival_s, t_last)
 
@@ -363,4 +439,4 @@ def bench_main(a):
         "speedup_vs_one_patch_per_launch": round(results["offered_2000_per_s"]["patches_per_s"]
                                                   / (count / seq_s), 2),
     }
-    print(json.dumps(out), flush=True)
+    return out
