@@ -42,6 +42,8 @@ def _args():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-growth", action="store_true",
+                   help="poisson3d: leave out the batched-patch and serving figures of the line")
     p.add_argument("--per-colour", action="store_true",
                    help="run the GS rows as one launch per colour pass (no work array)")
     p.add_argument("--workload", default="poisson3d",
@@ -54,6 +56,9 @@ def _args():
                         "smoother to 1e-10; slab: the sweep rows on one GPU's z-slab; calib: a "
                         "plain 1 GiB device copy for scaling rocprofv3's byte counters")
     p.add_argument("--tune", action="store_true", help="patches: run the tile autotuner first")
+    p.add_argument("--patch-baselines", default="per_colour,fused_per_patch",
+                   help="patches: the per-patch launch schedules timed beside the batch "
+                        "(comma list of per_colour, fused_per_patch; empty for none)")
     p.add_argument("--refine-n", type=int, default=512, help="refine: interior edge")
     p.add_argument("--mg-n", type=int, default=255, help="multigrid: interior edge, 2^m - 1")
     p.add_argument("--mg-gs-compare", type=int, default=1,
@@ -61,6 +66,11 @@ def _args():
     p.add_argument("--slab", default="512,512,64;256,256,32",
                    help="slab: interior shapes nx,ny,nz separated by ';' (one GPU's eighth of "
                         "512^3 and of 256^3 by default)")
+    p.add_argument("--slab-dtype", default="f64", choices=["f64", "f32"],
+                   help="slab: element type of the sweeps")
+    p.add_argument("--slab-rows", default="gs_fd7,jacobi_fd7,gs_q1_27,jacobi_q1_27",
+                   help="slab: the sweep rows to run")
+    p.add_argument("--slab-sweeps", type=int, default=100, help="slab: sweeps per row")
     return p.parse_args()
 
 
@@ -306,13 +316,43 @@ def run_poisson3d(a):
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
         out["cpu_openmp"] = cpu_baseline(openmp=True)
+    if not a.no_growth:
+        # the growth rows, bounded: the 4096-patch batch (3 timed runs of 20
+        # sweeps against one launch per patch and colour) and a 100-request
+        # serving stream; each block is freed before the next
+        del grids, tmp, b
+        torch.cuda.empty_cache()
+        pa = patches_measure(steps=3, warmup=1, tune=False, baselines=("per_colour",))
+        out["patches_4096"] = {k: pa[k] for k in ("value", "unit", "ms_per_step", "patches_per_s",
+                                                  "speedup_vs_per_patch_launches")}
+        out["patches_4096"]["baseline_ms_one_launch_per_patch_per_colour"] = \
+            pa["baseline_ms"]["one_launch_per_patch_per_colour"]
+        torch.cuda.empty_cache()
+        from paper_1810_04033_amd import serve as SV
+        sv = SV.serve_measure(100)
+        out["serve_100"] = {"patches_per_s": sv["value"],
+                            "p50_latency_s": sv["served"]["offered_2000_per_s"]["p50_latency_s"],
+                            "p99_latency_s": sv["served"]["offered_2000_per_s"]["p99_latency_s"],
+                            "gpu_busy_fraction": sv["served"]["offered_2000_per_s"]["gpu_busy_fraction"],
+                            "at_0.8x_capacity": {k: sv["served"]["offered_0.8x_capacity"][k]
+                                                 for k in ("rate_per_s", "patches_per_s",
+                                                           "p50_latency_s", "p99_latency_s")},
+                            "speedup_vs_one_patch_per_launch": sv["speedup_vs_one_patch_per_launch"],
+                            "workload": sv["config"]["workload"]}
     print(json.dumps(out), flush=True)
 
 
 def run_patches(a):
+    out = patches_measure(a.steps, a.warmup, a.tune, cpu=not a.no_cpu_baseline,
+                          baselines=tuple(m for m in a.patch_baselines.split(",") if m))
+    print(json.dumps(out), flush=True)
+
+
+def patches_measure(steps, warmup, tune, baselines=("per_colour", "fused_per_patch"), cpu=False):
     """4096 cubic patches, edges uniform over {8,16,24,32,48,64} (seed 3), zero
     halo, uniform[-1,1) RHS per patch (stream = patch id), u0 = 0, 20 red-black
-    7-point GS sweeps in FP64: one batched launch per sweep against one launch
+    7-point GS sweeps in FP64: the batch (small patches resident in LDS for all
+    sweeps, the others one launch per tile group and pass) against one launch
     per patch and colour (and one fused launch per patch and sweep)."""
     import numpy as np
     import torch
@@ -323,7 +363,7 @@ def run_patches(a):
 
     torch.cuda.set_device(0)
     sweeps = 20
-    tuned = TU.tune(C.CS_FD, torch.float64) if a.tune else TU.apply_cached(C.CS_FD, torch.float64)
+    tuned = TU.tune(C.CS_FD, torch.float64) if tune else TU.apply_cached(C.CS_FD, torch.float64)
     edges = I.patch_edges(3, 4096)
     ps = []
     for i, e in enumerate(edges):
@@ -339,11 +379,11 @@ def run_patches(a):
         for u, *_ in ps:
             u.zero_()
 
-    for _ in range(a.warmup):
+    for _ in range(warmup):
         reset()
         bt.gs(sweeps)
     times = []
-    for _ in range(a.steps):
+    for _ in range(steps):
         reset()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -359,7 +399,7 @@ def run_patches(a):
 
     # one launch per patch per colour pass (in place), then one fused launch per sweep
     base = {}
-    for mode in ("per_colour", "fused_per_patch"):
+    for mode in baselines:
         reset()
         grids = [C.Grid(u, b, dim=3, stencil=C.CS_FD, h=h) for (u, b, t, st, h, par) in ps]
         for g in grids:
@@ -388,27 +428,29 @@ def run_patches(a):
     achieved = bytes_per_sweep / (ms * 1e-3 / sweeps) / 1e9
     out = {
         "metric": "GLUP/s and patches/s (batched coloured GS on 4096 patches)",
-        "value": round(value, 3), "unit": "GLUP/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "value": round(value, 3), "unit": "GLUP/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "4096 cubic patches, edge uniform over {8,16,24,32,48,64} (seed 3), "
                                "FP64 7-point red-black GS, 20 sweeps per patch, zero Dirichlet halo",
                    "points": pts, "sweeps": sweeps, "tile_policy": tuned},
         "patches_per_s": round(4096 / (ms * 1e-3), 1),
-        "baseline_ms": {"one_launch_per_patch_per_colour": round(base["per_colour"], 3),
-                        "one_fused_launch_per_patch_per_sweep": round(base["fused_per_patch"], 3)},
-        "speedup_vs_per_patch_launches": round(base["per_colour"] / ms, 2),
+        "baseline_ms": {("one_launch_per_patch_per_colour" if m == "per_colour" else
+                         "one_fused_launch_per_patch_per_sweep"): round(v, 3) for m, v in base.items()},
+        "speedup_vs_per_patch_launches": (round(base["per_colour"] / ms, 2)
+                                          if "per_colour" in base else None),
         "roofline": {"bound": "hbm", "kernel": "batched_gs_fd7", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "bytes_per_sweep": int(bytes_per_sweep),
                      "mean_sweep_us": round(ms * 1e3 / sweeps, 3),
                      "points_swept_two_per_pass": paired_pts,
                      "note": "bytes moved per sweep over the time per sweep; patches of the large "
-                             "tile class run two sweeps per pass (12 B per update), the others one "
-                             "(24 B)"},
+                             "tile class run two sweeps per pass (12 B per update), patches resident "
+                             "in LDS move 24 B per point once for all sweeps, the others one sweep "
+                             "per pass (24 B)"},
         "max_final_rel_residual": float(np.max(norms[:, 0] / norms[:, 2])),
     }
-    if not a.no_cpu_baseline:
+    if cpu:
         from oracle import oracle as O
         t0 = time.perf_counter()
         sample_pts = 0
@@ -423,7 +465,8 @@ def run_patches(a):
                                "kind": "oracle",
                                "sample": "patches 0-7 of the same set, 20 sweeps each, sequential "
                                          "C oracle, %.1f s" % dt}
-    print(json.dumps(out), flush=True)
+    del ps
+    return out
 
 
 def run_refine(a):
@@ -894,10 +937,12 @@ XGMI_LINK_GBS = 153.0  # one xGMI link, per direction
 
 def run_slab(a):
     """One GPU's share of a grid cut into z-slabs: the four sweep rows of the
-    headline step on each slab shape (100 sweeps each, FP64, the slab's halo
-    standing in for its neighbours' planes), beside the time a one-link
-    exchange of the planes the next pass needs would take (2 planes per side
-    per sweep, each way)."""
+    headline step on each slab shape (100 sweeps each, FP64 by default, the
+    slab's halo standing in for its neighbours' planes), beside the time a
+    one-link exchange of the planes the next pass needs would take (2 planes
+    per side per sweep, each way).  The shapes, element type, rows and sweep
+    count are options, so the same rows can be timed (and profiled) on a whole
+    grid such as 512^3."""
     import torch
 
     from paper_1810_04033_amd import colsten as C
@@ -908,25 +953,33 @@ def run_slab(a):
     for n in shapes:
         if len(n) != 3 or min(n) < 1:
             raise SystemExit("--slab: shapes are nx,ny,nz;...")
+    dt = torch.float64 if a.slab_dtype == "f64" else torch.float32
+    want = set(a.slab_rows.split(","))
+    nsw = a.slab_sweeps
     res = {}
     for n in shapes:
         pts = n[0] * n[1] * n[2]
-        b = C.empty_grid(n)
+        b = C.empty_grid(n, dtype=dt)
         C.fill_uniform(b, 2, dim=3)
-        tmp = C.empty_grid(n)
+        tmp = C.empty_grid(n, dtype=dt)
         h = 1.0 / (max(n) + 1)
         rows = {}
         for name, st in (("fd7", C.CS_FD), ("q1_27", C.CS_Q1)):
-            u = C.empty_grid(n)
+            if not any(k + "_" + name in want for k in ("gs", "jacobi")):
+                continue
+            u = C.empty_grid(n, dtype=dt)
             g = C.Grid(u, b, dim=3, stencil=st, h=h)
             for kind in ("gs", "jacobi"):
+                if kind + "_" + name not in want:
+                    continue
+
                 def run():
                     u.zero_()
                     e0.record(stream)
                     if kind == "gs":
-                        g.gs(SWEEPS, tmp=tmp)
+                        g.gs(nsw, tmp=tmp)
                     else:
-                        g.jacobi(OMEGA, SWEEPS, tmp)
+                        g.jacobi(OMEGA, nsw, tmp)
                     e1.record(stream)
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
@@ -938,12 +991,12 @@ def run_slab(a):
                     run()
                     torch.cuda.synchronize()
                     ms += e0.elapsed_time(e1)
-                per_sweep_us = ms / a.steps / SWEEPS * 1e3
+                per_sweep_us = ms / a.steps / nsw * 1e3
                 rows[kind + "_" + name] = {"us_per_sweep": round(per_sweep_us, 3),
                                            "GLUP/s": round(pts / (per_sweep_us * 1e-6) / 1e9, 2),
                                            "sweeps_per_pass": g.sweeps_per_pass(jacobi=(kind == "jacobi"))}
             g.close()
-        exch_bytes = 2 * n[0] * n[1] * 8  # per neighbour and sweep, each way
+        exch_bytes = 2 * n[0] * n[1] * (8 if dt == torch.float64 else 4)  # per neighbour, sweep, way
         res["x".join(map(str, n))] = {
             "rows": rows,
             "exchange_bytes_per_neighbour_per_sweep": exch_bytes,
@@ -954,10 +1007,11 @@ def run_slab(a):
         "metric": "GLUP/s on one GPU's z-slab (mean over the four sweep rows and the shapes)",
         "value": round(mean, 3), "unit": "GLUP/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "one GPU's z-slab of a larger 3D Poisson grid, FP64, seeded "
-                               "uniform[-1,1) RHS, u0=0, 100 sweeps per row",
-                   "slabs": list(res)},
+        "dtype": a.slab_dtype, "data": "synthetic",
+        "config": {"workload": "one GPU's z-slab of a larger 3D Poisson grid (or a whole grid), "
+                               "%s, seeded uniform[-1,1) RHS, u0=0, %d sweeps per row"
+                               % (a.slab_dtype.upper(), nsw),
+                   "slabs": list(res), "rows": sorted(want)},
         "slabs": res}), flush=True)
 
 
