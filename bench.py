@@ -59,6 +59,7 @@ def _args():
     p.add_argument("--patch-baselines", default="per_colour,fused_per_patch",
                    help="patches: the per-patch launch schedules timed beside the batch "
                         "(comma list of per_colour, fused_per_patch; empty for none)")
+    p.add_argument("--serve-count", type=int, default=300, help="serve: requests in the stream")
     p.add_argument("--refine-n", type=int, default=512, help="refine: interior edge")
     p.add_argument("--mg-n", type=int, default=255, help="multigrid: interior edge, 2^m - 1")
     p.add_argument("--mg-gs-compare", type=int, default=1,

@@ -354,7 +354,13 @@ cs_status cs_batch_ir_update(cs_batch bt, const double* scales, void* stream);
  * 24^3 in FP64 and 32^3 in FP32, see cs_batch_resident_policy) run all nsweeps
  * sweeps in one launch, one workgroup per patch, the patch loaded once,
  * swept colour by colour in LDS with a workgroup barrier after each colour,
- * and written back to u.  The other patches read their u / tmp alternately,
+ * and written back to u.  Patches of at most 2^17 points whose halo'd
+ * cross-section fits at least six (7-point) or seven (27-point) times in LDS
+ * (up to about 55 x 55 in FP64), when the batch holds enough of them (see
+ * cs_batch_resident_policy), also run all sweeps in one launch, one
+ * workgroup per patch:
+ * it streams through z with 2 or 3 sweeps per pass, the later sweeps trailing
+ * by two planes, in place in u.  The other patches read their u / tmp alternately,
  * one launch per tile group and pass; the result ends in u (one copy back
  * where a patch's last pass wrote tmp).  Patches of the large 7-point tile
  * class run two red-black sweeps per pass (an odd last sweep alone).  Every
@@ -362,7 +368,7 @@ cs_status cs_batch_ir_update(cs_batch bt, const double* scales, void* stream);
  * tmp of a tiled patch is overwritten with u's. */
 cs_status cs_batch_gs_sweeps(cs_batch bt, int32_t nsweeps, void* stream);
 
-/* *out = sweeps per pass over memory (1 or 2) of patch index (the caller's
+/* *out = sweeps per pass over memory (1, 2 or 3) of patch index (the caller's
  * order) in cs_batch_gs_sweeps, or 0 for a patch swept resident in LDS (all
  * sweeps of a call in one pass).  Errors: CS_EINVAL (NULL, index out of
  * range). */
@@ -374,11 +380,12 @@ cs_status cs_batch_sweeps_per_pass(cs_batch bt, int32_t index, int32_t* out);
  * so its norms do not depend on the rest of the batch. */
 cs_status cs_batch_residual(cs_batch bt, double* norms, void* stream);
 
-/* Tile policy for batches created afterwards (process-wide, per stencil and
- * dtype): a patch with n[0] <= small_max uses the small tile, n[0] <= mid_max
- * the middle one, else the large one (7-point: 16x16, 32x16, 64x16;
- * 27-point: 16x8, 32x16, 64x16).  Set by the autotuner.  Errors: CS_EINVAL
- * for a bad stencil or dtype, or small_max > mid_max. */
+/* Tile policy for batches created or assigned afterwards (process-wide, per
+ * stencil and dtype): a tiled patch with n[0] <= small_max uses the small
+ * tile, n[0] <= mid_max the middle one, else the large one (7-point: 16x16,
+ * 32x16, 64x16; 27-point: 16x8, 32x16, 64x16).  Default 0, 0 (large tiles
+ * only).  Set by the autotuner.  Errors: CS_EINVAL for a bad stencil or
+ * dtype, or small_max > mid_max. */
 cs_status cs_batch_tile_policy(int32_t stencil, int32_t dtype, int32_t small_max, int32_t mid_max);
 
 /* Colour schedule for batches created afterwards (process-wide, per stencil
@@ -388,12 +395,16 @@ cs_status cs_batch_tile_policy(int32_t stencil, int32_t dtype, int32_t small_max
  * dtype, or pair_large not 0/1. */
 cs_status cs_batch_pass_policy(int32_t stencil, int32_t dtype, int32_t pair_large);
 
-/* Resident schedule for batches created afterwards (process-wide, per stencil
- * and dtype): enable = 1 (default) sweeps every patch that fits one
- * workgroup's LDS and registers resident there (all sweeps of a call in one
- * launch), 0 sends every patch to the tile kernels; the iterate is the same
- * either way.  Set by the autotuner.  Errors: CS_EINVAL for a bad stencil or
- * dtype, or enable not 0/1. */
+/* Resident schedules for batches created or assigned afterwards
+ * (process-wide, per stencil and dtype), a bit mask: bit 0 sweeps every patch
+ * that fits one workgroup's LDS and registers resident there; bit 1 streams
+ * the patches whose cross-section fits through one workgroup when the batch
+ * holds at least one such patch of the stencil and dtype for every compute
+ * unit of the device (fewer would leave most of it idle); bit 2 streams them
+ * whatever their number.  Resident and streamed patches run all sweeps of a
+ * call in one launch; the others go to the tile kernels.  Default 3; the
+ * iterate is the same under every mask.  Set by the autotuner.  Errors:
+ * CS_EINVAL for a bad stencil or dtype, or a mask outside [0, 7]. */
 cs_status cs_batch_resident_policy(int32_t stencil, int32_t dtype, int32_t enable);
 
 /* ---- Captured sweep sequences (HIP graphs) -------------------------------

@@ -1,6 +1,7 @@
 // C ABI of the batched patches: validation, grouping, device tables, the
 // per-sweep launches and the batched refinement steps.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <new>
 #include <vector>
@@ -13,18 +14,21 @@ namespace {
 
 struct Group {
     int dtype = 0, stencil = 0, variant = 0;
-    int tier = 0;        // LDS-resident tier (1, 2), or 0 for the tile kernels
+    int tier = 0;        // LDS-resident tier (1, 2), plane streaming (3), or 0 for the tile kernels
     bool pairs = false;  // two sweeps per launch
     std::vector<BatchPatch> host;
     BatchPatch* dev = nullptr;
     int64_t items = 0, res_items = 0, partial_base = 0;
 };
 
-// [stencil][dtype]
-int g_small_max[2][2] = {{16, 16}, {16, 16}};
-int g_mid_max[2][2] = {{40, 40}, {40, 40}};
+// [stencil][dtype].  By default every tiled patch takes the large tiles: on
+// patches of arbitrary shape (the tiled ones, now that small patches are
+// resident or streamed) they sweep fastest despite their ragged edge tiles.
+int g_small_max[2][2] = {{0, 0}, {0, 0}};
+int g_mid_max[2][2] = {{0, 0}, {0, 0}};
 int g_pair_large[2][2] = {{1, 1}, {1, 1}};  // pair the sweeps of the large tile class
-int g_resident[2][2] = {{1, 1}, {1, 1}};    // sweep patches that fit in LDS there
+int g_resident[2][2] = {{3, 3}, {3, 3}};    // bit 0: whole patches in LDS; bit 1: plane streaming
+                                            // for large classes; bit 2: plane streaming always
 
 int pick_variant(int stencil, int dtype, int64_t nx)
 {
@@ -36,6 +40,29 @@ int pick_variant(int stencil, int dtype, int64_t nx)
 int64_t span_of3(const cs_grid_desc& d)
 {
     return (d.n[2] + 1) * d.stride[2] + (d.n[1] + 1) * d.stride[1] + d.n[0] + 2;
+}
+
+// Plane streaming gives each patch one workgroup for all its sweeps: it pays
+// only when a group holds at least one such patch for every compute unit;
+// fewer would leave most of the device idle while the tile kernels could
+// spread the same patches over all of it.
+int planes_min_patches()
+{
+    static std::atomic<int> cu[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return 256;
+    }
+    int n = cu[dev].load(std::memory_order_relaxed);
+    if (n < 1) {
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) {
+            (void)hipGetLastError();
+            n = 256;
+        }
+        cu[dev].store(n, std::memory_order_relaxed);
+    }
+    return n;
 }
 
 // Host plan of a batch: its groups (tables not yet on the device), the sweeps
@@ -55,6 +82,22 @@ cs_status plan_batch(const cs_grid_desc* descs, void* const* u, const void* cons
     if (count < 0) { set_error("count must be >= 0"); return CS_EINVAL; }
     if (count > 0 && (!descs || !u || !b || !tmp)) { set_error("NULL array"); return CS_EINVAL; }
     std::vector<int32_t> seen;
+    // plane-streaming candidates per [stencil][dtype]; a class with fewer
+    // than planes_min_patches() of them keeps the tile kernels
+    int planes_cand[2][2] = {{0, 0}, {0, 0}};
+    for (int32_t i = 0; i < count; ++i) {
+        const cs_grid_desc& d = descs[i];
+        if (validate_desc_pub(&d) != CS_OK || d.dim != 3) continue;  // reported below
+        Geo g{};
+        g.nx = d.n[0];
+        g.ny = d.n[1];
+        g.nz = d.n[2];
+        const int pol = g_resident[d.stencil][d.dtype];
+        if ((pol & 6) && !((pol & 1) && batch_resident_tier(d.dtype, d.stencil, g)) &&
+            batch_planes_fits(d.dtype, d.stencil, g))
+            ++planes_cand[d.stencil][d.dtype];
+    }
+    const int planes_min = planes_min_patches();
     for (int32_t i = 0; i < count; ++i) {
         const cs_grid_desc& d = descs[i];
         cs_status st = validate_desc_pub(&d);
@@ -84,15 +127,19 @@ cs_status plan_batch(const cs_grid_desc* descs, void* const* u, const void* cons
         p.g.sy = d.stride[1];
         p.g.sz = d.stride[2];
         p.g.parity = d.parity;
-        p.u = u[i];
-        p.tmp = tmp[i];
-        p.b = b[i];
+        p.u = (CS_GLOBAL void*)u[i];
+        p.tmp = (CS_GLOBAL void*)tmp[i];
+        p.b = (const CS_GLOBAL void*)b[i];
         p.hh = d.h * d.h;
         p.h2 = d.dtype == CS_F32 ? (double)(float)p.hh : p.hh;
         p.index = row;
         p.stencil = d.stencil;
         p.dtype = d.dtype;
-        const int tier = g_resident[d.stencil][d.dtype] ? batch_resident_tier(d.dtype, d.stencil, p.g) : 0;
+        const int pol = g_resident[d.stencil][d.dtype];
+        int tier = (pol & 1) ? batch_resident_tier(d.dtype, d.stencil, p.g) : 0;
+        if (!tier && ((pol & 4) || ((pol & 2) && planes_cand[d.stencil][d.dtype] >= planes_min)) &&
+            batch_planes_fits(d.dtype, d.stencil, p.g))
+            tier = 3;
         const int variant = tier ? 0 : pick_variant(d.stencil, d.dtype, d.n[0]);
         const bool pairs = !tier && batch_variant_pairs(d.stencil, variant) && g_pair_large[d.stencil][d.dtype];
         int tx = 0, ty = 0;
@@ -119,7 +166,8 @@ cs_status plan_batch(const cs_grid_desc* descs, void* const* u, const void* cons
         }
         pl->groups[k].host.push_back(p);
         pl->by_index.push_back(p);
-        pl->per_pass.push_back(tier ? 0 : (pairs ? 2 : 1));
+        pl->per_pass.push_back(tier == 3 ? batch_planes_sweeps(d.dtype, d.stencil, p.g)
+                               : (tier ? 0 : (pairs ? 2 : 1)));
         pl->rows = std::max(pl->rows, row + 1);
     }
     std::sort(seen.begin(), seen.end());
@@ -293,7 +341,7 @@ cs_status cs_batch_pass_policy(int32_t stencil, int32_t dtype, int32_t pair_larg
 cs_status cs_batch_resident_policy(int32_t stencil, int32_t dtype, int32_t enable)
 {
     if ((stencil != CS_FD && stencil != CS_Q1) || (dtype != CS_F64 && dtype != CS_F32) ||
-        (enable != 0 && enable != 1)) {
+        enable < 0 || enable > 7) {
         set_error("bad resident policy");
         return CS_EINVAL;
     }
@@ -381,7 +429,7 @@ cs_status cs_batch_ir_attach(cs_batch bt, const cs_grid_desc* descs64, void* con
         if ((st = check_device_range_pub(x[i], bytes, 8, "patch x")) != CS_OK ||
             (st = check_device_range_pub(b[i], bytes, 8, "patch b")) != CS_OK)
             return st;
-        if (x[i] == b[i] || x[i] == p.u || x[i] == p.b || x[i] == p.tmp) {
+        if (x[i] == b[i] || x[i] == (const void*)p.u || x[i] == (const void*)p.b || x[i] == (const void*)p.tmp) {
             set_error("patch %d: x must be separate from b and the FP32 arrays", i);
             return CS_EINVAL;
         }
@@ -393,10 +441,10 @@ cs_status cs_batch_ir_attach(cs_batch bt, const cs_grid_desc* descs64, void* con
         q.g.sz = d.stride[2];
         q.g.parity = d.parity;
         q.g2 = p.g;
-        q.x = (double*)x[i];
-        q.b = (const double*)b[i];
-        q.e = (float*)p.u;
-        q.r32 = (float*)p.b;
+        q.x = (CS_GLOBAL double*)x[i];
+        q.b = (const CS_GLOBAL double*)b[i];
+        q.e = (CS_GLOBAL float*)p.u;
+        q.r32 = (CS_GLOBAL float*)p.b;
         q.hh = d.h * d.h;
         q.stencil = d.stencil;
         q.row = p.index;
@@ -453,12 +501,15 @@ cs_status cs_batch_gs_sweeps(cs_batch bt, int32_t nsweeps, void* stream)
     if (nsweeps == 0) return CS_OK;
     hipStream_t s = (hipStream_t)stream;
     cs_status st;
-    // LDS-resident groups: every sweep in one launch, in place in u
-    for (auto& gr : bt->groups)
-        if (gr.tier &&
-            (st = launch_batch_resident(gr.dtype, gr.stencil, gr.tier, gr.dev, (int)gr.host.size(),
-                                        nsweeps, s)) != CS_OK)
-            return st;
+    // LDS-resident and plane-streaming groups: every sweep in one launch, in
+    // place in u
+    for (auto& gr : bt->groups) {
+        if (!gr.tier) continue;
+        st = gr.tier == 3 ? launch_batch_planes(gr.dtype, gr.stencil, gr.dev, (int)gr.host.size(), nsweeps, s)
+                          : launch_batch_resident(gr.dtype, gr.stencil, gr.tier, gr.dev, (int)gr.host.size(),
+                                                  nsweeps, s);
+        if (st != CS_OK) return st;
+    }
     for (auto& gr : bt->groups)
         if (!gr.tier && (st = launch_batch_halo(gr.dtype, gr.dev, (int)gr.host.size(), s)) != CS_OK)
             return st;

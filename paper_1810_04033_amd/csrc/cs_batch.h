@@ -5,12 +5,18 @@
 
 namespace cs {
 
+// Array pointers in the device tables are typed as global memory: a pointer
+// loaded from memory is otherwise generic, and the kernels would access the
+// arrays with flat instructions, which also count against the LDS wait counter
+// (every LDS wait would then wait for the prefetched loads as well).
+#define CS_GLOBAL __attribute__((address_space(1)))
+
 // One patch of a batch group, as stored in the group's device table.
 struct BatchPatch {
     Geo g;
-    void* u;          // iterate (the result ends here)
-    void* tmp;        // work array with u's layout
-    const void* b;    // right-hand side
+    CS_GLOBAL void* u;        // iterate (the result ends here)
+    CS_GLOBAL void* tmp;      // work array with u's layout
+    const CS_GLOBAL void* b;  // right-hand side
     double h2;        // h^2 as the sweeps use it (rounded to FP32 for FP32 patches)
     double hh;        // h*h in FP64 (residual)
     int tiles_x, tiles_y, chunks;
@@ -27,10 +33,10 @@ struct BatchPatch {
 struct IrPatch {
     Geo g;            // x and b
     Geo g2;           // e and r32
-    double* x;
-    const double* b;
-    float* e;
-    float* r32;
+    CS_GLOBAL double* x;
+    const CS_GLOBAL double* b;
+    CS_GLOBAL float* e;
+    CS_GLOBAL float* r32;
     double hh;        // h*h (FP64)
     int stencil;
     int row;          // row in the norms and scales
@@ -61,6 +67,13 @@ cs_status launch_batch_ir_residual(const IrPatch* tab, int count, int64_t items,
                                    double* scales, double* norms, hipStream_t s);
 cs_status launch_batch_ir_update(const IrPatch* tab, int count, int64_t items, const double* scales,
                                  hipStream_t s);
+// Whether a patch is swept by the plane-streaming tier (its whole halo'd
+// cross-section fits at least 2 x 2 + 1 + NPL times in LDS), and its launch:
+// all nsweeps sweeps, one workgroup per patch, in place in u.
+bool batch_planes_fits(int dtype, int stencil, const Geo& g);
+int batch_planes_sweeps(int dtype, int stencil, const Geo& g);  // sweeps per pass there
+cs_status launch_batch_planes(int dtype, int stencil, const BatchPatch* tab, int count, int nsweeps,
+                              hipStream_t s);
 cs_status launch_batch_halo(int dtype, const BatchPatch* tab, int count, hipStream_t s);
 cs_status launch_batch_copyback(int dtype, const BatchPatch* tab, int count, int64_t res_items,
                                 hipStream_t s);

@@ -166,6 +166,263 @@ k_batch_resident(const BatchPatch* __restrict__ tab, int nsweeps)
     }
 }
 
+// Patches whose whole halo'd cross-section fits several times in LDS: one
+// workgroup per patch streams through z with S sweeps per pass, in place in
+// u.  Sweep j trails sweep j-1 by two planes, in the order of the colour
+// passes:
+//   7-point, step t:   R_j on plane t-2j, then B_j on plane t-2j-1, j = 0..S-1
+//   27-point, step t:  A_j, B_j on plane t-2j, then C_j, D_j on plane t-2j-1
+// (t runs over all planes for 7 points, over the "even" planes, two per step,
+// for 27 points; A..D are the four row phases).  Every update reads the values
+// the colour passes give it: the neighbour plane t-2j+1 already holds sweep
+// j-1 (its last phase ran earlier in the step), the plane t-2j-1 still holds
+// sweep j-1 (sweep j reaches it later).  The tile is the whole cross-section,
+// so nothing is recomputed.  A window of 2S+1+NPL planes (NPL planes per step)
+// lives in LDS slots, the planes leaving it are final and go back to u, and
+// the planes entering it are old ones (the pass has not written them).  Passes
+// repeat until nsweeps sweeps are done.  Each thread owns pairs of columns of
+// opposite classes ((x, x+1) in row-major order for 7 points, rows (y, y+1) at
+// one x for 27 points), so every phase gives it one point per pair; the
+// right-hand side of its columns rides in a shift register of planes.  Point
+// updates are the colour pass's, so the iterate equals the colour passes' bit
+// for bit.
+template <typename T, int ST, int NT, int CAP, int SMAX, int PP, int MPL>
+__global__ void __launch_bounds__(NT)
+k_batch_planes(const BatchPatch* __restrict__ tab, int nsweeps)
+{
+    constexpr int NPL = ST == FD ? 1 : 2;      // planes per step
+    constexpr int RB = NPL + 2 * SMAX - 1;     // b register: ring[d] = plane t + NPL - 1 - d
+    __shared__ __attribute__((aligned(16))) T L[CAP];
+    const BatchPatch P = tab[blockIdx.x];
+    const Geo& g = P.g;
+    const int nx = (int)g.nx, ny = (int)g.ny, nz = (int)g.nz;
+    const int wx = nx + 2, PL = wx * (ny + 2);
+    int smax = (CAP / PL - 1 - NPL) / 2;
+    if (smax > SMAX) smax = SMAX;
+    T* u = (T*)P.u;
+    const T* __restrict__ b = (const T*)P.b;
+    const T h2 = (T)P.h2;
+    const int tid = threadIdx.x;
+    const int par = g.parity;
+
+    // column pairs: LDS and global in-plane offsets and the class of each
+    // column (7 points: (x-1)+(y-1)+parity; 27 points: the row type)
+    int lo[PP][2], go[PP][2], cls[PP][2];
+#pragma unroll
+    for (int q = 0; q < PP; ++q) {
+        const int pi = tid + NT * q;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            int x, y;
+            bool ok;
+            if (ST == FD) {
+                const int c = 2 * pi + h;
+                ok = c < nx * ny;
+                x = 1 + (ok ? c % nx : 0);
+                y = 1 + (ok ? c / nx : 0);
+            } else {
+                ok = pi < nx * ((ny + 1) / 2);
+                x = 1 + (ok ? pi % nx : 0);
+                y = 1 + (ok ? 2 * (pi / nx) + h : 0);
+                ok = ok && y <= ny;
+            }
+            lo[q][h] = ok ? y * wx + x : -1;
+            go[q][h] = ok ? (int)(y * g.sy + x) : 0;
+            cls[q][h] = ST == FD ? (((x - 1) + (y - 1) + par) & 1) : ((y - 1 + par) & 1);
+        }
+    }
+    int goff[MPL];
+#pragma unroll
+    for (int m = 0; m < MPL; ++m) {
+        const int t = tid + NT * m;
+        const int y = t / wx;
+        goff[m] = t < PL ? (int)(y * g.sy + (t - y * wx)) : -1;
+    }
+    // (the offsets go through an empty asm so that their 64-bit addresses are
+    // formed where used instead of being kept live across the step loop)
+    auto load_plane = [&](int k, T* v) {
+        const bool kin = k >= 0 && k <= nz + 1;
+        const T* sp = u + (kin ? k : 0) * g.sz;
+#pragma unroll
+        for (int m = 0; m < MPL; ++m) {
+            int o = goff[m];
+            asm volatile("" : "+v"(o));
+            v[m] = (kin && o >= 0) ? sp[o] : T(0);
+        }
+    };
+    auto load_b = [&](int k, T (&v)[PP][2]) {
+        const bool kin = k >= 1 && k <= nz;
+        const T* bp = b + (kin ? k : 0) * g.sz;
+#pragma unroll
+        for (int q = 0; q < PP; ++q)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                int o = go[q][h];
+                asm volatile("" : "+v"(o));
+                v[q][h] = (kin && lo[q][h] >= 0) ? bp[o] : T(0);
+            }
+    };
+    auto is_even = [&](int k) { return ((k - 1 + par) & 1) == 0; };
+
+    T ring[PP][2][RB];
+    for (int done = 0; done < nsweeps;) {
+        const int S = nsweeps - done < smax ? nsweeps - done : smax;
+        const int NS = 2 * S + 1 + NPL;
+        // slot of plane p = p mod NS, formed from the current step's slot
+        // (a modulo by a run-time NS costs a long scalar sequence per call,
+        // repeated by every wave); planes lie within NS of the step's plane
+        const int t0 = ST == FD ? 1 : (is_even(1) ? 1 : 2);
+        int tcur = t0, sbase = t0 % NS;
+        auto slot = [&](int p) -> T* {
+            int k = sbase + (p - tcur);
+            k += k < 0 ? NS : 0;
+            k -= k >= NS ? NS : 0;
+            return L + k * PL;
+        };
+        auto store_plane = [&](const T* v, int p) {
+            T* lp = slot(p);
+#pragma unroll
+            for (int m = 0; m < MPL; ++m) {
+                const int t = tid + NT * m;
+                if (t < PL) lp[t] = v[m];
+            }
+        };
+        auto write_plane = [&](int p) {
+            if (p < 1 || p > nz) return;
+            const T* lp = slot(p);
+            T* dp = u + p * g.sz;
+#pragma unroll
+            for (int q = 0; q < PP; ++q)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    int o = go[q][h], l = lo[q][h];
+                    asm volatile("" : "+v"(o), "+v"(l));
+                    if (l >= 0) dp[o] = lp[l];
+                }
+        };
+        // the thread's points of class `sel` on plane p, b from rb: the two
+        // columns of a pair have opposite classes, so each pair gives exactly
+        // one point, picked by a select rather than a branch per column (a
+        // divergent branch per column costs a run of scalar mask instructions
+        // in every wave, and the scalar unit is shared by the CU)
+        auto phase = [&](int p, int sel, const T (&rb)[PP][2]) {
+            if (p < 1 || p > nz) return;
+            const T* lm = slot(p - 1);
+            T* lk = slot(p);
+            const T* lq = slot(p + 1);
+#pragma unroll
+            for (int q = 0; q < PP; ++q) {
+                const bool first = cls[q][0] == sel;
+                // opaque, so neither the selected offset nor the neighbour
+                // addresses are hoisted out of the step loop (all of them
+                // live at once would spill)
+                int l0 = lo[q][0], l1 = lo[q][1];
+                asm volatile("" : "+v"(l0), "+v"(l1));
+                int o = first ? l0 : l1;
+                T bq = first ? rb[q][0] : rb[q][1];
+                if (o < 0) continue;
+                asm volatile("" : "+v"(o), "+v"(bq));
+                auto ld = [&](int ox, int oy, int oz) {
+                    const T* pl = oz < 0 ? lm : (oz > 0 ? lq : lk);
+                    return pl[o + oy * wx + ox];
+                };
+                lk[o] = gs_value<T, 3, ST>(h2, bq, ld);
+            }
+        };
+        const int t_last = nz + 2 * S - 1;
+        // planes 0 .. t0+1-NPL straight into LDS, t0+2-NPL .. t0+1 into the
+        // registers stored at the top of the first step
+        {
+            T v[MPL];
+            for (int k = 0; k <= t0 + 1 - NPL; ++k) {
+                load_plane(k, v);
+                store_plane(v, k);
+            }
+        }
+        T pre[NPL][MPL];
+        T bnew[NPL][PP][2];
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) load_plane(t0 + 2 - NPL + i, pre[i]);
+#pragma unroll
+        for (int d = 0; d < RB; ++d) {
+            T tb[PP][2];
+            load_b(t0 + NPL - 1 - d, tb);
+#pragma unroll
+            for (int q = 0; q < PP; ++q)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) ring[q][h][d] = tb[q][h];
+        }
+        for (int t = t0; t <= t_last; t += NPL) {
+#pragma unroll
+            for (int i = 0; i < NPL; ++i)
+                if (t + 2 - NPL + i <= nz + 1) store_plane(pre[i], t + 2 - NPL + i);
+            const bool more = t + NPL <= t_last;
+            if (more) {
+#pragma unroll
+                for (int i = 0; i < NPL; ++i) {
+                    load_plane(t + 2 + i, pre[i]);
+                    load_b(t + 2 * NPL - 1 - i, bnew[i]);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < SMAX; ++j) {
+                if (j < S) {
+                    T r0[PP][2], r1[PP][2];
+#pragma unroll
+                    for (int q = 0; q < PP; ++q)
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            r0[q][h] = ring[q][h][NPL - 1 + 2 * j];  // plane t - 2j
+                            r1[q][h] = ring[q][h][NPL + 2 * j];      // plane t - 2j - 1
+                        }
+                    const int p0 = t - 2 * j, p1 = t - 2 * j - 1;
+                    if (ST == FD) {
+                        phase(p0, (p0 - 1) & 1, r0);  // red of plane p0
+                        __syncthreads();
+                        phase(p1, p1 & 1, r1);        // black of plane p1
+                        __syncthreads();
+                    } else {
+                        phase(p0, 0, r0);             // A
+                        __syncthreads();
+                        phase(p0, 1, r0);             // B
+                        __syncthreads();
+                        phase(p1, 0, r1);             // C
+                        __syncthreads();
+                        phase(p1, 1, r1);             // D
+                        __syncthreads();
+                    }
+                }
+            }
+            // planes finished by the last sweep of the pass
+            if (ST == FD) {
+                write_plane(t - 2 * S + 1);
+            } else {
+                write_plane(t - 2 * S + 2);
+                write_plane(t - 2 * S + 1);
+            }
+            if (more) {
+#pragma unroll
+                for (int q = 0; q < PP; ++q)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                        for (int d = RB - 1; d >= NPL; --d) ring[q][h][d] = ring[q][h][d - NPL];
+#pragma unroll
+                        for (int i = 0; i < NPL; ++i) ring[q][h][i] = bnew[i][q][h];
+                    }
+            }
+            tcur += NPL;
+            sbase += NPL;
+            sbase -= sbase >= NS ? NS : 0;
+        }
+        done += S;
+        // the next pass reads back what this one wrote
+        __threadfence_block();
+        __syncthreads();
+    }
+}
+
 // Halo copy u -> tmp, one workgroup per patch.
 template <typename T>
 __global__ void __launch_bounds__(256) k_batch_halo(const BatchPatch* __restrict__ tab)
@@ -587,6 +844,66 @@ cs_status launch_batch_resident(int dtype, int stencil, int tier, const BatchPat
     }
 #undef CS_RES
     return check_launch("batched resident sweeps");
+}
+
+// The plane-streaming tier: 1024 threads, the whole LDS, at most 3 (7-point)
+// or 2 (27-point) sweeps per pass and two column pairs per thread, taken where
+// at least 2 sweeps fit.
+namespace {
+constexpr int kPlNT = 1024;
+constexpr int pl_smax(int st) { return st == FD ? 3 : 2; }
+constexpr int pl_pp(int) { return 2; }
+constexpr int kPlCap64 = 20000, kPlCap32 = 40000;  // elements: 160 KB
+constexpr int pl_mpl(int cap, int npl) { return (cap / (2 * 2 + 1 + npl) + kPlNT - 1) / kPlNT; }
+}  // namespace
+
+int batch_planes_sweeps(int dtype, int stencil, const Geo& g)
+{
+    const int npl = stencil == FD ? 1 : 2;
+    const int64_t pl = (g.nx + 2) * (g.ny + 2);
+    const int64_t cap = dtype == 0 ? kPlCap64 : kPlCap32;
+    const int64_t s = (cap / pl - 1 - npl) / 2;
+    const int smax = stencil == FD ? pl_smax(FD) : pl_smax(Q1);
+    return (int)(s < smax ? s : smax);
+}
+
+// At most this many points: one workgroup carries the whole patch, so a much
+// larger patch would make one long pole for the batch (a serving step waits
+// for its slowest patch), while the tile kernels spread it over the device.
+constexpr int64_t kPlMaxPoints = 1 << 17;
+
+bool batch_planes_fits(int dtype, int stencil, const Geo& g)
+{
+    if (g.nx * g.ny * g.nz > kPlMaxPoints) return false;
+    const int npl = stencil == FD ? 1 : 2;
+    const int64_t pl = (g.nx + 2) * (g.ny + 2);
+    const int64_t cap = dtype == 0 ? kPlCap64 : kPlCap32;
+    const int64_t s = (cap / pl - 1 - npl) / 2;
+    const int64_t pairs = stencil == FD ? (g.nx * g.ny + 1) / 2 : g.nx * ((g.ny + 1) / 2);
+    return s >= 2 && pairs <= (int64_t)kPlNT * (stencil == FD ? pl_pp(FD) : pl_pp(Q1)) && g.nz >= 1;
+}
+
+cs_status launch_batch_planes(int dtype, int stencil, const BatchPatch* tab, int count, int nsweeps,
+                              hipStream_t s)
+{
+    if (count <= 0 || nsweeps <= 0) return CS_OK;
+    const dim3 grid((unsigned)count), blk(kPlNT);
+    if (dtype == 0) {
+        if (stencil == FD)
+            hipLaunchKernelGGL((k_batch_planes<double, FD, kPlNT, kPlCap64, pl_smax(FD), pl_pp(FD), pl_mpl(kPlCap64, 1)>),
+                               grid, blk, 0, s, tab, nsweeps);
+        else
+            hipLaunchKernelGGL((k_batch_planes<double, Q1, kPlNT, kPlCap64, pl_smax(Q1), pl_pp(Q1), pl_mpl(kPlCap64, 2)>),
+                               grid, blk, 0, s, tab, nsweeps);
+    } else {
+        if (stencil == FD)
+            hipLaunchKernelGGL((k_batch_planes<float, FD, kPlNT, kPlCap32, pl_smax(FD), pl_pp(FD), pl_mpl(kPlCap32, 1)>),
+                               grid, blk, 0, s, tab, nsweeps);
+        else
+            hipLaunchKernelGGL((k_batch_planes<float, Q1, kPlNT, kPlCap32, pl_smax(Q1), pl_pp(Q1), pl_mpl(kPlCap32, 2)>),
+                               grid, blk, 0, s, tab, nsweeps);
+    }
+    return check_launch("batched plane-streaming sweeps");
 }
 
 cs_status launch_batch_halo(int dtype, const BatchPatch* tab, int count, hipStream_t s)

@@ -233,6 +233,7 @@ class GpuExecutor:
         self.has_mixed = False
         self.has_fp64 = False
         self._pending = None
+        self.point_sweeps = 0  # interior points times sweeps, over all steps
 
     def close(self):
         for h in ("b64", "b32"):
@@ -326,6 +327,8 @@ class GpuExecutor:
         e1.record(s)
         for t in tickets:
             t.sweeps += k
+            nx, ny, nz = t.req.n
+            self.point_sweeps += nx * ny * nz * k
         prev = self._pending
         self._pending = ([(t, t.state["row"]) for t in tickets], self.buf, e0, e1)
         self.buf ^= 1
@@ -396,8 +399,18 @@ def serve_measure(count):
         done = sch.run(tickets)
         ex.close()
         t_last = max(t.finished_s for t in done)
-        return sch.stats.summary(reqs[0].arrival_s, t_last)
+        out = sch.stats.summary(reqs[0].arrival_s, t_last)
+        # sweep work done per second of the serving span (GS updates / s)
+        out["GLUP_per_s"] = ex.point_sweeps / out["span_s"] / 1e9 if out["span_s"] else None
+        return out
 
+    # warm-up: a short stream first, as on a server that is already running
+    # (first-use costs of the allocator, pinned buffers and kernels)
+    reqs = I.request_stream(6, 24, 2000.0)
+    ex = GpuExecutor(max_active=256)
+    Scheduler(ex, budget_bytes=32 << 30, max_active=256, sweeps_per_step=k, tol=1e-8,
+              clock=time.perf_counter).run(make_tickets(reqs))
+    ex.close()
     results["offered_2000_per_s"] = serve_at(2000.0)
     capacity = results["offered_2000_per_s"]["patches_per_s"]
     # below capacity the latencies measure service, not queueing

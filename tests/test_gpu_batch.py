@@ -37,8 +37,29 @@ SHAPES = [(1, 1, 1), (2, 3, 4), (5, 7, 3), (8, 8, 8), (16, 16, 16), (17, 9, 12),
           (33, 20, 18), (48, 48, 48), (64, 64, 64), (70, 13, 65), (40, 66, 9)]
 
 
+def _set_policies(tile, resident):
+    for st in (C.CS_FD, C.CS_Q1):
+        for dt in (C.CS_F64, C.CS_F32):
+            C.cs_batch_tile_policy(st, dt, *tile)
+            C.cs_batch_resident_policy(st, dt, resident)
+
+
+@pytest.mark.parametrize("policy", ["default", "all_tile_classes"])
 @pytest.mark.parametrize("nsw", [1, 2, 3, 4, 5])
-def test_mixed_batch_matches_oracle(nsw):
+def test_mixed_batch_matches_oracle(nsw, policy):
+    """A mixed batch (both stencils, FP64 and FP32, shapes from 1^3 to 70 x 13 x
+    65, both parities, odd layouts) equals the oracle: under the default
+    policies, and with every tile class in use (small and middle tiles for
+    the smaller patches, nothing resident)."""
+    if policy != "default":
+        _set_policies((16, 40), 0)
+    try:
+        _mixed_batch_case(nsw)
+    finally:
+        _set_policies((0, 0), 3)
+
+
+def _mixed_batch_case(nsw):
     ps = []
     for i, n in enumerate(SHAPES):
         for st in (C.CS_FD, C.CS_Q1):
@@ -135,19 +156,28 @@ def test_patch_workload_4096_sampled():
 
 def test_sweeps_per_pass_by_tile_class():
     """Patches of the large 7-point tile class run two sweeps per pass, the
-    other tiled ones (middle class, 27-point) one, and patches that fit in LDS
-    all sweeps of a call in one pass (reported as 0); bad queries are
-    rejected."""
+    other tiled ones (27-point here) one, patches that fit in LDS all sweeps of
+    a call in one pass (reported as 0), and patches streamed through one
+    workgroup up to three per pass; bad queries are rejected."""
     ps = [_patch(n, st, torch.float64, 0, seed=1700 + i)
           for i, (n, st) in enumerate([((8, 8, 8), C.CS_FD), ((64, 64, 64), C.CS_FD),
                                        ((64, 64, 64), C.CS_Q1), ((30, 30, 30), C.CS_FD)])]
     bt = _batch(ps)
-    assert [bt.sweeps_per_pass(i) for i in range(4)] == [0, 2, 1, 1]
+    # one streamable 7-point patch is too few to stream by default: it takes
+    # the large tiles, two sweeps per pass
+    assert [bt.sweeps_per_pass(i) for i in range(4)] == [0, 2, 1, 2]
     for bad in (-1, 4):
         with pytest.raises(C.ColstenError) as e:
             bt.sweeps_per_pass(bad)
         assert e.value.status == C.CS_EINVAL
     bt.close()
+    C.cs_batch_resident_policy(C.CS_FD, C.CS_F64, 7)
+    try:
+        bt = _batch(ps)
+        assert [bt.sweeps_per_pass(i) for i in range(4)] == [0, 2, 1, 3]
+        bt.close()
+    finally:
+        C.cs_batch_resident_policy(C.CS_FD, C.CS_F64, 3)
 
 
 def test_pass_policy_one_sweep_per_pass_same_iterate():
@@ -157,6 +187,7 @@ def test_pass_policy_one_sweep_per_pass_same_iterate():
     res = {}
     for pair in (1, 0):
         C.cs_batch_pass_policy(C.CS_FD, C.CS_F64, pair)
+        C.cs_batch_resident_policy(C.CS_FD, C.CS_F64, 1)  # no plane streaming: tiles only
         try:
             ps = [_patch(n, C.CS_FD, torch.float64, i % 2, seed=1800 + i) for i, n in enumerate(shapes)]
             bt = _batch(ps)
@@ -167,6 +198,7 @@ def test_pass_policy_one_sweep_per_pass_same_iterate():
             bt.close()
         finally:
             C.cs_batch_pass_policy(C.CS_FD, C.CS_F64, 1)
+            C.cs_batch_resident_policy(C.CS_FD, C.CS_F64, 3)
     assert res[1][1] == [2, 2, 0] and res[0][1] == [1, 1, 0]
     for a, b in zip(res[1][0], res[0][0]):
         assert np.array_equal(a, b)
@@ -193,7 +225,7 @@ def test_resident_patches_equal_tiles_and_oracle(nsw, st):
     24^3 FP64 and 32^3 FP32 large tier, one more point along x leaves it),
     non-cubic shapes, both parities and an odd layout, and equal the oracle."""
     res = {}
-    for policy in (1, 0):
+    for policy in (1, 0, 3):
         for dt in (torch.float64, torch.float32):
             C.cs_batch_resident_policy(st, C._DT[dt], policy)
         try:
@@ -207,15 +239,17 @@ def test_resident_patches_equal_tiles_and_oracle(nsw, st):
             bt.close()
         finally:
             for dt in (torch.float64, torch.float32):
-                C.cs_batch_resident_policy(st, C._DT[dt], 1)
+                C.cs_batch_resident_policy(st, C._DT[dt], 3)
     for i, (n, dt, tier) in enumerate(RESIDENT):
         assert (res[1][1][i] == 0) == (tier > 0), (n, dt)
-        assert res[0][1][i] != 0
+        assert res[0][1][i] in (1, 2)
+        assert (res[3][1][i] == 0) == (tier > 0)
         assert np.array_equal(res[1][0][i], res[0][0][i]), (n, dt)
+        assert np.array_equal(res[3][0][i], res[0][0][i]), (n, dt)
         p = res[1][2][i]
         assert G.relmax(res[1][0][i], _oracle(p, nsw)) <= TOL[dt], (n, dt)
     with pytest.raises(C.ColstenError):
-        C.cs_batch_resident_policy(st, 0, 2)
+        C.cs_batch_resident_policy(st, 0, 8)
 
 
 def test_resident_patch_alone_equals_patch_in_mix():
@@ -237,3 +271,94 @@ def test_resident_patch_alone_equals_patch_in_mix():
         assert torch.equal(probe["ug"], alone["ug"])
         bm.close()
         ba.close()
+
+
+def _expected_per_pass(n, st, dt, mask):
+    """Sweeps per pass the batch should report, from the documented tier rules
+    (default tile and pass policies), for a batch too small to stream under
+    bit 1 alone."""
+    nx, ny, nz = n
+    f64 = dt == torch.float64
+    fd = st == C.CS_FD
+    if mask & 1:
+        elems = (nx + 2) * (ny + 2) * (nz + 2)
+        per = (nx + 1) // 2 * ny * nz if fd else nx * ((ny + 1) // 2) * ((nz + 1) // 2)
+        if elems <= 6144 and per <= 512 * (4 if fd else 2):
+            return 0
+        cap = 17600 if f64 else 40000
+        pmax = (7 if fd else 4) if f64 else (16 if fd else 8)
+        if elems <= cap and per <= 1024 * pmax:
+            return 0
+    if mask & 4 and nx * ny * nz <= 1 << 17:
+        npl = 1 if fd else 2
+        s_ = ((20000 if f64 else 40000) // ((nx + 2) * (ny + 2)) - 1 - npl) // 2
+        pairs = (nx * ny + 1) // 2 if fd else nx * ((ny + 1) // 2)
+        if s_ >= 2 and pairs <= 2048:
+            return min(s_, 3 if fd else 2)
+    return 2 if fd else 1
+
+
+PLANES = [(32, 32, 32), (48, 48, 48), (25, 24, 24), (33, 9, 100), (40, 50, 3), (30, 30, 8),
+          (55, 40, 30), (64, 64, 20), (80, 70, 9), (45, 44, 2)]
+
+
+@pytest.mark.parametrize("nsw", [1, 4, 5, 7])
+@pytest.mark.parametrize("st", [C.CS_FD, C.CS_Q1])
+def test_plane_streamed_patches_equal_tiles_and_oracle(nsw, st):
+    """Patches whose cross-section fits several planes of LDS run every sweep
+    of a call in one launch, streamed through z two or three sweeps per pass,
+    in place; with that schedule off they take the tile kernels.  The reported
+    sweeps per pass follow the tier rules, and both schedules give the same
+    iterate bit for bit, equal to the oracle: cubic and flat shapes, a thin
+    slab, both parities, an odd layout, FP64 and FP32."""
+    cases = [(n, dt) for n in PLANES for dt in (torch.float64, torch.float32)]
+    res = {}
+    for policy in (7, 1):
+        for dt in (torch.float64, torch.float32):
+            C.cs_batch_resident_policy(st, C._DT[dt], policy)
+        try:
+            ps = [_patch(n, st, dt, i % 2, seed=2400 + 7 * i + st, layout="odd" if i % 4 == 3 else "aligned")
+                  for i, (n, dt) in enumerate(cases)]
+            bt = _batch(ps)
+            per = [bt.sweeps_per_pass(i) for i in range(len(ps))]
+            bt.gs(nsw)
+            torch.cuda.synchronize()
+            res[policy] = ([G.download(p["ug"]) for p in ps], per, ps)
+            bt.close()
+        finally:
+            for dt in (torch.float64, torch.float32):
+                C.cs_batch_resident_policy(st, C._DT[dt], 3)
+    streamed = 0
+    for i, (n, dt) in enumerate(cases):
+        for policy in (7, 1):
+            assert res[policy][1][i] == _expected_per_pass(n, st, dt, policy), (n, dt, policy)
+        streamed += _expected_per_pass(n, st, dt, 7) != _expected_per_pass(n, st, dt, 1)
+        assert np.array_equal(res[7][0][i], res[1][0][i]), (n, dt)
+        assert G.relmax(res[7][0][i], _oracle(res[7][2][i], nsw)) <= TOL[dt], (n, dt)
+    assert streamed >= 8
+
+
+def test_streaming_needs_a_patch_per_compute_unit():
+    """Under the default mask the streamable patches of a stencil and dtype
+    are streamed only when the batch holds one per compute unit: a batch of
+    that many streams every one of them, a batch of one fewer sweeps them all
+    with the tile kernels, and the shared patches end bit for bit equal, and
+    equal to the oracle."""
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    n = (26, 26, 30)  # beyond the resident tiers, streamable
+    ps = [_patch(n, C.CS_FD, torch.float64, i % 2, seed=2600 + i) for i in range(ncu)]
+    bt_all = _batch(ps)
+    assert {bt_all.sweeps_per_pass(i) for i in range(ncu)} == {3}
+    bt_all.gs(5)
+    torch.cuda.synchronize()
+    got_all = [G.download(ps[i]["ug"]) for i in (0, 1, ncu - 2)]
+    bt_all.close()
+    qs = [_patch(n, C.CS_FD, torch.float64, i % 2, seed=2600 + i) for i in range(ncu - 1)]
+    bt_less = _batch(qs)
+    assert {bt_less.sweeps_per_pass(i) for i in range(ncu - 1)} == {2}
+    bt_less.gs(5)
+    torch.cuda.synchronize()
+    for k, i in enumerate((0, 1, ncu - 2)):
+        assert np.array_equal(got_all[k], G.download(qs[i]["ug"])), i
+    bt_less.close()
+    assert G.relmax(got_all[1], _oracle(_patch(n, C.CS_FD, torch.float64, 1, seed=2601), 5)) <= 1e-13
