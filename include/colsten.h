@@ -360,7 +360,9 @@ cs_status cs_batch_ir_update(cs_batch bt, const double* scales, void* stream);
  * cs_batch_resident_policy), also run all sweeps in one launch, one
  * workgroup per patch:
  * it streams through z with 2 or 3 sweeps per pass, the later sweeps trailing
- * by two planes, in place in u.  The other patches read their u / tmp alternately,
+ * by two planes, in place in u.  Small groups of the remaining patches are
+ * swept one colour at a time in place (see cs_batch_colour_policy).  The other
+ * patches read their u / tmp alternately,
  * one launch per tile group and pass; the result ends in u (one copy back
  * where a patch's last pass wrote tmp).  Patches of the large 7-point tile
  * class run two red-black sweeps per pass (an odd last sweep alone).  Every
@@ -369,8 +371,9 @@ cs_status cs_batch_ir_update(cs_batch bt, const double* scales, void* stream);
 cs_status cs_batch_gs_sweeps(cs_batch bt, int32_t nsweeps, void* stream);
 
 /* *out = sweeps per pass over memory (1, 2 or 3) of patch index (the caller's
- * order) in cs_batch_gs_sweeps, or 0 for a patch swept resident in LDS (all
- * sweeps of a call in one pass).  Errors: CS_EINVAL (NULL, index out of
+ * order) in cs_batch_gs_sweeps (1 also for the colour passes, one launch per
+ * colour), or 0 for a patch swept resident in LDS (all sweeps of a call in
+ * one pass).  Errors: CS_EINVAL (NULL, index out of
  * range). */
 cs_status cs_batch_sweeps_per_pass(cs_batch bt, int32_t index, int32_t* out);
 
@@ -394,6 +397,18 @@ cs_status cs_batch_tile_policy(int32_t stencil, int32_t dtype, int32_t small_max
  * either way.  Set by the autotuner.  Errors: CS_EINVAL for a bad stencil or
  * dtype, or pair_large not 0/1. */
 cs_status cs_batch_pass_policy(int32_t stencil, int32_t dtype, int32_t pair_large);
+
+/* Colour-pass schedule for batches created or assigned afterwards
+ * (process-wide, per stencil and dtype): a group of tiled patches (one
+ * stencil, dtype and tile class) with fewer than max_points interior points in
+ * all is swept one colour at a time instead (Sec. 3: one launch per colour,
+ * an x-parity pair of colours for the 27-point stencil), in place in u, so
+ * that a group too small to give the tile kernels enough work items still
+ * spreads over the device.  0 turns it off, -1 restores the default (7-point:
+ * 1.25 x 2^20 points in FP64, 1.5 x 2^20 in FP32; 27-point: 2^20 in FP64,
+ * 2^22 in FP32).  The iterate is the same either way.  Errors: CS_EINVAL for a bad stencil or dtype, or
+ * max_points < -1. */
+cs_status cs_batch_colour_policy(int32_t stencil, int32_t dtype, int64_t max_points);
 
 /* Resident schedules for batches created or assigned afterwards
  * (process-wide, per stencil and dtype), a bit mask: bit 0 sweeps every patch

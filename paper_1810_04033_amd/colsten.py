@@ -94,6 +94,7 @@ _SIGS = {
     "cs_batch_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "cs_batch_sweeps_per_pass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "cs_batch_tile_policy": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "cs_batch_colour_policy": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]),
     "cs_batch_pass_policy": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "cs_batch_resident_policy": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "cs_graph_gs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
@@ -348,6 +349,10 @@ def cs_batch_pass_policy(stencil, dtype, pair_large):
 def cs_batch_resident_policy(stencil, dtype, enable):
     _check(lib().cs_batch_resident_policy(ctypes.c_int32(stencil), ctypes.c_int32(dtype),
                                           ctypes.c_int32(int(enable))))
+
+
+def cs_batch_colour_policy(stencil, dtype, max_points):
+    _check(lib().cs_batch_colour_policy(int(stencil), int(dtype), int(max_points)))
 
 
 def cs_batch_tile_policy(stencil, dtype, small_max, mid_max):

@@ -14,12 +14,20 @@ namespace {
 
 struct Group {
     int dtype = 0, stencil = 0, variant = 0;
-    int tier = 0;        // LDS-resident tier (1, 2), plane streaming (3), or 0 for the tile kernels
+    int tier = 0;        // LDS-resident tier (1, 2), plane streaming (3), colour passes (4),
+                         // or 0 for the tile kernels
     bool pairs = false;  // two sweeps per launch
     std::vector<BatchPatch> host;
     BatchPatch* dev = nullptr;
     int64_t items = 0, res_items = 0, partial_base = 0;
 };
+
+// [stencil][dtype]: below these totals a tiled group runs faster as colour
+// passes (measured on groups of the largest patches of a request stream: the
+// colour passes win for one such patch, about 1M points, and lose from two
+// on, except FP32 27-point groups, where they win up to about 6M points).
+constexpr int64_t kColourMax[2][2] = {{(int64_t)5 << 18, (int64_t)6 << 18},
+                                      {(int64_t)4 << 18, (int64_t)16 << 18}};
 
 // [stencil][dtype].  By default every tiled patch takes the large tiles: on
 // patches of arbitrary shape (the tiled ones, now that small patches are
@@ -27,6 +35,9 @@ struct Group {
 int g_small_max[2][2] = {{0, 0}, {0, 0}};
 int g_mid_max[2][2] = {{0, 0}, {0, 0}};
 int g_pair_large[2][2] = {{1, 1}, {1, 1}};  // pair the sweeps of the large tile class
+// Tiled groups of fewer interior points than this are swept by colour passes
+// instead (a small group gives the tile kernels too few work items).
+int64_t g_colour_max[2][2] = {{kColourMax[0][0], kColourMax[0][1]}, {kColourMax[1][0], kColourMax[1][1]}};
 int g_resident[2][2] = {{3, 3}, {3, 3}};    // bit 0: whole patches in LDS; bit 1: plane streaming
                                             // for large classes; bit 2: plane streaming always
 
@@ -98,6 +109,7 @@ cs_status plan_batch(const cs_grid_desc* descs, void* const* u, const void* cons
             ++planes_cand[d.stencil][d.dtype];
     }
     const int planes_min = planes_min_patches();
+    std::vector<int> gidx;  // group of each patch, caller's order
     for (int32_t i = 0; i < count; ++i) {
         const cs_grid_desc& d = descs[i];
         cs_status st = validate_desc_pub(&d);
@@ -165,6 +177,7 @@ cs_status plan_batch(const cs_grid_desc* descs, void* const* u, const void* cons
             k = (int)pl->groups.size() - 1;
         }
         pl->groups[k].host.push_back(p);
+        gidx.push_back(k);
         pl->by_index.push_back(p);
         pl->per_pass.push_back(tier == 3 ? batch_planes_sweeps(d.dtype, d.stencil, p.g)
                                : (tier ? 0 : (pairs ? 2 : 1)));
@@ -174,6 +187,18 @@ cs_status plan_batch(const cs_grid_desc* descs, void* const* u, const void* cons
     if (std::adjacent_find(seen.begin(), seen.end()) != seen.end()) {
         set_error("two patches share a norm row");
         return CS_EINVAL;
+    }
+    // small tiled groups go to the colour passes (same iterate, in place)
+    for (size_t j = 0; j < pl->groups.size(); ++j) {
+        Group& gr = pl->groups[j];
+        if (gr.tier) continue;
+        int64_t pts = 0;
+        for (auto& p : gr.host) pts += p.g.nx * p.g.ny * p.g.nz;
+        if (pts >= g_colour_max[gr.stencil][gr.dtype]) continue;
+        gr.tier = 4;
+        gr.pairs = false;
+        for (size_t i = 0; i < gidx.size(); ++i)
+            if (gidx[i] == (int)j) pl->per_pass[i] = 1;
     }
     // z chunks: enough work items to fill the GPU (about 2048) when the batch
     // holds few patches, never chunks thinner than 8 planes (16 for the tile
@@ -197,7 +222,8 @@ cs_status plan_batch(const cs_grid_desc* descs, void* const* u, const void* cons
         int64_t it = 0, rit = 0;
         for (auto& p : gr.host) {
             p.item_begin = it;
-            it += gr.tier ? 1 : (int64_t)p.tiles_x * p.tiles_y * p.chunks;
+            it += gr.tier == 4 ? batch_colour_items(gr.stencil, p.g)
+                               : (gr.tier ? 1 : (int64_t)p.tiles_x * p.tiles_y * p.chunks);
             p.res_begin = rit;
             rit += p.res_items;
         }
@@ -335,6 +361,16 @@ cs_status cs_batch_pass_policy(int32_t stencil, int32_t dtype, int32_t pair_larg
         return CS_EINVAL;
     }
     g_pair_large[stencil][dtype] = pair_large;
+    return CS_OK;
+}
+
+cs_status cs_batch_colour_policy(int32_t stencil, int32_t dtype, int64_t max_points)
+{
+    if ((stencil != CS_FD && stencil != CS_Q1) || (dtype != CS_F64 && dtype != CS_F32) || max_points < -1) {
+        set_error("bad colour policy");
+        return CS_EINVAL;
+    }
+    g_colour_max[stencil][dtype] = max_points >= 0 ? max_points : kColourMax[stencil][dtype];
     return CS_OK;
 }
 
@@ -501,13 +537,17 @@ cs_status cs_batch_gs_sweeps(cs_batch bt, int32_t nsweeps, void* stream)
     if (nsweeps == 0) return CS_OK;
     hipStream_t s = (hipStream_t)stream;
     cs_status st;
-    // LDS-resident and plane-streaming groups: every sweep in one launch, in
-    // place in u
+    // LDS-resident and plane-streaming groups: every sweep in one launch;
+    // colour-pass groups: one launch per colour phase; all in place in u
     for (auto& gr : bt->groups) {
         if (!gr.tier) continue;
-        st = gr.tier == 3 ? launch_batch_planes(gr.dtype, gr.stencil, gr.dev, (int)gr.host.size(), nsweeps, s)
-                          : launch_batch_resident(gr.dtype, gr.stencil, gr.tier, gr.dev, (int)gr.host.size(),
-                                                  nsweeps, s);
+        const int n = (int)gr.host.size();
+        if (gr.tier == 4)
+            st = launch_batch_colour(gr.dtype, gr.stencil, gr.dev, n, gr.items, nsweeps, s);
+        else if (gr.tier == 3)
+            st = launch_batch_planes(gr.dtype, gr.stencil, gr.dev, n, nsweeps, s);
+        else
+            st = launch_batch_resident(gr.dtype, gr.stencil, gr.tier, gr.dev, n, nsweeps, s);
         if (st != CS_OK) return st;
     }
     for (auto& gr : bt->groups)

@@ -74,6 +74,11 @@ bool batch_planes_fits(int dtype, int stencil, const Geo& g);
 int batch_planes_sweeps(int dtype, int stencil, const Geo& g);  // sweeps per pass there
 cs_status launch_batch_planes(int dtype, int stencil, const BatchPatch* tab, int count, int nsweeps,
                               hipStream_t s);
+// Colour-pass tier: work items of a patch, and nsweeps sweeps of a group, one
+// launch per colour phase, in place in u.
+int64_t batch_colour_items(int stencil, const Geo& g);
+cs_status launch_batch_colour(int dtype, int stencil, const BatchPatch* tab, int count, int64_t items,
+                              int nsweeps, hipStream_t s);
 cs_status launch_batch_halo(int dtype, const BatchPatch* tab, int count, hipStream_t s);
 cs_status launch_batch_copyback(int dtype, const BatchPatch* tab, int count, int64_t res_items,
                                 hipStream_t s);

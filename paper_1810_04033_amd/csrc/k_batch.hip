@@ -485,6 +485,51 @@ __global__ void __launch_bounds__(256) k_batch_copyback(const BatchPatch* __rest
     }
 }
 
+// Groups too small to fill the device with tiles: one colour phase of every
+// patch per launch, in place in u (a phase is one colour for red-black, an
+// x-parity pair of colours for 27 points, which never read each other), so a
+// patch spreads over many workgroups whatever its size.  An item covers
+// kColRows rows (j, k) of the phase, 64 threads along x x 4 rows.  The point
+// update is the colour pass's, so the iterate equals it bit for bit.
+constexpr int kColRows = 8;
+
+template <typename T, int ST>
+__global__ void __launch_bounds__(256)
+k_batch_colour(const BatchPatch* __restrict__ tab, int count, int phase)
+{
+    const int64_t w = blockIdx.x;
+    const int p = find_patch(tab, count, w, false);
+    const BatchPatch P = tab[p];
+    const Geo& g = P.g;
+    const int64_t item = w - P.item_begin;
+    T* u = (T*)P.u;
+    const T* b = (const T*)P.b;
+    const T h2 = (T)P.h2;
+    const int par = g.parity;
+    // rows of the phase: every row for red-black, for 27 points the rows whose
+    // y and z parities are the phase's (py = phase & 1, pz = phase >> 1)
+    const int64_t jo = ST == FD ? 0 : ((phase & 1) + par) & 1;
+    const int64_t ko = ST == FD ? 0 : ((phase >> 1) + par) & 1;
+    const int64_t rows_y = ST == FD ? g.ny : (g.ny - jo + 1) / 2;
+    const int64_t rows = rows_y * (ST == FD ? g.nz : (g.nz - ko + 1) / 2);
+    const int64_t sy = g.sy, sz = g.sz;
+    for (int rr = threadIdx.y; rr < kColRows; rr += 4) {
+        const int64_t row = item * kColRows + rr;
+        if (row >= rows) break;
+        const int64_t ty = row % rows_y, tz = row / rows_y;
+        const int64_t j = ST == FD ? 1 + ty : 1 + jo + 2 * ty;
+        const int64_t k = ST == FD ? 1 + tz : 1 + ko + 2 * tz;
+        // red-black: points with (i-1)+(j-1)+(k-1)+parity = phase (mod 2)
+        const int64_t i0 = ST == FD ? 1 + ((phase + (j - 1) + (k - 1) + par) & 1) : 1;
+        const int64_t di = ST == FD ? 2 : 1;
+        for (int64_t i = i0 + di * threadIdx.x; i <= g.nx; i += di * 64) {
+            const int64_t q = k * sz + j * sy + i;
+            auto ld = [&](int ox, int oy, int oz) { return u[q + oz * sz + oy * sy + ox]; };
+            u[q] = gs_value<T, 3, ST>(h2, b[q], ld);
+        }
+    }
+}
+
 template <typename S, int ST>
 __global__ void __launch_bounds__(256)
 k_batch_residual(const BatchPatch* __restrict__ tab, int count, Partial* __restrict__ partials)
@@ -927,6 +972,34 @@ cs_status launch_batch_copyback(int dtype, const BatchPatch* tab, int count, int
         hipLaunchKernelGGL(k_batch_copyback<float>, dim3((unsigned)res_items), dim3(64, 4), 0, s,
                            tab, count);
     return check_launch("batched copy back");
+}
+
+int64_t batch_colour_items(int stencil, const Geo& g)
+{
+    const int64_t rows = stencil == FD ? g.ny * g.nz : ((g.ny + 1) / 2) * ((g.nz + 1) / 2);
+    return (rows + kColRows - 1) / kColRows;
+}
+
+cs_status launch_batch_colour(int dtype, int stencil, const BatchPatch* tab, int count, int64_t items,
+                              int nsweeps, hipStream_t s)
+{
+    if (count <= 0 || items <= 0 || nsweeps <= 0) return CS_OK;
+    if (items > 0x7fffffff) { set_error("colour group too large"); return CS_EUNSUPPORTED; }
+    const dim3 grid((unsigned)items), blk(64, 4);
+    const int nph = stencil == FD ? 2 : 4;
+    for (int it = 0; it < nsweeps; ++it)
+        for (int ph = 0; ph < nph; ++ph) {
+            if (dtype == 0) {
+                if (stencil == FD) hipLaunchKernelGGL((k_batch_colour<double, FD>), grid, blk, 0, s, tab, count, ph);
+                else hipLaunchKernelGGL((k_batch_colour<double, Q1>), grid, blk, 0, s, tab, count, ph);
+            } else {
+                if (stencil == FD) hipLaunchKernelGGL((k_batch_colour<float, FD>), grid, blk, 0, s, tab, count, ph);
+                else hipLaunchKernelGGL((k_batch_colour<float, Q1>), grid, blk, 0, s, tab, count, ph);
+            }
+            cs_status st = check_launch("batched colour pass");
+            if (st != CS_OK) return st;
+        }
+    return CS_OK;
 }
 
 cs_status launch_batch_residual(int dtype, int stencil, const BatchPatch* tab, int count,

@@ -7,7 +7,10 @@ or streamed and the tiles serve the rest: each candidate pair of thresholds
 (small_max, mid_max) of cs_batch_tile_policy is timed on the mix and the
 fastest is set; for the 7-point stencil the large tiles' two sweeps per pass
 are then timed against one sweep per pass on the same mix and the faster is
-set with cs_batch_pass_policy.  Last, the resident schedules are timed on a
+set with cs_batch_pass_policy.  Groups of the 1, 2, 4, 8 and 16 largest
+patches of the mix are timed with the tiles and with the colour passes, and
+the colour-pass threshold of cs_batch_colour_policy is set past the largest
+group on which the colour passes won.  Last, the resident schedules are timed on a
 mix of cubic patches of every edge class (8 to 64) with the resident masks 3
 (whole patches in LDS, plane streaming for large classes), 1 (whole patches
 only) and 0 (tiles only), and the fastest mask is set with
@@ -106,6 +109,7 @@ def tune(stencil, dtype=torch.float64, edges=(8, 16, 24, 32, 48, 64), points_tar
     mix = shape_mix(points_target)
     C.cs_batch_resident_policy(stencil, dt, 3)
     C.cs_batch_pass_policy(stencil, dt, 1)
+    C.cs_batch_colour_policy(stencil, dt, 0)  # the tiles themselves are timed first
     tiles = {}
     for cand in TILE_CANDIDATES:
         C.cs_batch_tile_policy(stencil, dt, *cand)
@@ -120,6 +124,27 @@ def tune(stencil, dtype=torch.float64, edges=(8, 16, 24, 32, 48, 64), points_tar
         _log("shape mix, one sweep per pass: %.1f GLUP/s" % passes[False])
     pair = passes[True] >= passes.get(False, 0.0)
     C.cs_batch_pass_policy(stencil, dt, pair)
+    # colour passes for small groups: groups of the k largest patches of the
+    # mix, tiles against colour passes; the threshold lies past the largest
+    # group on which the colour passes won
+    big = sorted(mix, key=lambda n: -n[0] * n[1] * n[2])
+    small, colour_max = {}, 0
+    for k in (1, 2, 4, 8, 16):
+        grp = big[:k]
+        pts = sum(n[0] * n[1] * n[2] for n in grp)
+        r = []
+        for cm in (0, 1 << 40):
+            C.cs_batch_colour_policy(stencil, dt, cm)
+            r.append(_time_shapes(grp, stencil, dtype, sweeps))
+        small[k] = (pts, r)
+        _log("%d largest patches (%d points): tiles %.1f, colour passes %.1f GLUP/s" % (k, pts, r[0], r[1]))
+    for k in (1, 2, 4, 8, 16):
+        pts, (tile_r, col_r) = small[k]
+        if col_r <= tile_r:
+            break
+        nxt = small.get(2 * k)
+        colour_max = (pts + nxt[0]) // 2 if nxt else pts + 1
+    C.cs_batch_colour_policy(stencil, dt, colour_max)
     cubes = cube_mix(list(edges), 8 * points_target)
     res = {}
     for r in (3, 1, 0):
@@ -129,7 +154,9 @@ def tune(stencil, dtype=torch.float64, edges=(8, 16, 24, 32, 48, 64), points_tar
     resident = max(res, key=lambda r: res[r])
     C.cs_batch_resident_policy(stencil, dt, resident)
     rec = {"small_max": small_max, "mid_max": mid_max, "pair_large": bool(pair),
-           "resident": resident,
+           "colour_max_points": colour_max, "resident": resident,
+           "glups_small_groups": {str(k): {"points": v[0], "tiles": round(v[1][0], 2),
+                                           "colour_passes": round(v[1][1], 2)} for k, v in small.items()},
            "glups_shape_mix_tiles": {"%d,%d" % c: round(v, 2) for c, v in tiles.items()},
            "glups_shape_mix_passes": {("two_sweeps" if p else "one_sweep") + "_per_pass": round(v, 2)
                                       for p, v in passes.items()},
@@ -164,6 +191,7 @@ def apply_cached(stencil, dtype=torch.float64):
     if rec:
         C.cs_batch_tile_policy(stencil, C._DT[dtype], rec["small_max"], rec["mid_max"])
         C.cs_batch_pass_policy(stencil, C._DT[dtype], rec.get("pair_large", True))
+        C.cs_batch_colour_policy(stencil, C._DT[dtype], rec.get("colour_max_points", -1))
         res = rec.get("resident", 3)
         C.cs_batch_resident_policy(stencil, C._DT[dtype], 3 if res is True else int(res))
     return rec

@@ -37,26 +37,40 @@ SHAPES = [(1, 1, 1), (2, 3, 4), (5, 7, 3), (8, 8, 8), (16, 16, 16), (17, 9, 12),
           (33, 20, 18), (48, 48, 48), (64, 64, 64), (70, 13, 65), (40, 66, 9)]
 
 
-def _set_policies(tile, resident):
+def _set_policies(tile=(0, 0), resident=3, colour=-1):
+    """Batch policies of every stencil and dtype (the defaults restore them)."""
     for st in (C.CS_FD, C.CS_Q1):
         for dt in (C.CS_F64, C.CS_F32):
             C.cs_batch_tile_policy(st, dt, *tile)
             C.cs_batch_resident_policy(st, dt, resident)
+            C.cs_batch_colour_policy(st, dt, colour)
 
 
-@pytest.mark.parametrize("policy", ["default", "all_tile_classes"])
+@pytest.fixture
+def tiles_only_for_small_groups():
+    """Small groups keep the tile kernels (colour passes off) during a test."""
+    _set_policies(colour=0)
+    yield
+    _set_policies()
+
+
+@pytest.mark.parametrize("policy", ["default", "all_tile_classes", "colour_passes"])
 @pytest.mark.parametrize("nsw", [1, 2, 3, 4, 5])
 def test_mixed_batch_matches_oracle(nsw, policy):
     """A mixed batch (both stencils, FP64 and FP32, shapes from 1^3 to 70 x 13 x
     65, both parities, odd layouts) equals the oracle: under the default
-    policies, and with every tile class in use (small and middle tiles for
-    the smaller patches, nothing resident)."""
-    if policy != "default":
-        _set_policies((16, 40), 0)
+    policies (this small batch's tiled groups go to the colour passes), with
+    every tile class in use (small and middle tiles for the smaller patches,
+    nothing resident, no colour passes), and with every patch on the colour
+    passes."""
+    if policy == "all_tile_classes":
+        _set_policies((16, 40), 0, 0)
+    elif policy == "colour_passes":
+        _set_policies(resident=0, colour=1 << 40)
     try:
         _mixed_batch_case(nsw)
     finally:
-        _set_policies((0, 0), 3)
+        _set_policies()
 
 
 def _mixed_batch_case(nsw):
@@ -154,7 +168,7 @@ def test_patch_workload_4096_sampled():
                                    rtol=1e-11)
 
 
-def test_sweeps_per_pass_by_tile_class():
+def test_sweeps_per_pass_by_tile_class(tiles_only_for_small_groups):
     """Patches of the large 7-point tile class run two sweeps per pass, the
     other tiled ones (27-point here) one, patches that fit in LDS all sweeps of
     a call in one pass (reported as 0), and patches streamed through one
@@ -178,9 +192,14 @@ def test_sweeps_per_pass_by_tile_class():
         bt.close()
     finally:
         C.cs_batch_resident_policy(C.CS_FD, C.CS_F64, 3)
+    # by default these small tiled groups take the colour passes
+    _set_policies()
+    bt = _batch(ps)
+    assert [bt.sweeps_per_pass(i) for i in range(4)] == [0, 1, 1, 1]
+    bt.close()
 
 
-def test_pass_policy_one_sweep_per_pass_same_iterate():
+def test_pass_policy_one_sweep_per_pass_same_iterate(tiles_only_for_small_groups):
     """With the pass policy off, the large 7-point class runs one sweep per
     pass and gives the same iterate bit for bit; bad policies are rejected."""
     shapes = [(64, 64, 64), (48, 50, 40), (8, 8, 8)]
@@ -242,7 +261,7 @@ def test_resident_patches_equal_tiles_and_oracle(nsw, st):
                 C.cs_batch_resident_policy(st, C._DT[dt], 3)
     for i, (n, dt, tier) in enumerate(RESIDENT):
         assert (res[1][1][i] == 0) == (tier > 0), (n, dt)
-        assert res[0][1][i] in (1, 2)
+        assert res[0][1][i] in (1, 2)  # tiles or, for small groups, colour passes
         assert (res[3][1][i] == 0) == (tier > 0)
         assert np.array_equal(res[1][0][i], res[0][0][i]), (n, dt)
         assert np.array_equal(res[3][0][i], res[0][0][i]), (n, dt)
@@ -304,7 +323,7 @@ PLANES = [(32, 32, 32), (48, 48, 48), (25, 24, 24), (33, 9, 100), (40, 50, 3), (
 
 @pytest.mark.parametrize("nsw", [1, 4, 5, 7])
 @pytest.mark.parametrize("st", [C.CS_FD, C.CS_Q1])
-def test_plane_streamed_patches_equal_tiles_and_oracle(nsw, st):
+def test_plane_streamed_patches_equal_tiles_and_oracle(nsw, st, tiles_only_for_small_groups):
     """Patches whose cross-section fits several planes of LDS run every sweep
     of a call in one launch, streamed through z two or three sweeps per pass,
     in place; with that schedule off they take the tile kernels.  The reported
@@ -338,7 +357,7 @@ def test_plane_streamed_patches_equal_tiles_and_oracle(nsw, st):
     assert streamed >= 8
 
 
-def test_streaming_needs_a_patch_per_compute_unit():
+def test_streaming_needs_a_patch_per_compute_unit(tiles_only_for_small_groups):
     """Under the default mask the streamable patches of a stencil and dtype
     are streamed only when the batch holds one per compute unit: a batch of
     that many streams every one of them, a batch of one fewer sweeps them all
@@ -362,3 +381,30 @@ def test_streaming_needs_a_patch_per_compute_unit():
         assert np.array_equal(got_all[k], G.download(qs[i]["ug"])), i
     bt_less.close()
     assert G.relmax(got_all[1], _oracle(_patch(n, C.CS_FD, torch.float64, 1, seed=2601), 5)) <= 1e-13
+
+
+@pytest.mark.parametrize("nsw", [1, 4, 5])
+def test_colour_passes_equal_tiles_bitwise(nsw):
+    """The same patches swept by the colour passes (every group) and by the
+    tile kernels (none) end bit for bit equal: both stencils, FP64 and FP32,
+    both parities, ragged and odd layouts, single and paired tile classes."""
+    shapes = [(1, 1, 1), (5, 7, 3), (17, 9, 12), (33, 20, 18), (70, 13, 65), (64, 64, 40),
+              (40, 66, 9), (123, 31, 17)]
+    res = {}
+    for colour in (1 << 40, 0):
+        _set_policies(resident=0, colour=colour)
+        try:
+            ps = [_patch(n, st, dt, (i + st) % 2, seed=2700 + 3 * i + st, layout="odd" if i % 3 == 2 else "aligned")
+                  for i, n in enumerate(shapes) for st in (C.CS_FD, C.CS_Q1)
+                  for dt in (torch.float64, torch.float32)]
+            bt = _batch(ps)
+            per = {bt.sweeps_per_pass(i) for i in range(len(ps))}
+            assert per == ({1} if colour else {1, 2})
+            bt.gs(nsw)
+            torch.cuda.synchronize()
+            res[colour] = [G.download(p["ug"]) for p in ps]
+            bt.close()
+        finally:
+            _set_policies()
+    for a, b in zip(res[1 << 40], res[0]):
+        assert np.array_equal(a, b)

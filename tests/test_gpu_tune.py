@@ -21,6 +21,7 @@ def test_tune_applies_and_caches_a_policy(tmp_path, monkeypatch):
             assert set(rec["glups_shape_mix_tiles"]) == {"%d,%d" % c for c in T.TILE_CANDIDATES}
             assert all(v > 0 for v in rec["glups_shape_mix_tiles"].values())
             assert (len(rec["glups_shape_mix_passes"]) == 2) == (st == C.CS_FD)
+            assert rec["colour_max_points"] >= 0 and len(rec["glups_small_groups"]) == 5
             data = json.load(open(tmp_path / "tune.json"))
             assert data[T._key(st, torch.float64)] == json.loads(json.dumps(rec))
             assert T.apply_cached(st, torch.float64) == data[T._key(st, torch.float64)]
@@ -31,3 +32,4 @@ def test_tune_applies_and_caches_a_policy(tmp_path, monkeypatch):
                 C.cs_batch_tile_policy(st, dt, 0, 0)
                 C.cs_batch_pass_policy(st, dt, 1)
                 C.cs_batch_resident_policy(st, dt, 3)
+                C.cs_batch_colour_policy(st, dt, -1)
