@@ -19,7 +19,7 @@ struct Group {
     bool pairs = false;  // two sweeps per launch
     std::vector<BatchPatch> host;
     BatchPatch* dev = nullptr;
-    int64_t items = 0, res_items = 0, partial_base = 0;
+    int64_t items = 0, res_items = 0, halo_items = 0, partial_base = 0;
 };
 
 // [stencil][dtype]: below these totals a tiled group runs faster as colour
@@ -219,17 +219,23 @@ cs_status plan_batch(const cs_grid_desc* descs, void* const* u, const void* cons
         std::stable_sort(gr.host.begin(), gr.host.end(), [](const BatchPatch& a, const BatchPatch& c) {
             return a.g.nx * a.g.ny * a.g.nz > c.g.nx * c.g.ny * c.g.nz;
         });
-        int64_t it = 0, rit = 0;
+        int64_t it = 0, rit = 0, hit = 0;
         for (auto& p : gr.host) {
+            p.halo_begin = hit;
+            hit += p.g.nz + 2;
             p.item_begin = it;
             it += gr.tier == 4 ? batch_colour_items(gr.stencil, p.g)
                                : (gr.tier ? 1 : (int64_t)p.tiles_x * p.tiles_y * p.chunks);
             p.res_begin = rit;
             rit += p.res_items;
         }
-        if (it > 0x7fffffff || rit > 0x7fffffff) { set_error("batch too large"); return CS_EUNSUPPORTED; }
+        if (it > 0x7fffffff || rit > 0x7fffffff || hit > 0x7fffffff) {
+            set_error("batch too large");
+            return CS_EUNSUPPORTED;
+        }
         gr.items = it;
         gr.res_items = rit;
+        gr.halo_items = hit;
         gr.partial_base = partial_total;
         partial_total += rit;
     }
@@ -551,7 +557,7 @@ cs_status cs_batch_gs_sweeps(cs_batch bt, int32_t nsweeps, void* stream)
         if (st != CS_OK) return st;
     }
     for (auto& gr : bt->groups)
-        if (!gr.tier && (st = launch_batch_halo(gr.dtype, gr.dev, (int)gr.host.size(), s)) != CS_OK)
+        if (!gr.tier && (st = launch_batch_halo(gr.dtype, gr.dev, (int)gr.host.size(), gr.halo_items, s)) != CS_OK)
             return st;
     // Each launch reads u (phase 0) or tmp (phase 1) and writes the other; a
     // group whose sweeps run two per launch flips less often, so the copy back

@@ -25,6 +25,7 @@ struct BatchPatch {
     int64_t item_begin;  // first work item of this patch in the sweep launch
     int64_t res_begin;   // first row-block item in the residual / copy launches
     int res_items;
+    int64_t halo_begin;  // first plane item in the halo copy (nz + 2 items)
 };
 
 // One patch of the refinement pairing of an FP32 batch: the FP64 iterate x
@@ -79,7 +80,7 @@ cs_status launch_batch_planes(int dtype, int stencil, const BatchPatch* tab, int
 int64_t batch_colour_items(int stencil, const Geo& g);
 cs_status launch_batch_colour(int dtype, int stencil, const BatchPatch* tab, int count, int64_t items,
                               int nsweeps, hipStream_t s);
-cs_status launch_batch_halo(int dtype, const BatchPatch* tab, int count, hipStream_t s);
+cs_status launch_batch_halo(int dtype, const BatchPatch* tab, int count, int64_t halo_items, hipStream_t s);
 cs_status launch_batch_copyback(int dtype, const BatchPatch* tab, int count, int64_t res_items,
                                 hipStream_t s);
 cs_status launch_batch_residual(int dtype, int stencil, const BatchPatch* tab, int count,

@@ -22,13 +22,16 @@ namespace cs {
 
 namespace {
 
-__device__ inline int find_patch(const BatchPatch* __restrict__ tab, int count, int64_t w,
-                                 bool residual)
+// which prefix a launch's items follow
+enum { kItemsSweep = 0, kItemsRows = 1, kItemsHalo = 2 };
+
+__device__ inline int find_patch(const BatchPatch* __restrict__ tab, int count, int64_t w, int kind)
 {
     int lo = 0, hi = count - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        const int64_t beg = residual ? tab[mid].res_begin : tab[mid].item_begin;
+        const int64_t beg = kind == kItemsRows ? tab[mid].res_begin
+                                               : (kind == kItemsHalo ? tab[mid].halo_begin : tab[mid].item_begin);
         if (beg <= w)
             lo = mid;
         else
@@ -42,7 +45,7 @@ __global__ void __launch_bounds__(NT)
 k_batch_fd3(const BatchPatch* __restrict__ tab, int count, int phase)
 {
     const int64_t w = blockIdx.x;
-    const int p = find_patch(tab, count, w, false);
+    const int p = find_patch(tab, count, w, kItemsSweep);
     const BatchPatch P = tab[p];
     const TileBox tb = tile_box<TX, TY>(P.g, P.tiles_x, P.tiles_y, P.chunks, w - P.item_begin);
     const T* src = (const T*)(phase ? P.tmp : P.u);
@@ -56,7 +59,7 @@ __global__ void __launch_bounds__(NT)
 k_batch_fd3_two(const BatchPatch* __restrict__ tab, int count, int phase)
 {
     const int64_t w = blockIdx.x;
-    const int p = find_patch(tab, count, w, false);
+    const int p = find_patch(tab, count, w, kItemsSweep);
     const BatchPatch P = tab[p];
     const TileBox tb = tile_box<TX, TY>(P.g, P.tiles_x, P.tiles_y, P.chunks, w - P.item_begin);
     const T* src = (const T*)(phase ? P.tmp : P.u);
@@ -69,7 +72,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_batch_q1_3(const BatchPatch* __restrict__ tab, int count, int phase)
 {
     const int64_t w = blockIdx.x;
-    const int p = find_patch(tab, count, w, false);
+    const int p = find_patch(tab, count, w, kItemsSweep);
     const BatchPatch P = tab[p];
     const TileBox tb = tile_box<TX, TY>(P.g, P.tiles_x, P.tiles_y, P.chunks, w - P.item_begin);
     const T* src = (const T*)(phase ? P.tmp : P.u);
@@ -423,39 +426,40 @@ k_batch_planes(const BatchPatch* __restrict__ tab, int nsweeps)
     }
 }
 
-// Halo copy u -> tmp, one workgroup per patch.
+// Halo copy u -> tmp, one workgroup per plane k of a patch (nz + 2 items):
+// the whole plane for k = 0 and k = nz + 1, else its two halo rows and two
+// halo columns.
 template <typename T>
-__global__ void __launch_bounds__(256) k_batch_halo(const BatchPatch* __restrict__ tab)
+__global__ void __launch_bounds__(256) k_batch_halo(const BatchPatch* __restrict__ tab, int count)
 {
-    const BatchPatch P = tab[blockIdx.x];
+    const int64_t w = blockIdx.x;
+    const int p = find_patch(tab, count, w, kItemsHalo);
+    const BatchPatch P = tab[p];
     const Geo& g = P.g;
-    const T* src = (const T*)P.u;
-    T* dst = (T*)P.tmp;
-    const int64_t wx = g.nx + 2, plane = wx * (g.ny + 2);
-    const int64_t per = 2 * wx + 2 * g.ny;
-    const int64_t total = 2 * plane + g.nz * per;
-    for (int64_t t = threadIdx.x; t < total; t += 256) {
-        int64_t i, j, k, r = t;
-        if (r < 2 * plane) {
-            k = r < plane ? 0 : g.nz + 1;
-            r %= plane;
-            j = r / wx;
-            i = r % wx;
-        } else {
-            r -= 2 * plane;
-            k = 1 + r / per;
-            r %= per;
-            if (r < 2 * wx) {
-                j = r < wx ? 0 : g.ny + 1;
-                i = r % wx;
-            } else {
-                r -= 2 * wx;
-                j = 1 + r / 2;
-                i = (r & 1) ? g.nx + 1 : 0;
-            }
+    const int k = (int)(w - P.halo_begin);
+    const T* src = (const T*)P.u + (int64_t)k * g.sz;
+    T* dst = (T*)P.tmp + (int64_t)k * g.sz;
+    const int nx = (int)g.nx, ny = (int)g.ny, wx = nx + 2, sy = (int)g.sy;
+    if (k == 0 || k == g.nz + 1) {
+        const int total = wx * (ny + 2);
+        for (int t = threadIdx.x; t < total; t += 256) {
+            const int j = t / wx, i = t - j * wx;
+            dst[j * sy + i] = src[j * sy + i];
         }
-        const int64_t q = k * g.sz + j * g.sy + i;
-        dst[q] = src[q];
+        return;
+    }
+    const int total = 2 * wx + 2 * ny;
+    for (int t = threadIdx.x; t < total; t += 256) {
+        int i, j;
+        if (t < 2 * wx) {
+            j = t < wx ? 0 : ny + 1;
+            i = t < wx ? t : t - wx;
+        } else {
+            const int r = t - 2 * wx;
+            j = 1 + (r >> 1);
+            i = (r & 1) ? nx + 1 : 0;
+        }
+        dst[j * sy + i] = src[j * sy + i];
     }
 }
 
@@ -467,7 +471,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_batch_copyback(const BatchPatch* __restrict__ tab, int count)
 {
     const int64_t w = blockIdx.x;
-    const int p = find_patch(tab, count, w, true);
+    const int p = find_patch(tab, count, w, kItemsRows);
     const BatchPatch P = tab[p];
     const Geo& g = P.g;
     const int64_t item = w - P.res_begin;
@@ -485,6 +489,40 @@ __global__ void __launch_bounds__(256) k_batch_copyback(const BatchPatch* __rest
     }
 }
 
+// One patch's norms from its n row-block partials, by a 64-thread
+// workgroup: lane l folds partials l, l + 64, l + 128, ... in order, then
+// the 64 lane values are added by a fixed binary tree.  The order depends
+// only on n, so a patch's norms do not depend on the rest of the batch.
+__device__ inline void fold_partials(const Partial* __restrict__ ps, int n, double* __restrict__ out)
+{
+    __shared__ double sh[3][64];
+    const int l = threadIdx.x;
+    double a = 0.0, m = 0.0, c = 0.0;
+    for (int i = l; i < n; i += 64) {
+        const Partial q = ps[i];
+        a += q.sum_r2;
+        m = fmax(m, q.max_r);
+        c += q.sum_b2;
+    }
+    sh[0][l] = a;
+    sh[1][l] = m;
+    sh[2][l] = c;
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+        if (l < w) {
+            sh[0][l] = sh[0][l] + sh[0][l + w];
+            sh[1][l] = fmax(sh[1][l], sh[1][l + w]);
+            sh[2][l] = sh[2][l] + sh[2][l + w];
+        }
+        __syncthreads();
+    }
+    if (l == 0) {
+        out[0] = sqrt(sh[0][0]);
+        out[1] = sh[1][0];
+        out[2] = sqrt(sh[2][0]);
+    }
+}
+
 // Groups too small to fill the device with tiles: one colour phase of every
 // patch per launch, in place in u (a phase is one colour for red-black, an
 // x-parity pair of colours for 27 points, which never read each other), so a
@@ -498,7 +536,7 @@ __global__ void __launch_bounds__(256)
 k_batch_colour(const BatchPatch* __restrict__ tab, int count, int phase)
 {
     const int64_t w = blockIdx.x;
-    const int p = find_patch(tab, count, w, false);
+    const int p = find_patch(tab, count, w, kItemsSweep);
     const BatchPatch P = tab[p];
     const Geo& g = P.g;
     const int64_t item = w - P.item_begin;
@@ -536,7 +574,7 @@ k_batch_residual(const BatchPatch* __restrict__ tab, int count, Partial* __restr
 {
     __shared__ double sh[3 * 256];
     const int64_t w = blockIdx.x;
-    const int p = find_patch(tab, count, w, true);
+    const int p = find_patch(tab, count, w, kItemsRows);
     const BatchPatch P = tab[p];
     const Geo& g = P.g;
     const int64_t item = w - P.res_begin;
@@ -586,17 +624,7 @@ k_batch_finish(const BatchPatch* __restrict__ tab, const Partial* __restrict__ p
                double* __restrict__ norms)
 {
     const BatchPatch P = tab[blockIdx.x];
-    if (threadIdx.x != 0) return;
-    double a = 0.0, m = 0.0, c = 0.0;
-    for (int i = 0; i < P.res_items; ++i) {
-        const Partial q = partials[P.res_begin + i];
-        a += q.sum_r2;
-        m = fmax(m, q.max_r);
-        c += q.sum_b2;
-    }
-    norms[3 * P.index + 0] = sqrt(a);
-    norms[3 * P.index + 1] = m;
-    norms[3 * P.index + 2] = sqrt(c);
+    fold_partials(partials + P.res_begin, P.res_items, norms + 3 * P.index);
 }
 
 // ---- batched refinement steps ---------------------------------------------
@@ -700,17 +728,7 @@ k_batch_ir_finish(const IrPatch* __restrict__ tab, const Partial* __restrict__ p
                   double* __restrict__ norms)
 {
     const IrPatch P = tab[blockIdx.x];
-    if (threadIdx.x != 0) return;
-    double a = 0.0, m = 0.0, c = 0.0;
-    for (int i = 0; i < P.res_items; ++i) {
-        const Partial q = partials[P.res_begin + i];
-        a += q.sum_r2;
-        m = fmax(m, q.max_r);
-        c += q.sum_b2;
-    }
-    norms[3 * P.row + 0] = sqrt(a);
-    norms[3 * P.row + 1] = m;
-    norms[3 * P.row + 2] = sqrt(c);
+    fold_partials(partials + P.res_begin, P.res_items, norms + 3 * P.row);
 }
 
 __global__ void __launch_bounds__(256)
@@ -951,13 +969,15 @@ cs_status launch_batch_planes(int dtype, int stencil, const BatchPatch* tab, int
     return check_launch("batched plane-streaming sweeps");
 }
 
-cs_status launch_batch_halo(int dtype, const BatchPatch* tab, int count, hipStream_t s)
+cs_status launch_batch_halo(int dtype, const BatchPatch* tab, int count, int64_t halo_items, hipStream_t s)
 {
-    if (count <= 0) return CS_OK;
+    if (count <= 0 || halo_items <= 0) return CS_OK;
+    if (halo_items > 0x7fffffff) { set_error("batch too large"); return CS_EUNSUPPORTED; }
+    const dim3 grid((unsigned)halo_items);
     if (dtype == 0)
-        hipLaunchKernelGGL(k_batch_halo<double>, dim3(count), dim3(256), 0, s, tab);
+        hipLaunchKernelGGL(k_batch_halo<double>, grid, dim3(256), 0, s, tab, count);
     else
-        hipLaunchKernelGGL(k_batch_halo<float>, dim3(count), dim3(256), 0, s, tab);
+        hipLaunchKernelGGL(k_batch_halo<float>, grid, dim3(256), 0, s, tab, count);
     return check_launch("batched halo copy");
 }
 
