@@ -420,11 +420,12 @@ def patches_measure(steps, warmup, tune, baselines=("per_colour", "fused_per_pat
             g.close()
 
     value = pts * sweeps / (ms * 1e-3) / 1e9
-    # bytes moved per sweep: 24 per point of a patch swept one sweep per pass,
-    # 12 per point of a patch whose sweeps run two per pass, 24 / sweeps per
-    # point of a patch swept resident in LDS (all sweeps in one pass)
-    per_pass = [k if k else sweeps for k in per_pass]
-    bytes_per_sweep = sum(24 * e ** 3 / k for e, k in zip(edges, per_pass))
+    # bytes moved per sweep: 24 per point and pass over memory, over the
+    # sweeps: a patch swept k sweeps per pass makes ceil(sweeps / k) passes
+    # (one sweep per pass: 24 B per update; two: 12; streamed three per pass:
+    # 24 x 7 / 20), a patch resident in LDS one pass for all sweeps
+    passes = [-(-sweeps // k) if k else 1 for k in per_pass]
+    bytes_per_sweep = sum(24 * e ** 3 * n / sweeps for e, n in zip(edges, passes))
     paired_pts = sum(e ** 3 for e, k in zip(edges, per_pass) if k == 2)
     achieved = bytes_per_sweep / (ms * 1e-3 / sweeps) / 1e9
     out = {
@@ -445,10 +446,11 @@ def patches_measure(steps, warmup, tune, baselines=("per_colour", "fused_per_pat
                      "traffic": None, "bytes_per_sweep": int(bytes_per_sweep),
                      "mean_sweep_us": round(ms * 1e3 / sweeps, 3),
                      "points_swept_two_per_pass": paired_pts,
-                     "note": "bytes moved per sweep over the time per sweep; patches of the large "
-                             "tile class run two sweeps per pass (12 B per update), patches resident "
-                             "in LDS move 24 B per point once for all sweeps, the others one sweep "
-                             "per pass (24 B)"},
+                     "streamed_points": sum(e ** 3 for e, k in zip(edges, per_pass) if k >= 3),
+                     "note": "bytes moved per sweep over the time per sweep: 24 B per point and "
+                             "pass over memory; patches of the large tile class run two sweeps per "
+                             "pass, streamed patches three (the last pass two), patches resident "
+                             "in LDS all sweeps in one pass, the others one sweep per pass"},
         "max_final_rel_residual": float(np.max(norms[:, 0] / norms[:, 2])),
     }
     if cpu:
