@@ -108,10 +108,11 @@ cs_status cs_colour_pass(cs_grid g, int32_t colour, void* stream);
  * four on 2D grids (see cs_grid_set_pass_mode).  The halo of u_tmp is
  * overwritten with u's halo, and the result ends in u.  Without u_tmp, each
  * sweep is c in-place colour passes.  In the automatic pass mode small 3D
- * grids take faster schedules of the same iterate whatever u_tmp is: up to
- * 4096 points every sweep runs in one workgroup with a workgroup barrier
- * after each colour (one launch in all), and 7-point grids of up to 1.1 M
- * points run the in-place colour passes (u_tmp unused in both cases).
+ * grids take faster schedules of the same iterate whatever u_tmp is: by
+ * default up to 4096 points every sweep runs in one workgroup with a
+ * workgroup barrier after each colour (one launch in all), and 7-point grids
+ * of up to 1.1 M points run the in-place colour passes (u_tmp unused in both
+ * cases); cs_grid_schedule_policy moves these limits.
  * nsweeps == 0 is a no-op.
  * Errors: CS_EINVAL (nsweeps < 0). */
 cs_status cs_gs_sweeps(cs_grid g, int32_t nsweeps, void* u_tmp, void* stream);
@@ -486,6 +487,19 @@ typedef enum { CS_PASS_AUTO = 0, CS_PASS_ONE = 1, CS_PASS_TWO = 2 } cs_pass_mode
 /* Set the grid's pass mode (a cs_pass_mode).  Errors: CS_EINVAL (bad grid or
  * mode). */
 cs_status cs_grid_set_pass_mode(cs_grid g, int32_t mode);
+
+/* Automatic schedule of cs_gs_sweeps on 3D grids in CS_PASS_AUTO
+ * (process-wide, per stencil and dtype; the colour order of Sec. 3 in every
+ * schedule, so the iterate is the same in all of them): grids of at most
+ * block_max interior points run every sweep in one workgroup, grids of at
+ * most colour_max points one launch per colour (in place, u_tmp unused),
+ * larger ones fused passes with u_tmp, two sweeps per pass from two_min
+ * points on where the double sweep is built.  A negative value restores that
+ * field's default: block_max 4096; colour_max 1.1 M points (7-point) or 0
+ * (27-point); two_min: 7-point where the grid fills the device, 27-point
+ * never.  Set by the autotuner.  Errors: CS_EINVAL (bad stencil or dtype). */
+cs_status cs_grid_schedule_policy(int32_t stencil, int32_t dtype, int64_t block_max, int64_t colour_max,
+                                  int64_t two_min);
 
 /* *out = sweeps per pass (1, 2, 4 or 8; more than 2 only on 2D grids) that cs_gs_sweeps with a work array
  * (jacobi == 0) or cs_jacobi_sweeps (jacobi == 1) uses on this grid under its

@@ -95,6 +95,8 @@ _SIGS = {
     "cs_batch_sweeps_per_pass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "cs_batch_tile_policy": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "cs_batch_colour_policy": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]),
+    "cs_grid_schedule_policy": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                               ctypes.c_int64]),
     "cs_batch_pass_policy": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "cs_batch_resident_policy": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "cs_graph_gs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
@@ -349,6 +351,11 @@ def cs_batch_pass_policy(stencil, dtype, pair_large):
 def cs_batch_resident_policy(stencil, dtype, enable):
     _check(lib().cs_batch_resident_policy(ctypes.c_int32(stencil), ctypes.c_int32(dtype),
                                           ctypes.c_int32(int(enable))))
+
+
+def cs_grid_schedule_policy(stencil, dtype, block_max, colour_max, two_min):
+    _check(lib().cs_grid_schedule_policy(int(stencil), int(dtype), int(block_max), int(colour_max),
+                                         int(two_min)))
 
 
 def cs_batch_colour_policy(stencil, dtype, max_points):

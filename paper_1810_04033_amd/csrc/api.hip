@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <cmath>
+#include <cstdint>
 #include <new>
 
 #include "cs_internal.h"
@@ -237,15 +238,39 @@ cs_status cs_num_colours(cs_grid g, int32_t* out)
 // level with the colour launches (7-point) or ahead (27-point).  Up to 16^3
 // points every sweep runs in one workgroup; 7-point grids up to ~100^3 run one
 // launch per colour, in place.
+// Automatic schedule of the 3D sweeps, per [stencil][dtype] (process-wide,
+// set by cs_grid_schedule_policy and the autotuner): all sweeps in one
+// workgroup up to block_max points, one launch per colour up to colour_max
+// points, else fused passes, two sweeps per pass from two_min points on where
+// the double sweep is built (two_min < 0: where the grid fills the device).
+// The defaults are measured at 7^3 .. 256^3 (FP64): the one-workgroup
+// schedule wins up to about 16^3, the 7-point colour launches up to about
+// 100^3, the 27-point double sweep nowhere.
+struct SchedPolicy {
+    int64_t block_max, colour_max, two_min;
+};
+constexpr int64_t kNever = INT64_MAX;
+constexpr SchedPolicy kSchedDefault[2] = {{4096, 1100000, -1}, {4096, 0, kNever}};
+SchedPolicy g_sched[2][2] = {{kSchedDefault[0], kSchedDefault[0]}, {kSchedDefault[1], kSchedDefault[1]}};
+
+static int64_t points_of(cs_grid g)
+{
+    return g->geo.nx * g->geo.ny * g->geo.nz;
+}
+
+static const SchedPolicy& sched_of(cs_grid g)
+{
+    return g_sched[g->d.stencil][g->d.dtype];
+}
+
 static bool block_sweeps_pay(cs_grid g)
 {
-    return g->d.dim == 3 && g->geo.nx * g->geo.ny * g->geo.nz <= 4096;
+    return g->d.dim == 3 && points_of(g) <= sched_of(g).block_max;
 }
 
 static bool colour_launches_pay(cs_grid g)
 {
-    return g->d.dim == 3 && g->d.stencil == CS_FD &&
-           g->geo.nx * g->geo.ny * g->geo.nz <= 1100000;
+    return g->d.dim == 3 && points_of(g) <= sched_of(g).colour_max;
 }
 
 static int gs_per_pass(cs_grid g)
@@ -254,7 +279,9 @@ static int gs_per_pass(cs_grid g)
     if (g->pass_mode == CS_PASS_ONE || !fused_supported(dt, dim, sten, g->geo)) return 1;
     if (dim == 2) return fused2d_max_sweeps(sten);
     if (g->pass_mode == CS_PASS_TWO) return fused_two_available(dt, dim, sten, g->geo) ? 2 : 1;
-    return fused_two_preferred(dt, dim, sten, g->geo) ? 2 : 1;
+    const int64_t two_min = sched_of(g).two_min;
+    if (two_min < 0) return fused_two_preferred(dt, dim, sten, g->geo) ? 2 : 1;
+    return fused_two_available(dt, dim, sten, g->geo) && points_of(g) >= two_min ? 2 : 1;
 }
 
 static int jacobi_per_pass(cs_grid g)
@@ -262,6 +289,21 @@ static int jacobi_per_pass(cs_grid g)
     if (g->pass_mode == CS_PASS_ONE) return 1;
     if (g->d.dim == 2) return jacobi2d_max_sweeps(g->geo);
     return jacobi3_two_supported(g->d.stencil, g->geo) ? 2 : 1;
+}
+
+cs_status cs_grid_schedule_policy(int32_t stencil, int32_t dtype, int64_t block_max, int64_t colour_max,
+                                  int64_t two_min)
+{
+    if ((stencil != CS_FD && stencil != CS_Q1) || (dtype != CS_F64 && dtype != CS_F32)) {
+        set_error("bad stencil or dtype");
+        return CS_EINVAL;
+    }
+    const SchedPolicy& d = kSchedDefault[stencil];
+    SchedPolicy& p = g_sched[stencil][dtype];
+    p.block_max = block_max >= 0 ? block_max : d.block_max;
+    p.colour_max = colour_max >= 0 ? colour_max : d.colour_max;
+    p.two_min = two_min >= 0 ? two_min : d.two_min;
+    return CS_OK;
 }
 
 cs_status cs_grid_set_pass_mode(cs_grid g, int32_t mode)

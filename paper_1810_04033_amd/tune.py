@@ -1,4 +1,5 @@
-"""Autotuner for the batched-patch tile shapes and colour schedules.
+"""Autotuner for the batched-patch tile shapes and colour schedules, and for
+the automatic schedule of single grids.
 
 The tile policy and the colour schedule are timed on a mix of patches of
 arbitrary shape (axis lengths log-uniform in [16, 128], aspect at most 4, as a
@@ -18,6 +19,11 @@ cs_batch_resident_policy.  Every schedule gives the same iterate.  Results are
 cached as JSON keyed by GPU architecture, stencil and dtype
 (COLSTEN_TUNE_CACHE, default ~/.cache/colsten_tune.json), so later processes
 apply them without re-timing.
+
+Single grids (tune_grid): cubic grids from 8^3 to 256^3 are swept under each
+schedule of the automatic mode -- every sweep in one workgroup, one launch per
+colour, fused passes of one or of two sweeps -- and the size limits of
+cs_grid_schedule_policy are set where the fastest schedule changes.
 """
 import json
 import os
@@ -163,31 +169,147 @@ def tune(stencil, dtype=torch.float64, edges=(8, 16, 24, 32, 48, 64), points_tar
            "glups_cube_mix_resident": {"mask_%d" % r: round(v, 2) for r, v in res.items()},
            "shape_mix_patches": len(mix), "tiles": VARIANT_TILES[stencil]}
     if save:
-        path = cache_path()
-        data = {}
-        if os.path.exists(path):
-            try:
-                data = json.load(open(path))
-            except ValueError:
-                data = {}
-        data[_key(stencil, dtype)] = rec
-        os.makedirs(os.path.dirname(path), exist_ok=True)
-        tmp = path + ".tmp%d" % os.getpid()
-        with open(tmp, "w") as f:
-            json.dump(data, f, indent=1)
-        os.replace(tmp, path)
+        _save(_key(stencil, dtype), rec)
     return rec
 
 
-def apply_cached(stencil, dtype=torch.float64):
-    """Apply a cached policy if there is one; returns it (or None)."""
+# ---- single grids ------------------------------------------------------------
+
+GRID_EDGES = (8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256)
+NEVER = 1 << 62
+
+
+def _grid_key(stencil, dtype):
+    return "grid/" + _key(stencil, dtype)
+
+
+def _time_grid(n, stencil, dtype, sweeps, schedule, reps=3):
+    """Seconds for `sweeps` sweeps of a cubic n^3 grid under one schedule of
+    the automatic mode: 'block' (one workgroup), 'colour' (one launch per
+    colour), 'one' / 'two' (fused passes, one or two sweeps per pass)."""
+    dt = C._DT[dtype]
+    big = NEVER
+    pol = {"block": (big, 0, big), "colour": (0, big, big), "one": (0, 0, big), "two": (0, 0, 0)}[schedule]
+    C.cs_grid_schedule_policy(stencil, dt, *pol)
+    u = C.empty_grid((n, n, n), dtype=dtype)
+    b = C.empty_grid((n, n, n), dtype=dtype)
+    b.fill_(1.0)
+    tmp = C.grid_like(u)
+    g = C.Grid(u, b, dim=3, stencil=stencil, h=1.0 / (n + 1))
+    try:
+        if schedule == "two" and g.sweeps_per_pass() != 2:
+            return None
+        g.gs(2, tmp=tmp)
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            g.gs(sweeps, tmp=tmp)
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) * 1e-3
+            best = t if best is None else min(best, t)
+        return best
+    finally:
+        g.close()
+
+
+def tune_grid(stencil, dtype=torch.float64, edges=GRID_EDGES, sweeps=20, block_edge_max=48, save=True):
+    """Time the automatic mode's schedules of cs_gs_sweeps on cubic grids of
+    the given edges, derive the size limits of cs_grid_schedule_policy from
+    the fastest schedule per edge, apply them and cache them."""
+    dt = C._DT[dtype]
+    table = {}
+    try:
+        for n in edges:
+            row = {}
+            for sch in ("block", "colour", "one", "two"):
+                if sch == "block" and n > block_edge_max:
+                    continue
+                t = _time_grid(n, stencil, dtype, sweeps, sch)
+                if t is not None:
+                    row[sch] = n ** 3 * sweeps / t / 1e9
+            table[n] = row
+            _log("grid %d^3: %s GLUP/s" % (n, {k: round(v, 1) for k, v in row.items()}))
+    finally:
+        C.cs_grid_schedule_policy(stencil, dt, -1, -1, -1)
+
+    def cut(lo_edge, hi_edge):
+        # a limit between two measured sizes (geometric mean of the point counts)
+        return int((lo_edge ** 3 * hi_edge ** 3) ** 0.5)
+
+    def limit_below(wins):
+        # the largest edge that wins, and every smaller one too; the limit lies
+        # between it and the next edge
+        last = None
+        for i, n in enumerate(edges):
+            if not wins(n):
+                break
+            last = i
+        if last is None:
+            return 0
+        return cut(edges[last], edges[last + 1]) if last + 1 < len(edges) else NEVER
+
+    fused = lambda n: max(v for k, v in table[n].items() if k in ("one", "two"))  # noqa: E731
+    block_max = limit_below(lambda n: "block" in table[n] and
+                            table[n]["block"] >= max(v for k, v in table[n].items()))
+    colour_max = limit_below(lambda n: table[n]["colour"] >= fused(n))
+    two_min = NEVER
+    for i in range(len(edges) - 1, -1, -1):
+        n = edges[i]
+        if table[n].get("two", 0.0) > table[n]["one"]:
+            two_min = cut(edges[i - 1], n) if i > 0 else 0
+        else:
+            break
+    C.cs_grid_schedule_policy(stencil, dt, block_max, colour_max, two_min)
+    rec = {"block_max": block_max, "colour_max": colour_max, "two_min": two_min,
+           "glups": {str(n): {k: round(v, 2) for k, v in row.items()} for n, row in table.items()},
+           "sweeps": sweeps}
+    if save:
+        _save(_grid_key(stencil, dtype), rec)
+    return rec
+
+
+def apply_cached_grid(stencil, dtype=torch.float64):
+    """Apply a cached single-grid schedule policy if there is one; returns it
+    (or None)."""
+    rec = _load(_grid_key(stencil, dtype))
+    if rec:
+        C.cs_grid_schedule_policy(stencil, C._DT[dtype], rec["block_max"], rec["colour_max"], rec["two_min"])
+    return rec
+
+
+def _save(key, rec):
+    path = cache_path()
+    data = {}
+    if os.path.exists(path):
+        try:
+            data = json.load(open(path))
+        except ValueError:
+            data = {}
+    data[key] = rec
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1)
+    os.replace(tmp, path)
+
+
+def _load(key):
     path = cache_path()
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path)).get(_key(stencil, dtype))
+        return json.load(open(path)).get(key)
     except ValueError:
         return None
+
+
+def apply_cached(stencil, dtype=torch.float64):
+    """Apply a cached batch policy if there is one; returns it (or None)."""
+    rec = _load(_key(stencil, dtype))
     if rec:
         C.cs_batch_tile_policy(stencil, C._DT[dtype], rec["small_max"], rec["mid_max"])
         C.cs_batch_pass_policy(stencil, C._DT[dtype], rec.get("pair_large", True))
