@@ -217,6 +217,10 @@ class GpuExecutor:
         self.torch = torch
         self.C = C
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        # the refinement requests' work runs on a second stream beside the
+        # FP64 requests' (the two batches share nothing within a step), so
+        # that steps with few patches still fill the device
+        self.stream2 = torch.cuda.Stream(device=self.stream.device)
         self.keep_results = keep_results
         self.max_active = int(max_active)
         self.max_edge = int(max_edge)
@@ -311,17 +315,24 @@ class GpuExecutor:
         torch, C = self.torch, self.C
         if self.dirty:
             self._assign(tickets)
-        s = self.stream
+        s, s2 = self.stream, self.stream2
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
+        fork, join = torch.cuda.Event(), torch.cuda.Event()
         e0.record(s)
+        fork.record(s)
+        s2.wait_event(fork)
+        # refinement requests (their own norm rows, scales and batch): s2
         if self.has_mixed:
-            C.cs_batch_ir_update(self.b32, self.scales.data_ptr(), s)
-            C.cs_batch_ir_residual(self.b32, self.scales.data_ptr(), self.norms.data_ptr(), s)
-        C.cs_batch_gs_sweeps(self.b64, k, s)
-        C.cs_batch_gs_sweeps(self.b32, k, s)
+            C.cs_batch_ir_update(self.b32, self.scales.data_ptr(), s2)
+            C.cs_batch_ir_residual(self.b32, self.scales.data_ptr(), self.norms.data_ptr(), s2)
+            C.cs_batch_gs_sweeps(self.b32, k, s2)
+        join.record(s2)
+        # FP64 requests: s
         if self.has_fp64:
+            C.cs_batch_gs_sweeps(self.b64, k, s)
             C.cs_batch_residual(self.b64, self.norms.data_ptr(), s)
+        s.wait_event(join)
         with torch.cuda.stream(s):
             self.host[self.buf].copy_(self.norms, non_blocking=True)
         e1.record(s)
