@@ -194,22 +194,26 @@ class Scheduler:
 
 
 class GpuExecutor:
-    """Runs admitted requests on the GPU through libcolsten, on one stream.
+    """Runs admitted requests on the GPU through libcolsten.
 
-    Two reserved batches hold the active patches: the FP64 requests (u, b and
-    a work array) and the refinement requests' FP32 correction e, its scaled
-    right-hand side r32 and work array, paired with their FP64 iterate x and
-    right-hand side b.  Each request keeps one norm row (its slot) for its
-    life, so a change of the active set only reassigns the batches: their
-    tables go to the device by asynchronous copies from pinned staging buffers,
-    with no allocation and no synchronisation.  A step enqueues, for the
-    refinement requests, the batched correction x += s e and the batched FP64
-    residual (scale and FP32 copy on the device), the sweeps of both batches,
-    the FP64 requests' batched residual and an asynchronous copy of all norms
-    to pinned host memory; it then waits for the previous step's norms, which
-    arrived while this step was queued (lag 1)."""
+    Four reserved batches hold the active patches, one per stencil and
+    precision: for FP64 requests u, b and a work array; for refinement
+    requests the FP32 correction e, its scaled right-hand side r32 and a work
+    array, paired with their FP64 iterate x and right-hand side b.  Each
+    request keeps one norm row (its slot) for its life, so a change of the
+    active set only reassigns the batches: their tables go to the device by
+    asynchronous copies from pinned staging buffers, with no allocation and no
+    synchronisation.  A step forks the four batches onto their own streams
+    (they share nothing within a step, so steps with few patches still fill
+    the device): for refinement requests the batched correction x += s e, the
+    batched FP64 residual (scale and FP32 copy on the device) and the sweeps;
+    for FP64 requests the sweeps and the batched residual.  It joins them,
+    copies all norms to pinned host memory asynchronously, and then waits for
+    the previous step's norms, which arrived while this step was queued
+    (lag 1)."""
 
     lag = 1
+    LANES = ((False, 0), (False, 1), (True, 0), (True, 1))  # (refinement, stencil)
 
     def __init__(self, stream=None, keep_results=False, max_active=256, max_edge=128):
         import torch
@@ -217,33 +221,31 @@ class GpuExecutor:
         self.torch = torch
         self.C = C
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        # the refinement requests' work runs on a second stream beside the
-        # FP64 requests' (the two batches share nothing within a step), so
-        # that steps with few patches still fill the device
-        self.stream2 = torch.cuda.Stream(device=self.stream.device)
+        # lane 0 runs on the executor's stream, the others on streams of their
+        # own (default priority)
+        self.streams = [self.stream] + [torch.cuda.Stream(device=self.stream.device)
+                                        for _ in self.LANES[1:]]
         self.keep_results = keep_results
         self.max_active = int(max_active)
         self.max_edge = int(max_edge)
         dev = torch.device("cuda", torch.cuda.current_device())
         partials = self.max_active * C.residual_items((max_edge, max_edge, max_edge))
-        self.b64 = C.cs_batch_reserve(self.max_active, partials)
-        self.b32 = C.cs_batch_reserve(self.max_active, partials)
+        self.batches = [C.cs_batch_reserve(self.max_active, partials) for _ in self.LANES]
+        self.busy = [False] * len(self.LANES)
         self.norms = torch.zeros(self.max_active, 3, dtype=torch.float64, device=dev)
         self.scales = torch.ones(self.max_active, dtype=torch.float64, device=dev)
         self.host = [torch.zeros(self.max_active, 3, dtype=torch.float64).pin_memory() for _ in range(2)]
         self.buf = 0
         self.free_rows = list(range(self.max_active - 1, -1, -1))
         self.dirty = True
-        self.has_mixed = False
-        self.has_fp64 = False
         self._pending = None
         self.point_sweeps = 0  # interior points times sweeps, over all steps
 
     def close(self):
-        for h in ("b64", "b32"):
-            if getattr(self, h, None):
-                self.C.cs_batch_destroy(getattr(self, h))
-                setattr(self, h, None)
+        for i, h in enumerate(getattr(self, "batches", [])):
+            if h:
+                self.C.cs_batch_destroy(h)
+                self.batches[i] = None
 
     def __del__(self):
         try:
@@ -292,47 +294,53 @@ class GpuExecutor:
 
     def _assign(self, tickets):
         C = self.C
-        f64 = [t for t in tickets if not t.req.mixed]
-        mix = [t for t in tickets if t.req.mixed]
-        C.cs_batch_assign(self.b64, [C.describe(t.state["u"], dim=3, stencil=t.req.stencil, h=t.state["h"])
-                                     for t in f64],
-                          [t.state["u"].data_ptr() for t in f64], [t.state["b"].data_ptr() for t in f64],
-                          [t.state["tmp"].data_ptr() for t in f64], [t.state["row"] for t in f64],
-                          self.stream)
-        C.cs_batch_assign(self.b32, [C.describe(t.state["e"], dim=3, stencil=t.req.stencil, h=t.state["h"])
-                                     for t in mix],
-                          [t.state["e"].data_ptr() for t in mix], [t.state["r32"].data_ptr() for t in mix],
-                          [t.state["tmp"].data_ptr() for t in mix], [t.state["row"] for t in mix],
-                          self.stream)
-        C.cs_batch_ir_attach(self.b32, [C.describe(t.state["u"], dim=3, stencil=t.req.stencil, h=t.state["h"])
-                                        for t in mix],
-                             [t.state["u"].data_ptr() for t in mix], [t.state["b"].data_ptr() for t in mix],
-                             self.stream)
-        self.has_fp64, self.has_mixed = bool(f64), bool(mix)
+        for li, (mixed, stencil) in enumerate(self.LANES):
+            ts = [t for t in tickets if t.req.mixed == mixed and t.req.stencil == stencil]
+            it, rt = ("e", "r32") if mixed else ("u", "b")
+            C.cs_batch_assign(self.batches[li],
+                              [C.describe(t.state[it], dim=3, stencil=stencil, h=t.state["h"]) for t in ts],
+                              [t.state[it].data_ptr() for t in ts], [t.state[rt].data_ptr() for t in ts],
+                              [t.state["tmp"].data_ptr() for t in ts], [t.state["row"] for t in ts],
+                              self.stream)
+            if mixed:
+                C.cs_batch_ir_attach(self.batches[li],
+                                     [C.describe(t.state["u"], dim=3, stencil=stencil, h=t.state["h"])
+                                      for t in ts],
+                                     [t.state["u"].data_ptr() for t in ts],
+                                     [t.state["b"].data_ptr() for t in ts], self.stream)
+            self.busy[li] = bool(ts)
         self.dirty = False
 
     def step(self, tickets, k):
         torch, C = self.torch, self.C
         if self.dirty:
             self._assign(tickets)
-        s, s2 = self.stream, self.stream2
+        s = self.stream
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        fork, join = torch.cuda.Event(), torch.cuda.Event()
         e0.record(s)
+        fork = torch.cuda.Event()
         fork.record(s)
-        s2.wait_event(fork)
-        # refinement requests (their own norm rows, scales and batch): s2
-        if self.has_mixed:
-            C.cs_batch_ir_update(self.b32, self.scales.data_ptr(), s2)
-            C.cs_batch_ir_residual(self.b32, self.scales.data_ptr(), self.norms.data_ptr(), s2)
-            C.cs_batch_gs_sweeps(self.b32, k, s2)
-        join.record(s2)
-        # FP64 requests: s
-        if self.has_fp64:
-            C.cs_batch_gs_sweeps(self.b64, k, s)
-            C.cs_batch_residual(self.b64, self.norms.data_ptr(), s)
-        s.wait_event(join)
+        joins = []
+        for li, (mixed, _) in enumerate(self.LANES):
+            if not self.busy[li]:
+                continue
+            ls, bt = self.streams[li], self.batches[li]
+            if ls is not s:
+                ls.wait_event(fork)
+            if mixed:
+                C.cs_batch_ir_update(bt, self.scales.data_ptr(), ls)
+                C.cs_batch_ir_residual(bt, self.scales.data_ptr(), self.norms.data_ptr(), ls)
+                C.cs_batch_gs_sweeps(bt, k, ls)
+            else:
+                C.cs_batch_gs_sweeps(bt, k, ls)
+                C.cs_batch_residual(bt, self.norms.data_ptr(), ls)
+            if ls is not s:
+                ev = torch.cuda.Event()
+                ev.record(ls)
+                joins.append(ev)
+        for ev in joins:
+            s.wait_event(ev)
         with torch.cuda.stream(s):
             self.host[self.buf].copy_(self.norms, non_blocking=True)
         e1.record(s)
