@@ -70,7 +70,8 @@ cs_status validate_desc(const cs_grid_desc* d)
 
 // The pointer must be device memory on the current device, aligned to the
 // element size, and the allocation must cover `bytes` from it.
-cs_status check_device_range(const void* p, size_t bytes, size_t align, const char* name)
+cs_status check_device_range(const void* p, size_t bytes, size_t align, const char* name,
+                             size_t* room_before = nullptr, size_t* room_after = nullptr)
 {
     if (!p) { set_error("%s is NULL", name); return CS_EINVAL; }
     if ((uintptr_t)p % align) { set_error("%s is not %zu-byte aligned", name, align); return CS_EINVAL; }
@@ -99,6 +100,8 @@ cs_status check_device_range(const void* p, size_t bytes, size_t align, const ch
         set_error("%s: the halo'd grid (%zu bytes) runs past its allocation", name, bytes);
         return CS_EINVAL;
     }
+    if (room_before) *room_before = a - lo;
+    if (room_after) *room_after = hi - (a + bytes);
     return CS_OK;
 }
 
@@ -118,10 +121,13 @@ double h2_of(const cs_grid_s* g)
     return g->d.dtype == CS_F32 ? (double)(float)h2 : h2;
 }
 
-cs_status check_tmp(const cs_grid_s* g, const void* tmp)
+cs_status check_tmp(const cs_grid_s* g, const void* tmp, bool* pairs = nullptr)
 {
     if (tmp == g->u || tmp == g->b) { set_error("u_tmp must be a separate array"); return CS_EINVAL; }
-    return check_device_range(tmp, (size_t)g->span * g->elem, g->elem, "u_tmp");
+    size_t before = 0, after = 0;
+    cs_status st = check_device_range(tmp, (size_t)g->span * g->elem, g->elem, "u_tmp", &before, &after);
+    if (st == CS_OK && pairs) *pairs = pair_layout(g->geo, g->d.dim, tmp, g->elem, before, after);
+    return st;
 }
 
 }  // namespace
@@ -158,7 +164,8 @@ cs_status cs_grid_create(const cs_grid_desc* desc, void* u, const void* b, cs_gr
     if (st != CS_OK) return st;
     const size_t elem = desc->dtype == CS_F64 ? 8 : 4;
     const int64_t span = span_of(*desc);
-    if ((st = check_device_range(u, (size_t)span * elem, elem, "u")) != CS_OK) return st;
+    size_t u_before = 0, u_after = 0;
+    if ((st = check_device_range(u, (size_t)span * elem, elem, "u", &u_before, &u_after)) != CS_OK) return st;
     if ((st = check_device_range(b, (size_t)span * elem, elem, "b")) != CS_OK) return st;
     if (u == b) { set_error("u and b must be separate arrays"); return CS_EINVAL; }
     cs_grid_s* g = new (std::nothrow) cs_grid_s();
@@ -175,6 +182,7 @@ cs_status cs_grid_create(const cs_grid_desc* desc, void* u, const void* b, cs_gr
     g->b = b;
     g->elem = elem;
     g->span = span;
+    g->pair_loads = pair_layout(g->geo, g->d.dim, u, elem, u_before, u_after);
     hipError_t e = hipGetDevice(&g->device);
     if (e != hipSuccess) { delete g; return hip_fail(e, "hipGetDevice"); }
     e = hipMalloc((void**)&g->partials, sizeof(Partial) * kMaxResidualBlocks);
@@ -354,8 +362,9 @@ cs_status cs_gs_sweeps(cs_grid g, int32_t nsweeps, void* u_tmp, void* stream)
     hipStream_t s = (hipStream_t)stream;
     const double h2 = h2_of(g);
     const int dt = g->d.dtype, dim = g->d.dim, sten = g->d.stencil;
+    bool tmp_pairs = false;
     if (u_tmp) {
-        if ((st = check_tmp(g, u_tmp)) != CS_OK) return st;
+        if ((st = check_tmp(g, u_tmp, &tmp_pairs)) != CS_OK) return st;
     }
     const bool automatic = g->pass_mode == CS_PASS_AUTO;
     if (automatic && block_sweeps_pay(g))
@@ -382,7 +391,8 @@ cs_status cs_gs_sweeps(cs_grid g, int32_t nsweeps, void* u_tmp, void* stream)
                 st = launch_fused_two(dt, dim, sten, g->geo, src, dst, g->b, h2, s);
                 it += 2;
             } else {
-                st = launch_fused_sweep(dt, dim, sten, g->geo, src, dst, g->b, h2, s);
+                st = launch_fused_sweep(dt, dim, sten, g->geo, src, dst, g->b, h2, s,
+                                        src == g->u ? g->pair_loads : tmp_pairs);
                 it += 1;
             }
             if (st != CS_OK) return st;

@@ -66,8 +66,17 @@ cs_status launch_residual(int dtype, int dim, int stencil, const Geo& g, const v
                           double* norms, hipStream_t s);
 // One fused Gauss-Seidel sweep src -> dst (3D grids); returns
 // CS_EUNSUPPORTED for shapes the fused kernels do not cover.
+// src_pairs: src admits two-column loads (pair_layout), used by the 27-point
+// sweep where given.
 cs_status launch_fused_sweep(int dtype, int dim, int stencil, const Geo& g, const void* src,
-                             void* dst, const void* b, double h2, hipStream_t s);
+                             void* dst, const void* b, double h2, hipStream_t s,
+                             bool src_pairs = false);
+// Whether an array of the grid's layout at p, with room_before / room_after
+// bytes of its allocation before p and after its span, admits the 27-point
+// sweep's two-column loads: odd columns aligned to two elements, even strides,
+// a padding element after every row, and one element of the allocation before
+// p and after the span (the loads of the pairs (-1, 0) and (nx+1, nx+2)).
+bool pair_layout(const Geo& g, int dim, const void* p, size_t elem, size_t room_before, size_t room_after);
 bool fused_supported(int dtype, int dim, int stencil, const Geo& g);
 // Two red-black sweeps (7-point, 3D) in one pass over memory, src -> dst: the
 // iterate of two fused sweeps bit for bit.  Available on every 7-point grid
@@ -173,4 +182,5 @@ struct cs_grid_s {
     cs::NdNode* nd_nodes; // nested-dissection tree on the device (built on first use)
     int64_t nd_leaf;      // leaf size it was built for (0: none)
     std::vector<int>* nd_stage_off;  // node offsets per height
+    bool pair_loads;      // u admits the two-column loads of the 27-point sweep (pair_layout)
 };

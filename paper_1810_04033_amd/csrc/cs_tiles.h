@@ -27,6 +27,7 @@
 
 #include "cs_device.h"
 
+#include <cstdint>
 #include <type_traits>
 #include "cs_internal.h"
 
@@ -561,14 +562,28 @@ __device__ __forceinline__ void q1_phase_pairs(bool active, const int* pc, const
     }
 }
 
-template <typename T, int TX, int TY, int NT, bool ROWWISE = false>
+// VEC: the planes are loaded two columns per load instruction.  The LDS
+// region starts at x0 - 4, an odd grid column (tiles start at x0 = 1 + TX i),
+// and is TX + 8 wide, so the column pairs (lx, lx + 1) with lx even are the
+// grid pairs (x, x + 1) with x odd: for a layout whose odd columns are
+// aligned to two elements (the library's aligned layout, x = 1 on an aligned
+// boundary, even strides) each is one aligned two-element load and one aligned
+// two-element LDS store.  A pair with a column in the halo'd row is loaded
+// whole: (-1, 0) reads the element before the row, (nx + 1, nx + 2) the row's
+// first padding element, both inside the allocation (the launch checks the
+// first row's and the last row's).  Their column outside the halo lands in
+// LDS columns that only discarded values read.
+template <typename T, int TX, int TY, int NT, bool ROWWISE = false, bool VEC = false>
 __device__ __forceinline__ void q1_3_tile_pairs(const T* __restrict__ src, T* __restrict__ dst,
                                                 const T* __restrict__ b, const Geo& g, T h2,
                                                 const TileBox& tb)
 {
     static_assert(TX % 2 == 0, "pairs need an even tile width");
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    using LV = typename std::conditional<VEC, v2, T>::type;
     constexpr int W = TX + 8, HH = TY + 8, NCOL = W * HH;
-    constexpr int M = (NCOL + NT - 1) / NT;
+    constexpr int LW = VEC ? 2 : 1;                        // columns per load
+    constexpr int M = (NCOL / LW + NT - 1) / NT;
     using PA = Q1Pairs<TX, TY, NT, 3>;
     using PB = Q1Pairs<TX, TY, NT, 2>;
     using PC = Q1Pairs<TX, TY, NT, 1>;
@@ -607,14 +622,15 @@ __device__ __forceinline__ void q1_3_tile_pairs(const T* __restrict__ src, T* __
             if ((omask >> i) & 1u) st_stream(dp + oglb[i], lp[olds[i]]);
     };
 
+    constexpr int kNoLoad = INT32_MIN;
     int coff[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int c = tid + NT * m;
-        const int ly = c / W, lx = c % W;
+        const int ly = c / (W / LW), lx = LW * (c % (W / LW));
         const int64_t x = x0 - 4 + lx, y = y0 - 4 + ly;
-        const bool ok = c < NCOL && x >= 0 && x <= g.nx + 1 && y >= 0 && y <= g.ny + 1;
-        coff[m] = ok ? (int)(y * g.sy + x) : -1;
+        const bool ok = c < NCOL / LW && y >= 0 && y <= g.ny + 1 && x >= 1 - LW && x <= g.nx + 1;
+        coff[m] = ok ? (int)(y * g.sy + x) : kNoLoad;
     }
     int ca[PA::P], oa[PA::P], fa[PA::P], cb[PB::P], ob[PB::P], fb[PB::P];
     int cc[PC::P], oc[PC::P], fc[PC::P], cd[PD::P], od[PD::P], fd[PD::P];
@@ -627,24 +643,30 @@ __device__ __forceinline__ void q1_3_tile_pairs(const T* __restrict__ src, T* __
     const int64_t e_first = is_even(z0 - 1) ? z0 - 1 : z0;
     const int64_t e_last = is_even(z1) ? z1 : z1 - 1;
 
-    auto load_plane = [&](int64_t k, T* v) {
+    auto load_plane = [&](int64_t k, LV* v) {
         const bool kin = k >= 0 && k <= g.nz + 1;
         const T* sp = src + (kin ? k : 0) * g.sz;
 #pragma unroll
-        for (int m = 0; m < M; ++m) v[m] = (kin && coff[m] >= 0) ? sp[coff[m]] : T(0);
+        for (int m = 0; m < M; ++m) {
+            const bool ld = kin && coff[m] != kNoLoad;
+            if constexpr (VEC)
+                v[m] = ld ? *reinterpret_cast<const v2*>(sp + coff[m]) : v2{T(0), T(0)};
+            else
+                v[m] = ld ? sp[coff[m]] : T(0);
+        }
     };
-    auto store_plane = [&](const T* v, T* lp) {
+    auto store_plane = [&](const LV* v, T* lp) {
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int c = tid + NT * m;
-            if (c < NCOL) lp[c] = v[m];
+            if (c < NCOL / LW) reinterpret_cast<LV*>(lp)[c] = v[m];
         }
     };
 
-    T n0[M], n1[M];
+    LV n0[M], n1[M];
     T ba[2 * PA::P], bb[2 * PB::P], bc[2 * PC::P], bd[2 * PD::P];
     {
-        T t[M];
+        LV t[M];
         load_plane(e_first - 1, t);
         store_plane(t, slot(e_first - 1));
     }

@@ -23,6 +23,8 @@
 // Workgroups are mapped XCD by XCD: consecutive tile indices (the xy tiles of
 // one z chunk) land on the same XCD so that the tiles' overlapping halo rows
 // are served from that XCD's L2.
+#include <cstdint>
+
 #include "cs_tiles.h"
 
 namespace cs {
@@ -49,14 +51,14 @@ k_fused_fd3_two(const T* __restrict__ src, T* __restrict__ dst, const T* __restr
     fd3_tile_two<T, TX, TY, NT, D, NB>(src, dst, b, g, h2, tb);
 }
 
-template <typename T, int TX, int TY, int NT, int WPE>
+template <typename T, int TX, int TY, int NT, int WPE, bool VEC>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_fused_q1_3(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict__ b, Geo g,
              T h2, FusedWork wk)
 {
     const TileBox tb = tile_box<TX, TY>(g, wk.tiles_x, wk.tiles_y, wk.chunks,
                                         xcd_ordered_block(wk.nblocks));
-    q1_3_tile_pairs<T, TX, TY, NT, true>(src, dst, b, g, h2, tb);
+    q1_3_tile_pairs<T, TX, TY, NT, true, VEC>(src, dst, b, g, h2, tb);
 }
 
 template <typename T, int TX, int TY, int NT>
@@ -167,10 +169,12 @@ cs_status fused_q1_3_two_t(const Geo& g, const void* src, void* dst, const void*
 
 template <typename T, int TX, int TY, int NT, int WPE>
 cs_status fused_q1_3_t(const Geo& g, const void* src, void* dst, const void* b, double h2,
-                       hipStream_t s)
+                       hipStream_t s, bool pairs)
 {
-    auto kern = k_fused_q1_3<T, TX, TY, NT, WPE>;
-    static const int64_t resident = resident_blocks(kern, NT);
+    // two-column loads where the layout allows them; the same plan and
+    // values either way
+    auto kern = pairs ? k_fused_q1_3<T, TX, TY, NT, WPE, true> : k_fused_q1_3<T, TX, TY, NT, WPE, false>;
+    static const int64_t resident = resident_blocks(k_fused_q1_3<T, TX, TY, NT, WPE, false>, NT);
     const FusedWork wk = plan_work(resident, g, TX, TY);
     hipLaunchKernelGGL(kern, dim3((unsigned)wk.nblocks), dim3(NT), 0, s, (const T*)src, (T*)dst,
                        (const T*)b, g, (T)h2, wk);
@@ -243,8 +247,14 @@ cs_status launch_fused_two(int dtype, int dim, int stencil, const Geo& g, const 
                      g, src, dst, b, h2, s);
 }
 
+bool pair_layout(const Geo& g, int dim, const void* p, size_t elem, size_t room_before, size_t room_after)
+{
+    return dim == 3 && ((uintptr_t)p + elem) % (2 * elem) == 0 && g.sy % 2 == 0 && g.sz % 2 == 0 &&
+           g.sy >= g.nx + 3 && room_before >= elem && room_after >= elem;
+}
+
 cs_status launch_fused_sweep(int dtype, int dim, int stencil, const Geo& g, const void* src,
-                             void* dst, const void* b, double h2, hipStream_t s)
+                             void* dst, const void* b, double h2, hipStream_t s, bool src_pairs)
 {
     if (dim != 3 || !fused_supported(dtype, dim, stencil, g)) {
         set_error("fused sweep not available for this grid");
@@ -254,8 +264,11 @@ cs_status launch_fused_sweep(int dtype, int dim, int stencil, const Geo& g, cons
         // the pair update row by row: FP64 with 512 threads (two workgroups
         // of 8 waves per CU, 107 VGPRs), FP32 with 256 (measured at 256^3 and
         // 512^3)
-        return dtype == 0 ? fused_q1_3_t<double, 64, 16, 512, 4>(g, src, dst, b, h2, s)
-                          : fused_q1_3_t<float, 64, 16, 256, 2>(g, src, dst, b, h2, s);
+        // (two-column loads in FP64, where the layout admits them: 172.7
+        // against 165.8 GLUP/s at 256^3, 190.0 against 183.7 at 512^3; in
+        // FP32 they gained nothing, 259.5 / 296.7 against 258.8 / 307.0)
+        return dtype == 0 ? fused_q1_3_t<double, 64, 16, 512, 4>(g, src, dst, b, h2, s, src_pairs)
+                          : fused_q1_3_t<float, 64, 16, 256, 2>(g, src, dst, b, h2, s, false);
     return dtype == 0 ? fused_fd3_t<double, 64, 16, 512, 1>(g, src, dst, b, h2, s)
                       : fused_fd3_t<float, 64, 16, 512, 1>(g, src, dst, b, h2, s);
 }
