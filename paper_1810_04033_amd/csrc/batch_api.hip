@@ -14,8 +14,8 @@ namespace {
 
 struct Group {
     int dtype = 0, stencil = 0, variant = 0;
-    int tier = 0;        // LDS-resident tier (1, 2), plane streaming (3), colour passes (4),
-                         // or 0 for the tile kernels
+    int tier = 0;        // LDS-resident tier (1, 2), plane streaming (3, or 5 in its small
+                         // form), colour passes (4), or 0 for the tile kernels
     bool pairs = false;  // two sweeps per launch
     std::vector<BatchPatch> host;
     BatchPatch* dev = nullptr;
@@ -151,7 +151,7 @@ cs_status plan_batch(const cs_grid_desc* descs, void* const* u, const void* cons
         int tier = (pol & 1) ? batch_resident_tier(d.dtype, d.stencil, p.g) : 0;
         if (!tier && ((pol & 4) || ((pol & 2) && planes_cand[d.stencil][d.dtype] >= planes_min)) &&
             batch_planes_fits(d.dtype, d.stencil, p.g))
-            tier = 3;
+            tier = batch_planes_small(d.dtype, d.stencil, p.g) ? 5 : 3;
         const int variant = tier ? 0 : pick_variant(d.stencil, d.dtype, d.n[0]);
         const bool pairs = !tier && batch_variant_pairs(d.stencil, variant) && g_pair_large[d.stencil][d.dtype];
         int tx = 0, ty = 0;
@@ -179,7 +179,7 @@ cs_status plan_batch(const cs_grid_desc* descs, void* const* u, const void* cons
         pl->groups[k].host.push_back(p);
         gidx.push_back(k);
         pl->by_index.push_back(p);
-        pl->per_pass.push_back(tier == 3 ? batch_planes_sweeps(d.dtype, d.stencil, p.g)
+        pl->per_pass.push_back(tier == 3 || tier == 5 ? batch_planes_sweeps(d.dtype, d.stencil, p.g)
                                : (tier ? 0 : (pairs ? 2 : 1)));
         pl->rows = std::max(pl->rows, row + 1);
     }
@@ -550,8 +550,8 @@ cs_status cs_batch_gs_sweeps(cs_batch bt, int32_t nsweeps, void* stream)
         const int n = (int)gr.host.size();
         if (gr.tier == 4)
             st = launch_batch_colour(gr.dtype, gr.stencil, gr.dev, n, gr.items, nsweeps, s);
-        else if (gr.tier == 3)
-            st = launch_batch_planes(gr.dtype, gr.stencil, gr.dev, n, nsweeps, s);
+        else if (gr.tier == 3 || gr.tier == 5)
+            st = launch_batch_planes(gr.dtype, gr.stencil, gr.dev, n, nsweeps, s, gr.tier == 5);
         else
             st = launch_batch_resident(gr.dtype, gr.stencil, gr.tier, gr.dev, n, nsweeps, s);
         if (st != CS_OK) return st;

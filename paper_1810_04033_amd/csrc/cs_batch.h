@@ -73,8 +73,11 @@ cs_status launch_batch_ir_update(const IrPatch* tab, int count, int64_t items, c
 // all nsweeps sweeps, one workgroup per patch, in place in u.
 bool batch_planes_fits(int dtype, int stencil, const Geo& g);
 int batch_planes_sweeps(int dtype, int stencil, const Geo& g);  // sweeps per pass there
+// The small form (two workgroups per compute unit) for patches it fits with
+// the same sweeps per pass.
+bool batch_planes_small(int dtype, int stencil, const Geo& g);
 cs_status launch_batch_planes(int dtype, int stencil, const BatchPatch* tab, int count, int nsweeps,
-                              hipStream_t s);
+                              hipStream_t s, bool small);
 // Colour-pass tier: work items of a patch, and nsweeps sweeps of a group, one
 // launch per colour phase, in place in u.
 int64_t batch_colour_items(int stencil, const Geo& g);

@@ -946,10 +946,49 @@ bool batch_planes_fits(int dtype, int stencil, const Geo& g)
     return s >= 2 && pairs <= (int64_t)kPlNT * (stencil == FD ? pl_pp(FD) : pl_pp(Q1)) && g.nz >= 1;
 }
 
+// The small form: 512 threads, one column pair each, half the LDS, so two
+// workgroups share a compute unit (for cross-sections of at most 1024 points,
+// e.g. 32 x 32, whose pairs would leave half of a 1024-thread workgroup idle).
+constexpr int kPlNTs = 512;
+constexpr int kPlCap64s = 10000, kPlCap32s = 20000;  // elements: 80 KB
+constexpr int pl_mpl_s(int cap, int npl) { return (cap / (2 * 2 + 1 + npl) + kPlNTs - 1) / kPlNTs; }
+
+bool batch_planes_small(int dtype, int stencil, const Geo& g)
+{
+    const int npl = stencil == FD ? 1 : 2;
+    const int64_t pl = (g.nx + 2) * (g.ny + 2);
+    const int64_t cap = dtype == 0 ? kPlCap64s : kPlCap32s;
+    int64_t s = (cap / pl - 1 - npl) / 2;
+    const int smax = stencil == FD ? pl_smax(FD) : pl_smax(Q1);
+    if (s > smax) s = smax;
+    const int64_t pairs = stencil == FD ? (g.nx * g.ny + 1) / 2 : g.nx * ((g.ny + 1) / 2);
+    // the same sweeps per pass as the large form
+    return pairs <= kPlNTs && s == batch_planes_sweeps(dtype, stencil, g);
+}
+
 cs_status launch_batch_planes(int dtype, int stencil, const BatchPatch* tab, int count, int nsweeps,
-                              hipStream_t s)
+                              hipStream_t s, bool small)
 {
     if (count <= 0 || nsweeps <= 0) return CS_OK;
+    if (small) {
+        const dim3 grid((unsigned)count), blk(kPlNTs);
+        if (dtype == 0) {
+            if (stencil == FD)
+                hipLaunchKernelGGL((k_batch_planes<double, FD, kPlNTs, kPlCap64s, pl_smax(FD), 1, pl_mpl_s(kPlCap64s, 1)>),
+                                   grid, blk, 0, s, tab, nsweeps);
+            else
+                hipLaunchKernelGGL((k_batch_planes<double, Q1, kPlNTs, kPlCap64s, pl_smax(Q1), 1, pl_mpl_s(kPlCap64s, 2)>),
+                                   grid, blk, 0, s, tab, nsweeps);
+        } else {
+            if (stencil == FD)
+                hipLaunchKernelGGL((k_batch_planes<float, FD, kPlNTs, kPlCap32s, pl_smax(FD), 1, pl_mpl_s(kPlCap32s, 1)>),
+                                   grid, blk, 0, s, tab, nsweeps);
+            else
+                hipLaunchKernelGGL((k_batch_planes<float, Q1, kPlNTs, kPlCap32s, pl_smax(Q1), 1, pl_mpl_s(kPlCap32s, 2)>),
+                                   grid, blk, 0, s, tab, nsweeps);
+        }
+        return check_launch("batched plane-streaming sweeps");
+    }
     const dim3 grid((unsigned)count), blk(kPlNT);
     if (dtype == 0) {
         if (stencil == FD)
