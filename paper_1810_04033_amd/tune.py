@@ -107,10 +107,25 @@ def _log(msg):
     print("tune: " + msg, file=sys.stderr, flush=True)
 
 
+def _restore_batch_defaults(stencil, dt):
+    C.cs_batch_tile_policy(stencil, dt, 0, 0)
+    C.cs_batch_pass_policy(stencil, dt, 1)
+    C.cs_batch_colour_policy(stencil, dt, -1)
+    C.cs_batch_resident_policy(stencil, dt, 3)
+
+
 def tune(stencil, dtype=torch.float64, edges=(8, 16, 24, 32, 48, 64), points_target=1 << 24,
          sweeps=10, save=True):
     """Time the candidate policies; returns the record and applies the
-    fastest."""
+    fastest (the defaults stay in force if a timing fails)."""
+    try:
+        return _tune(stencil, dtype, edges, points_target, sweeps, save)
+    except BaseException:
+        _restore_batch_defaults(stencil, C._DT[dtype])
+        raise
+
+
+def _tune(stencil, dtype, edges, points_target, sweeps, save):
     dt = C._DT[dtype]
     mix = shape_mix(points_target)
     C.cs_batch_resident_policy(stencil, dt, 3)
