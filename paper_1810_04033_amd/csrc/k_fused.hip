@@ -196,25 +196,11 @@ bool fused_supported(int dtype, int dim, int stencil, const Geo& g)
 // Tile, threads, prefetch depth and snapshot sets of the double sweep per
 // precision (measured at 256^3): FP64 64 x 16 with two snapshot sets, FP32
 // 64 x 32 with one.
-#ifndef CS_F2_TX
-#define CS_F2_TX 64
-#define CS_F2_TY 16
-#define CS_F2_NT 1024
-#define CS_F2_D 2
-#define CS_F2_NB 2
-#define CS_F2_TX32 64
-#define CS_F2_TY32 32
-#define CS_F2_NT32 1024
-#define CS_F2_D32 2
-#define CS_F2_NB32 1
-#endif
+constexpr int kF2TX = 64, kF2TY = 16, kF2NT = 1024, kF2D = 2, kF2NB = 2;
+constexpr int kF2TX32 = 64, kF2TY32 = 32, kF2NT32 = 1024, kF2D32 = 2, kF2NB32 = 1;
 // Tile and threads of the 27-point double sweep (one workgroup per CU: seven
 // LDS planes of the region T+8).
-#ifndef CS_Q2_TX
-#define CS_Q2_TX 64
-#define CS_Q2_TY 16
-#define CS_Q2_NT 1024
-#endif
+constexpr int kQ2TX = 64, kQ2TY = 16, kQ2NT = 1024;
 
 bool fused_two_available(int dtype, int dim, int stencil, const Geo& g)
 {
@@ -226,8 +212,8 @@ bool fused_two_preferred(int dtype, int dim, int stencil, const Geo& g)
     if (!fused_two_available(dtype, dim, stencil, g)) return false;
     if (stencil == Q1) return false;
     return dtype == 0
-               ? fused_two_fills<double, CS_F2_TX, CS_F2_TY, CS_F2_NT, CS_F2_D, CS_F2_NB>(g)
-               : fused_two_fills<float, CS_F2_TX32, CS_F2_TY32, CS_F2_NT32, CS_F2_D32, CS_F2_NB32>(g);
+               ? fused_two_fills<double, kF2TX, kF2TY, kF2NT, kF2D, kF2NB>(g)
+               : fused_two_fills<float, kF2TX32, kF2TY32, kF2NT32, kF2D32, kF2NB32>(g);
 }
 
 cs_status launch_fused_two(int dtype, int dim, int stencil, const Geo& g, const void* src,
@@ -238,12 +224,12 @@ cs_status launch_fused_two(int dtype, int dim, int stencil, const Geo& g, const 
         return CS_EUNSUPPORTED;
     }
     if (stencil == Q1)
-        return dtype == 0 ? fused_q1_3_two_t<double, CS_Q2_TX, CS_Q2_TY, CS_Q2_NT>(g, src, dst, b, h2, s)
-                          : fused_q1_3_two_t<float, CS_Q2_TX, CS_Q2_TY, CS_Q2_NT>(g, src, dst, b, h2, s);
+        return dtype == 0 ? fused_q1_3_two_t<double, kQ2TX, kQ2TY, kQ2NT>(g, src, dst, b, h2, s)
+                          : fused_q1_3_two_t<float, kQ2TX, kQ2TY, kQ2NT>(g, src, dst, b, h2, s);
     return dtype == 0
-               ? fused_fd3_two_t<double, CS_F2_TX, CS_F2_TY, CS_F2_NT, CS_F2_D, CS_F2_NB>(
+               ? fused_fd3_two_t<double, kF2TX, kF2TY, kF2NT, kF2D, kF2NB>(
                      g, src, dst, b, h2, s)
-               : fused_fd3_two_t<float, CS_F2_TX32, CS_F2_TY32, CS_F2_NT32, CS_F2_D32, CS_F2_NB32>(
+               : fused_fd3_two_t<float, kF2TX32, kF2TY32, kF2NT32, kF2D32, kF2NB32>(
                      g, src, dst, b, h2, s);
 }
 

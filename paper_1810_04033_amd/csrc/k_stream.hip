@@ -784,26 +784,15 @@ cs_status jacobi3_t(const Geo& g, const void* src, void* dst, const void* b, dou
 
 // Two sweeps per launch (the caller pairs the sweeps).  Tile 64 x 16; FP64
 // runs best with 512 threads, FP32 with 256 (measured at 256^3).
-#ifndef CS_J2_TX
-#define CS_J2_TX 64
-#define CS_J2_TY 16
-#define CS_J2_NT64 512
-#define CS_J2_NT32 256
-#define CS_J2_FILL 1
-#endif
-#ifndef CS_J2Q_TX
-#define CS_J2Q_TX 64
-#define CS_J2Q_TY 16
-#define CS_J2Q_NT64 512
-#define CS_J2Q_NT32 256
-#endif
+constexpr int kJ2TX = 64, kJ2TY = 16, kJ2NT64 = 512, kJ2NT32 = 256, kJ2Fill = 1;
+constexpr int kJ2QTX = 64, kJ2QTY = 16, kJ2QNT64 = 512, kJ2QNT32 = 256;
 template <typename S, int ST>
 cs_status jacobi3_two_t(const Geo& g, const void* src, void* dst, const void* b, double h2,
                         double omega, hipStream_t s)
 {
     constexpr bool f64 = sizeof(S) == 8;
     if (ST == Q1) {
-        constexpr int TX = CS_J2Q_TX, TY = CS_J2Q_TY, NT = f64 ? CS_J2Q_NT64 : CS_J2Q_NT32;
+        constexpr int TX = kJ2QTX, TY = kJ2QTY, NT = f64 ? kJ2QNT64 : kJ2QNT32;
         auto kern = k_jacobi3_q1_two<S, TX, TY, NT>;
         static const int64_t resident = resident_of(kern, NT);
         const StreamWork wk = chunk_tiles(g, TX, TY, resident);
@@ -811,10 +800,10 @@ cs_status jacobi3_two_t(const Geo& g, const void* src, void* dst, const void* b,
                            (S*)dst, (const S*)b, g, h2, omega, wk);
         return check_launch("streaming jacobi (two sweeps, 27-point)");
     }
-    constexpr int TX = CS_J2_TX, TY = CS_J2_TY, NT = f64 ? CS_J2_NT64 : CS_J2_NT32;
+    constexpr int TX = kJ2TX, TY = kJ2TY, NT = f64 ? kJ2NT64 : kJ2NT32;
     auto kern = k_jacobi3_fd_two<S, TX, TY, NT>;
     static const int64_t resident = resident_of(kern, NT);
-    const StreamWork wk = chunk_tiles(g, TX, TY, resident * CS_J2_FILL);
+    const StreamWork wk = chunk_tiles(g, TX, TY, resident * kJ2Fill);
     hipLaunchKernelGGL(kern, dim3((unsigned)wk.nblocks), dim3(NT), 0, s, (const S*)src, (S*)dst,
                        (const S*)b, g, h2, omega, wk);
     return check_launch("streaming jacobi (two sweeps, 7-point)");
